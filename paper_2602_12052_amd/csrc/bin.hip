@@ -1,0 +1,190 @@
+// Block-sparse binned tensor (Sec. III-B): active bins, their keys and the dense
+// charge of each active bin, reduced over overlapping deposition patches.
+#include "tred_internal.hpp"
+#include "validate.hpp"
+
+namespace {
+
+struct BinGeom {
+    int32_t bf[3];   // bin extent in fine cells
+    int32_t nb[3];   // bins per axis
+    int64_t vblk;    // cells per bin
+};
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// every bin touched by a footprint box gets flag 1
+__global__ __launch_bounds__(256) void k_mark(BinGeom G, int64_t n, const int32_t* __restrict__ fp,
+                                              int32_t* __restrict__ flag) {
+    int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    const int32_t* f = fp + 6 * d;
+    if (f[3] < f[0] || f[4] < f[1] || f[5] < f[2]) return;
+    for (int bx = f[0] / G.bf[0]; bx <= f[3] / G.bf[0]; ++bx)
+        for (int by = f[1] / G.bf[1]; by <= f[4] / G.bf[1]; ++by)
+            for (int bt = f[2] / G.bf[2]; bt <= f[5] / G.bf[2]; ++bt)
+                flag[((int64_t)bx * G.nb[1] + by) * G.nb[2] + bt] = 1;
+}
+
+__device__ __forceinline__ int wave_incl_scan_i32(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Stream compaction of the flags in bin order (one workgroup): flag -> slot or -1,
+// keys of active bins in ascending order, count of active bins.
+__global__ __launch_bounds__(1024) void k_compact(BinGeom G, int32_t* __restrict__ flag,
+                                                  int32_t* __restrict__ keys,
+                                                  int32_t* __restrict__ n_active, int32_t cap) {
+    __shared__ int wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tot = (int64_t)G.nb[0] * G.nb[1] * G.nb[2];
+    int carry = 0;
+    for (int64_t base = 0; base < tot; base += 1024) {
+        const int64_t i = base + tid;
+        const int f = (i < tot && flag[i] != 0) ? 1 : 0;
+        const int incl = wave_incl_scan_i32(f, lane);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        if (wave == 0) {
+            int t = lane < 16 ? wsum[lane] : 0;
+            t = wave_incl_scan_i32(t, lane);
+            if (lane < 16) wsum[lane] = t;
+        }
+        __syncthreads();
+        const int slot = carry + incl - f + (wave > 0 ? wsum[wave - 1] : 0);
+        if (i < tot) {
+            if (f && slot < cap) {
+                keys[3 * slot + 0] = (int32_t)(i / ((int64_t)G.nb[1] * G.nb[2]));
+                keys[3 * slot + 1] = (int32_t)((i / G.nb[2]) % G.nb[1]);
+                keys[3 * slot + 2] = (int32_t)(i % G.nb[2]);
+            }
+            flag[i] = (f && slot < cap) ? slot : -1;
+        }
+        carry += wsum[15];
+        __syncthreads();
+    }
+    if (tid == 0) *n_active = carry;
+}
+
+// zero the first min(n_active, cap) bins
+__global__ __launch_bounds__(256) void k_zero_blocks(float4* __restrict__ blocks,
+                                                     const int32_t* __restrict__ n_active,
+                                                     int32_t cap, int64_t vblk) {
+    const int64_t na = min(*n_active, cap);
+    const int64_t n4 = na * vblk / 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * blockDim.x)
+        blocks[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_zero_tail(float* __restrict__ blocks,
+                                                   const int32_t* __restrict__ n_active,
+                                                   int32_t cap, int64_t vblk) {
+    const int64_t na = min(*n_active, cap);
+    const int64_t n = na * vblk;
+    const int64_t i = (n / 4) * 4 + threadIdx.x;
+    if (i < n) blocks[i] = 0.f;
+}
+
+// one workgroup per deposition: add its patch into the bins (FP32 atomics; the
+// reduction order over overlapping patches is unspecified)
+__global__ __launch_bounds__(256) void k_accum(BinGeom G, int64_t n, const int32_t* __restrict__ fp,
+                                               const int64_t* __restrict__ off,
+                                               const float* __restrict__ val, int64_t val_cap,
+                                               const int32_t* __restrict__ slot,
+                                               float* __restrict__ blocks) {
+    for (int64_t d = blockIdx.x; d < n; d += gridDim.x) {
+        const int32_t* f = fp + 6 * d;
+        if (f[3] < f[0] || f[4] < f[1] || f[5] < f[2]) continue;
+        const int ny = f[4] - f[1] + 1, nt = f[5] - f[2] + 1;
+        if (off[d + 1] > val_cap) continue;
+        const int64_t cnt = off[d + 1] - off[d];
+        const float* v = val + off[d];
+        for (int64_t k = threadIdx.x; k < cnt; k += blockDim.x) {
+            const float q = v[k];
+            if (q == 0.0f) continue;
+            const int it = (int)(k % nt);
+            const int64_t r = k / nt;
+            const int iy = (int)(r % ny), ix = (int)(r / ny);
+            const int gx = f[0] + ix, gy = f[1] + iy, gt = f[2] + it;
+            const int bx = gx / G.bf[0], by = gy / G.bf[1], bt = gt / G.bf[2];
+            const int s = slot[((int64_t)bx * G.nb[1] + by) * G.nb[2] + bt];
+            if (s < 0) continue;
+            float* dst = blocks + (int64_t)s * G.vblk +
+                         ((int64_t)(gx - bx * G.bf[0]) * G.bf[1] + (gy - by * G.bf[1])) * G.bf[2] +
+                         (gt - bt * G.bf[2]);
+            unsafeAtomicAdd(dst, q);
+        }
+    }
+}
+
+BinGeom geom(const tred_grid* g, const tred_blocking* b) {
+    BinGeom G;
+    G.bf[0] = b->blk_pix[0] * g->sub[0];
+    G.bf[1] = b->blk_pix[1] * g->sub[1];
+    G.bf[2] = b->blk_ticks;
+    for (int a = 0; a < 3; ++a) G.nb[a] = nblk_axis(g, b, a);
+    G.vblk = (int64_t)G.bf[0] * G.bf[1] * G.bf[2];
+    return G;
+}
+
+}  // namespace
+
+extern "C" int32_t tred_block_count(const tred_grid* grid, const tred_blocking* blocking) {
+    if (validate_grid(grid) != TRED_OK || validate_blocking(blocking) != TRED_OK) return -1;
+    int64_t n = (int64_t)nblk_axis(grid, blocking, 0) * nblk_axis(grid, blocking, 1) *
+                nblk_axis(grid, blocking, 2);
+    return n > INT32_MAX ? -1 : (int32_t)n;
+}
+
+extern "C" int64_t tred_block_bin_workspace(const tred_grid* grid, const tred_blocking* blocking) {
+    int32_t n = tred_block_count(grid, blocking);
+    return n < 0 ? -1 : (int64_t)n * 4;
+}
+
+extern "C" tred_status tred_block_bin(const tred_grid* grid, const tred_blocking* blocking,
+                                      int64_t n_dep, const int32_t* fp, const int64_t* off,
+                                      const float* val, int64_t val_cap, int32_t* keys,
+                                      int32_t* n_active,
+                                      float* blocks, int32_t cap, void* work, void* stream) {
+    TRED_TRY(validate_grid(grid));
+    TRED_TRY(validate_blocking(blocking));
+    TRED_REQUIRE(n_dep >= 0, "n_dep must be >= 0");
+    TRED_REQUIRE(cap >= 0, "cap must be >= 0");
+    TRED_REQUIRE(n_active && work, "n_active/work is NULL");
+    TRED_REQUIRE(cap == 0 || (keys && blocks), "keys/blocks is NULL");
+    TRED_REQUIRE(n_dep == 0 || (fp && off && val), "fp/off/val is NULL");
+    TRED_REQUIRE(tred_block_count(grid, blocking) > 0, "too many bins");
+    TRED_REQUIRE(((uintptr_t)blocks & 15) == 0, "blocks must be 16-byte aligned");
+    const BinGeom G = geom(grid, blocking);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t* flag = (int32_t*)work;
+    const int64_t tot = (int64_t)G.nb[0] * G.nb[1] * G.nb[2];
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 4096)),
+                       dim3(256), 0, st, flag, tot, 0);
+    if (n_dep > 0)
+        hipLaunchKernelGGL(k_mark, dim3((unsigned)((n_dep + 255) / 256)), dim3(256), 0, st, G,
+                           n_dep, fp, flag);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, G, flag, keys, n_active, cap);
+    TRED_TRY(tred_check_launch("tred_block_bin compact"));
+    if (cap > 0) {
+        hipLaunchKernelGGL(k_zero_blocks, dim3(2048), dim3(256), 0, st, (float4*)blocks, n_active,
+                           cap, G.vblk);
+        hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(4), 0, st, blocks, n_active, cap, G.vblk);
+        if (n_dep > 0) {
+            unsigned nb = (unsigned)std::min<int64_t>(n_dep, 1 << 20);
+            hipLaunchKernelGGL(k_accum, dim3(nb), dim3(256), 0, st, G, n_dep, fp, off, val, val_cap,
+                               flag, blocks);
+        }
+    }
+    return tred_check_launch("tred_block_bin");
+}

@@ -1,0 +1,729 @@
+// Interlaced convolution of the charge blocks with the field response by FFT
+// (Sec. II-D eq. interlaced; Sec. III-A: per-channel transforms, channel sum in the
+// frequency domain, one inverse per block; mirror-pair complex packing, eq. multch).
+//
+// Per block and impact channel j the transform is separable:
+//   k_tf : time FFT (length ft) of every (channel, pixel) row   -> T[b][j][p/8][f][p%8]
+//   k_sp : per time frequency f, 2-D spatial FFT of each channel (block pixels zero
+//          padded to fs x fs), multiply-accumulate with the precomputed response
+//          spectra of every response piece, inverse spatial FFT   -> U[b][c][q/8][f][q%8]
+//   k_ti : inverse time FFT per output pixel and piece, overlap-add of the pieces
+//          into the block's output rows.
+// When ft < blk_ticks + kticks - 1 the response is cut into pieces of ct = ft -
+// blk_ticks ticks; piece c's linear convolution (length <= ft - 1, no wrap) lands at
+// tick offset c * ct.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "tred_internal.hpp"
+#include "validate.hpp"
+
+namespace {
+
+struct ConvArgs {
+    int32_t Bx, By, Bt, sx, sy, NYf, S;
+    int32_t nch, nc, ct, ft, fs;
+    int32_t ppad, qpad, box, boy, bot;
+    int32_t mpcp, chx, cap;
+    int32_t ldsA, ldsB;       // k_sp LDS region sizes (float2)
+    int64_t vblk, vout;
+};
+
+// ---------------------------------------------------------------------------
+// plan set-up kernels (binary64 arithmetic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 tw64(int64_t k, int64_t n) {
+    // exp(-2 pi i k / n) with exact argument reduction
+    double s, c;
+    sincospi(-2.0 * (double)(k % n) / (double)n, &s, &c);
+    return make_double2(c, s);
+}
+
+__global__ void k_twiddles(float2* __restrict__ twt, int ft, float2* __restrict__ tws, int fs,
+                           double2* __restrict__ twdt, double2* __restrict__ twds) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ft) {
+        double2 w = tw64(i, ft);
+        twt[i] = make_float2((float)w.x, (float)w.y);
+        twdt[i] = w;
+    }
+    if (i < fs) {
+        double2 w = tw64(i, fs);
+        tws[i] = make_float2((float)w.x, (float)w.y);
+        twds[i] = w;
+    }
+}
+
+// number of entries violating R[K-1-k][sub-1-j][tau] == R[k][j][tau]
+__global__ void k_symcheck(const float* __restrict__ R, int Kx, int Ky, int sx, int sy, int kt,
+                           int* __restrict__ bad) {
+    int64_t n = (int64_t)Kx * Ky * sx * sy * kt;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i;
+        int t = (int)(r % kt); r /= kt;
+        int jy = (int)(r % sy); r /= sy;
+        int jx = (int)(r % sx); r /= sx;
+        int ky = (int)(r % Ky); r /= Ky;
+        int kx = (int)r;
+        int64_t m = ((((int64_t)(Kx - 1 - kx) * Ky + (Ky - 1 - ky)) * sx + (sx - 1 - jx)) * sy +
+                     (sy - 1 - jy)) * kt + t;
+        if (R[i] != R[m]) atomicAdd(bad, 1);
+    }
+}
+
+// PA[ch][c][kx][ky][f] = sum_{tau < ct} R[kx][ky][j][c ct + tau] exp(-2 pi i tau f / ft)
+__global__ void k_rhat_time(const float* __restrict__ R, ConvArgs A, int Kx, int Ky, int kt,
+                            const double2* __restrict__ twd, double2* __restrict__ PA) {
+    const int64_t n = (int64_t)A.nch * A.nc * Kx * Ky * A.ft;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i;
+        const int f = (int)(r % A.ft); r /= A.ft;
+        const int ky = (int)(r % Ky); r /= Ky;
+        const int kx = (int)(r % Kx); r /= Kx;
+        const int c = (int)(r % A.nc); r /= A.nc;
+        const int ch = (int)r;
+        const int jx = ch / A.sy, jy = ch % A.sy;
+        const float* row = R + ((((int64_t)kx * Ky + ky) * A.sx + jx) * A.sy + jy) * kt;
+        const int t0 = c * A.ct;
+        const int len = min(A.ct, kt - t0);
+        double re = 0.0, im = 0.0;
+        for (int tau = 0; tau < len; ++tau) {
+            const double v = (double)row[t0 + tau];
+            const double2 w = twd[((int64_t)tau * f) & (A.ft - 1)];
+            re += v * w.x;
+            im += v * w.y;
+        }
+        PA[i] = make_double2(re, im);
+    }
+}
+
+// PB[ch][c][kxf][ky][f] = sum_kx PA[ch][c][kx][ky][f] exp(-2 pi i kx kxf / fs)
+__global__ void k_rhat_x(ConvArgs A, int Kx, int Ky, const double2* __restrict__ twd,
+                         const double2* __restrict__ PA, double2* __restrict__ PB) {
+    const int64_t n = (int64_t)A.nch * A.nc * A.fs * Ky * A.ft;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i;
+        const int f = (int)(r % A.ft); r /= A.ft;
+        const int ky = (int)(r % Ky); r /= Ky;
+        const int kxf = (int)(r % A.fs); r /= A.fs;
+        const int64_t cc = r;  // ch * nc + c
+        double re = 0.0, im = 0.0;
+        for (int kx = 0; kx < Kx; ++kx) {
+            const double2 a = PA[((cc * Kx + kx) * Ky + ky) * A.ft + f];
+            const double2 w = twd[(kx * kxf) % A.fs];
+            re += a.x * w.x - a.y * w.y;
+            im += a.x * w.y + a.y * w.x;
+        }
+        PB[i] = make_double2(re, im);
+    }
+}
+
+// R̂[ch][c][m][f][item] = scale * sum_ky PB[ch][c][kxf][ky][f] exp(-2 pi i ky kyf / fs),
+// item = kxf * RS + ry, kyf = ry + RS * m (the order in which k_sp holds spectra).
+__global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2* __restrict__ twd,
+                         const double2* __restrict__ PB, float2* __restrict__ rhat) {
+    const int RS = A.fs / L;
+    const int TPF = A.fs * RS;
+    const int64_t n = (int64_t)A.nch * A.nc * L * A.ft * TPF;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i;
+        const int item = (int)(r % TPF); r /= TPF;
+        const int f = (int)(r % A.ft); r /= A.ft;
+        const int m = (int)(r % L); r /= L;
+        const int64_t cc = r;
+        const int kxf = item / RS, ry = item % RS;
+        const int kyf = ry + RS * m;
+        double re = 0.0, im = 0.0;
+        for (int ky = 0; ky < Ky; ++ky) {
+            const double2 a = PB[((cc * A.fs + kxf) * Ky + ky) * A.ft + f];
+            const double2 w = twd[(ky * kyf) % A.fs];
+            re += a.x * w.x - a.y * w.y;
+            im += a.x * w.y + a.y * w.x;
+        }
+        rhat[i] = make_float2((float)(re * scale), (float)(im * scale));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_tf: time FFT of the (channel, pixel) rows of a block; one wavefront per row,
+// 8 rows (one tile of the spectral scratch) per workgroup.
+// Under mirror-pair packing the row is Q_j[p] + i Q_{j'}[B-1-p] with j' = sub-1-j.
+// ---------------------------------------------------------------------------
+template <int FT>
+__global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* __restrict__ n_active,
+                                            const float* __restrict__ blocks,
+                                            const float2* __restrict__ tw, float2* __restrict__ T) {
+    extern __shared__ float lds[];
+    constexpr int M = FT / kWave;
+    const int bl = blockIdx.z, b = b0 + bl;
+    if (b >= min(*n_active, A.cap)) return;
+    const int ch = blockIdx.y;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = blockIdx.x * kTile + wv;
+    const int jx = ch / A.sy, jy = ch % A.sy;
+    const int jb = A.S - 1 - ch;
+    const bool pair = A.mpcp && jb != ch;
+    const int mb = A.Bt / kWave;
+    float2 v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = make_float2(0.f, 0.f);
+    if (p < A.Bx * A.By) {
+        const float* blk = blocks + (int64_t)b * A.vblk;
+        const int px = p / A.By, py = p % A.By;
+        const float* r0 = blk + ((int64_t)(px * A.sx + jx) * A.NYf + (py * A.sy + jy)) * A.Bt;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (m < mb) v[m].x = r0[lane + kWave * m];
+        if (pair) {
+            const int jbx = jb / A.sy, jby = jb % A.sy;
+            const float* r1 = blk + ((int64_t)((A.Bx - 1 - px) * A.sx + jbx) * A.NYf +
+                                     ((A.By - 1 - py) * A.sy + jby)) * A.Bt;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                if (m < mb) v[m].y = r1[lane + kWave * m];
+        }
+    }
+    wave_fft<FT>(v, lds + wv * kFftLds<FT>, tw, lane);
+    float2* stage = (float2*)lds;
+#pragma unroll
+    for (int m = 0; m < M; ++m) stage[(lane + kWave * m) * kTile + wv] = v[m];
+    __syncthreads();
+    const int64_t base = (((int64_t)bl * A.nch + ch) * (A.ppad / kTile) + blockIdx.x) * FT * kTile;
+    float4* d4 = (float4*)(T + base);
+    const float4* s4 = (const float4*)stage;
+    for (int i = threadIdx.x; i < FT * kTile / 2; i += blockDim.x) d4[i] = s4[i];
+}
+
+// ---------------------------------------------------------------------------
+// k_sp: spatial transforms and the spectral multiply-accumulate, per time frequency.
+// The fs-point transform along an axis with at most L = min(fs, 16) nonzero inputs
+// is split as k = r + RS m (RS = fs / L): for each r an L-point DFT of the inputs
+// twiddled by exp(-2 pi i n r / fs). Its inverse with pruned outputs runs the same
+// split backwards (L-point inverse DFTs, then an RS-point combination).
+// One workgroup of 256 threads handles NF = 256 / (fs RS) consecutive frequencies;
+// thread (fl, kx, ry) owns the spectrum column kx, ky = ry + RS m of frequency f0+fl.
+// ---------------------------------------------------------------------------
+template <int FS, int L>
+__global__ __launch_bounds__(256) void k_sp(ConvArgs A, int b0, const int32_t* __restrict__ n_active,
+                                            const float2* __restrict__ T,
+                                            const float2* __restrict__ rhat,
+                                            const float2* __restrict__ tws,
+                                            float2* __restrict__ U) {
+    constexpr int RS = FS / L, TPF = FS * RS, NF = 256 / TPF;
+    extern __shared__ float2 sm[];
+    const int bl = blockIdx.y, b = b0 + bl;
+    if (b >= min(*n_active, A.cap)) return;
+    const int f0 = blockIdx.x * NF;
+    const int tid = threadIdx.x, fl = tid / TPF, item = tid % TPF;
+    const int kx = item / RS, ry = item % RS;
+    const int By = A.By, Bx = A.Bx, CHX = A.chx, ppad = A.ppad, box = A.box, boy = A.boy;
+    const int ptiles = ppad / kTile;
+    float2* twl = sm;                 // exp(-2 pi i k / fs)
+    float2* regA = sm + FS;
+    float2* regB = regA + A.ldsA;
+    float2* zbuf = regA;                              // [CHX][NF][ppad]
+    float2* abuf = regA + CHX * NF * ppad;            // [CHX][NF][FS][By]
+    if (tid < FS) twl[tid] = tws[tid];
+
+    float2 acc[4][L];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int m = 0; m < L; ++m) acc[c][m] = make_float2(0.f, 0.f);
+    __syncthreads();
+
+    for (int j0 = 0; j0 < A.nch; j0 += CHX) {
+        // stage the time spectra of CHX channels at frequencies f0 .. f0+NF-1
+        const int nld = CHX * ptiles * NF * kTile;
+        for (int i = tid; i < nld; i += 256) {
+            const int pi = i % kTile;
+            int r = i / kTile;
+            const int fl2 = r % NF;
+            r /= NF;
+            const int pt = r % ptiles;
+            const int cx = r / ptiles;
+            const int ch = j0 + cx;
+            float2 z = make_float2(0.f, 0.f);
+            if (ch < A.nch)
+                z = T[((((int64_t)bl * A.nch + ch) * ptiles + pt) * A.ft + f0 + fl2) * kTile + pi];
+            zbuf[(cx * NF + fl2) * ppad + pt * kTile + pi] = z;
+        }
+        __syncthreads();
+        // x pass: for each (channel, frequency, py, rx): L-point DFT over px
+        const int nx = CHX * NF * By * RS;
+        for (int i = tid; i < nx; i += 256) {
+            const int rx = i % RS;
+            int r = i / RS;
+            const int py = r % By;
+            r /= By;
+            const int fl2 = r % NF;
+            const int cx = r / NF;
+            const float2* zr = zbuf + (cx * NF + fl2) * ppad;
+            float2 s[L];
+#pragma unroll
+            for (int n = 0; n < L; ++n)
+                s[n] = n < Bx ? cmul(zr[n * By + py], twl[(n * rx) % FS]) : make_float2(0.f, 0.f);
+            Dft<L>::run(s);
+            float2* ar = abuf + ((cx * NF + fl2) * FS) * By + py;
+#pragma unroll
+            for (int m = 0; m < L; ++m) ar[(rx + RS * m) * By] = s[m];
+        }
+        __syncthreads();
+        // y pass and multiply-accumulate, one channel at a time
+        for (int cx = 0; cx < CHX; ++cx) {
+            const int ch = j0 + cx;
+            if (ch >= A.nch) break;
+            const float2* ar = abuf + ((cx * NF + fl) * FS + kx) * By;
+            float2 s[L];
+#pragma unroll
+            for (int n = 0; n < L; ++n)
+                s[n] = n < By ? cmul(ar[n], twl[(n * ry) % FS]) : make_float2(0.f, 0.f);
+            Dft<L>::run(s);
+            const float2* rh = rhat + ((int64_t)ch * A.nc * L * A.ft + f0) * TPF + tid;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c < A.nc) {
+#pragma unroll
+                    for (int m = 0; m < L; ++m) {
+                        const float2 w = rh[((int64_t)(c * L + m) * A.ft) * TPF];
+                        acc[c][m].x += s[m].x * w.x - s[m].y * w.y;
+                        acc[c][m].y += s[m].x * w.y + s[m].y * w.x;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // inverse spatial transform of every response piece and the mirror-pair unpacking
+    const int qtiles = A.qpad / kTile;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c >= A.nc) break;
+        float2* gbuf = regA;    // [NF][FS][RS][L]
+        float2* ybuf = regB;    // [NF][FS][boy]
+        {
+            float2 s[L];
+#pragma unroll
+            for (int m = 0; m < L; ++m) s[m] = cconj(acc[c][m]);
+            Dft<L>::run(s);
+            float2* gr = gbuf + ((fl * FS + kx) * RS + ry) * L;
+#pragma unroll
+            for (int n0 = 0; n0 < L; ++n0) gr[n0] = cmulc(cconj(s[n0]), twl[(n0 * ry) % FS]);
+        }
+        __syncthreads();
+        // combine over ry -> y-inverse at qy = n0 + L n1 < boy
+        for (int i = tid; i < NF * FS * L; i += 256) {
+            const int n0 = i % L;
+            int r = i / L;
+            const int kx2 = r % FS;
+            const int fl2 = r / FS;
+            float2 col[RS];
+#pragma unroll
+            for (int rr = 0; rr < RS; ++rr) col[rr] = gbuf[((fl2 * FS + kx2) * RS + rr) * L + n0];
+#pragma unroll
+            for (int n1 = 0; n1 < RS; ++n1) {
+                const int qy = n0 + L * n1;
+                if (qy < boy) {
+                    float2 y = col[0];
+#pragma unroll
+                    for (int rr = 1; rr < RS; ++rr) y = cadd(y, cmulc(col[rr], twl[(n1 * rr * L) % FS]));
+                    ybuf[(fl2 * FS + kx2) * boy + qy] = y;
+                }
+            }
+        }
+        __syncthreads();
+        // x-inverse: L-point inverse DFTs over kx = rx + RS m
+        float2* g2 = regA;      // [NF][boy][RS][L]
+        for (int i = tid; i < NF * boy * RS; i += 256) {
+            const int rx = i % RS;
+            int r = i / RS;
+            const int qy = r % boy;
+            const int fl2 = r / boy;
+            float2 s[L];
+#pragma unroll
+            for (int m = 0; m < L; ++m) s[m] = cconj(ybuf[(fl2 * FS + rx + RS * m) * boy + qy]);
+            Dft<L>::run(s);
+            float2* gr = g2 + ((fl2 * boy + qy) * RS + rx) * L;
+#pragma unroll
+            for (int n0 = 0; n0 < L; ++n0) gr[n0] = cmulc(cconj(s[n0]), twl[(n0 * rx) % FS]);
+        }
+        __syncthreads();
+        float2* y2 = regB;      // [NF][box][boy]
+        for (int i = tid; i < NF * boy * L; i += 256) {
+            const int n0 = i % L;
+            int r = i / L;
+            const int qy = r % boy;
+            const int fl2 = r / boy;
+            float2 col[RS];
+#pragma unroll
+            for (int rr = 0; rr < RS; ++rr) col[rr] = g2[((fl2 * boy + qy) * RS + rr) * L + n0];
+#pragma unroll
+            for (int n1 = 0; n1 < RS; ++n1) {
+                const int qx = n0 + L * n1;
+                if (qx < box) {
+                    float2 y = col[0];
+#pragma unroll
+                    for (int rr = 1; rr < RS; ++rr) y = cadd(y, cmulc(col[rr], twl[(n1 * rr * L) % FS]));
+                    y2[(fl2 * box + qx) * boy + qy] = y;
+                }
+            }
+        }
+        __syncthreads();
+        // I[q] = Re Y[q] + Im Y[q'] with q' the point reflection within the block output
+        // (Re Y(t) + Im Y'(t) = Re(Y(t) - i Y'(t)), taken after the inverse time FFT)
+        const int nq = box * boy;
+        for (int i = tid; i < qtiles * NF * kTile; i += 256) {
+            const int qi = i % kTile;
+            int r = i / kTile;
+            const int fl2 = r % NF;
+            const int qt = r / NF;
+            const int q = qt * kTile + qi;
+            float2 vq = make_float2(0.f, 0.f);
+            if (q < nq) {
+                const int qx = q / boy, qy = q % boy;
+                vq = y2[(fl2 * box + qx) * boy + qy];
+                if (A.mpcp) {
+                    const float2 yb = y2[(fl2 * box + (box - 1 - qx)) * boy + (boy - 1 - qy)];
+                    vq = make_float2(vq.x + yb.y, vq.y - yb.x);
+                }
+            }
+            U[((((int64_t)bl * A.nc + c) * qtiles + qt) * A.ft + f0 + fl2) * kTile + qi] = vq;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_ti: inverse time FFT of each output pixel and response piece; the real part of
+// piece c lands at tick offset c * ct. The lane that owns tick a in piece c owned
+// it in every earlier piece (ct is a multiple of 64), so the overlap is added in
+// program order by one thread.
+// ---------------------------------------------------------------------------
+template <int FT>
+__global__ __launch_bounds__(512) void k_ti(ConvArgs A, int b0, const int32_t* __restrict__ n_active,
+                                            const float2* __restrict__ U,
+                                            const float2* __restrict__ tw, float* __restrict__ out) {
+    extern __shared__ float lds[];
+    constexpr int M = FT / kWave;
+    const int bl = blockIdx.y, b = b0 + bl;
+    if (b >= min(*n_active, A.cap)) return;
+    const int qt = blockIdx.x;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = qt * kTile + wv;
+    const bool valid = q < A.box * A.boy;
+    const int qtiles = A.qpad / kTile;
+    float* orow = out + (int64_t)b * A.vout + (int64_t)(valid ? q : 0) * A.bot;
+    for (int c = 0; c < A.nc; ++c) {
+        const float4* s4 = (const float4*)(U + ((((int64_t)bl * A.nc + c) * qtiles + qt) * FT) * kTile);
+        float4* d4 = (float4*)lds;
+        for (int i = threadIdx.x; i < FT * kTile / 2; i += blockDim.x) d4[i] = s4[i];
+        __syncthreads();
+        const float2* stage = (const float2*)lds;
+        float2 v[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = cconj(stage[(lane + kWave * m) * kTile + wv]);
+        __syncthreads();
+        wave_fft<FT>(v, lds + wv * kFftLds<FT>, tw, lane);
+        if (valid) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int t = lane + kWave * m;
+                const int a = c * A.ct + t;
+                if (a < A.bot) {
+                    const float r = v[m].x;  // Re conj(.) = Re(.)
+                    if (c > 0 && t < A.Bt) orow[a] += r;
+                    else orow[a] = r;
+                }
+            }
+        }
+    }
+}
+
+int pow2_at_least(int v, int lo) {
+    int p = lo;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+ConvArgs make_args(const tred_conv_plan* P) {
+    ConvArgs A;
+    const tred_grid& g = P->grid;
+    A.Bx = P->blk.blk_pix[0];
+    A.By = P->blk.blk_pix[1];
+    A.Bt = P->blk.blk_ticks;
+    A.sx = g.sub[0];
+    A.sy = g.sub[1];
+    A.NYf = A.By * A.sy;
+    A.S = A.sx * A.sy;
+    A.nch = P->nch;
+    A.nc = P->nc;
+    A.ct = P->ct;
+    A.ft = P->ft;
+    A.fs = P->fs;
+    A.ppad = (A.Bx * A.By + kTile - 1) / kTile * kTile;
+    A.qpad = P->qpad;
+    A.box = P->bo[0];
+    A.boy = P->bo[1];
+    A.bot = P->bo[2];
+    A.mpcp = P->mpcp;
+    A.chx = std::max(1, A.fs / A.By);
+    A.cap = 0;
+    const int L = std::min(A.fs, 16);
+    const int RS = A.fs / L;
+    const int NF = 256 / (A.fs * RS);
+    const int64_t fwd = (int64_t)A.chx * NF * A.ppad + (int64_t)A.chx * NF * A.fs * A.By;
+    const int64_t g1 = (int64_t)NF * A.fs * A.fs;
+    const int64_t g2 = (int64_t)NF * A.boy * A.fs;
+    A.ldsA = (int32_t)std::max(fwd, std::max(g1, g2));
+    A.ldsB = (int32_t)std::max((int64_t)NF * A.fs * A.boy, (int64_t)NF * A.box * A.boy);
+    A.vblk = (int64_t)A.Bx * A.sx * A.NYf * A.Bt;
+    A.vout = (int64_t)A.box * A.boy * A.bot;
+    return A;
+}
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+    // permit dynamic LDS above the 64 KiB default (gfx950 has 160 KiB per CU)
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+
+template <int FT>
+tred_status launch_time_fwd(const ConvArgs& A, int b0, int nb, const int32_t* na, const float* blocks,
+                            const float2* tw, float2* T, hipStream_t st) {
+    const size_t lds = (size_t)8 * kFftLds<FT> * sizeof(float);
+    allow_lds(k_tf<FT>, lds);
+    hipLaunchKernelGGL((k_tf<FT>), dim3(A.ppad / kTile, A.nch, nb), dim3(512), lds, st, A, b0, na,
+                       blocks, tw, T);
+    return tred_check_launch("tred_block_conv time forward");
+}
+
+template <int FT>
+tred_status launch_time_inv(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* U,
+                            const float2* tw, float* out, hipStream_t st) {
+    const size_t lds = (size_t)8 * kFftLds<FT> * sizeof(float);
+    allow_lds(k_ti<FT>, lds);
+    hipLaunchKernelGGL((k_ti<FT>), dim3(A.qpad / kTile, nb), dim3(512), lds, st, A, b0, na, U, tw,
+                       out);
+    return tred_check_launch("tred_block_conv time inverse");
+}
+
+template <int FS, int L>
+tred_status launch_space(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
+                         const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
+    constexpr int RS = FS / L, NF = 256 / (FS * RS);
+    const size_t lds = (size_t)(FS + A.ldsA + A.ldsB) * sizeof(float2);
+    allow_lds(k_sp<FS, L>, lds);
+    hipLaunchKernelGGL((k_sp<FS, L>), dim3(A.ft / NF, nb), dim3(256), lds, st, A, b0, na, T, rhat,
+                       tws, U);
+    return tred_check_launch("tred_block_conv space");
+}
+
+template <typename F>
+tred_status dispatch_ft(int ft, F&& f) {
+    switch (ft) {
+        case 256: return f(std::integral_constant<int, 256>{});
+        case 512: return f(std::integral_constant<int, 512>{});
+        case 1024: return f(std::integral_constant<int, 1024>{});
+        case 2048: return f(std::integral_constant<int, 2048>{});
+        default: return tred_fail(TRED_EUNSUPPORTED, "time FFT size %d", ft);
+    }
+}
+
+}  // namespace
+
+extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_blocking* blocking,
+                                             const int32_t kpix[2], int32_t kticks,
+                                             const int32_t fft[3], uint32_t flags, int32_t batch,
+                                             tred_conv_plan** plan, int64_t* workspace_bytes) {
+    TRED_TRY(validate_grid(grid));
+    TRED_TRY(validate_blocking(blocking));
+    TRED_REQUIRE(kpix && plan && workspace_bytes, "kpix/plan/workspace_bytes is NULL");
+    TRED_REQUIRE(kpix[0] > 0 && kpix[1] > 0 && (kpix[0] & 1) && (kpix[1] & 1),
+                 "kpix must be positive and odd");
+    TRED_REQUIRE(kticks > 0, "kticks must be > 0");
+    TRED_REQUIRE(batch > 0, "batch must be > 0");
+    TRED_REQUIRE((flags & ~TRED_CONV_MPCP) == 0, "unknown flags");
+    *plan = nullptr;
+    tred_conv_plan* P = new tred_conv_plan();
+    P->grid = *grid;
+    P->blk = *blocking;
+    P->kpix[0] = kpix[0];
+    P->kpix[1] = kpix[1];
+    P->kticks = kticks;
+    P->mpcp = (flags & TRED_CONV_MPCP) ? 1 : 0;
+    P->batch = batch;
+    const int Bx = blocking->blk_pix[0], By = blocking->blk_pix[1], Bt = blocking->blk_ticks;
+    P->bo[0] = Bx + kpix[0] - 1;
+    P->bo[1] = By + kpix[1] - 1;
+    P->bo[2] = Bt + kticks - 1;
+    int fsx = fft && fft[0] ? fft[0] : pow2_at_least(P->bo[0], 8);
+    int fsy = fft && fft[1] ? fft[1] : pow2_at_least(P->bo[1], 8);
+    int ft = fft && fft[2] ? fft[2] : pow2_at_least(P->bo[2], 256);
+    auto bad = [&](tred_status s, const char* msg) {
+        delete P;
+        return tred_fail(s, "%s", msg);
+    };
+    if (!is_pow2(fsx) || !is_pow2(fsy) || fsx < P->bo[0] || fsy < P->bo[1])
+        return bad(TRED_EINVAL, "spatial FFT sizes must be powers of two >= blk_pix + kpix - 1");
+    if (fsx != fsy || fsx < 8 || fsx > 64)
+        return bad(TRED_EUNSUPPORTED, "spatial FFT sizes must be equal and in {8,16,32,64}");
+    const int L = std::min(fsx, 16);
+    if (Bx > L || By > L) return bad(TRED_EUNSUPPORTED, "blk_pix must be <= min(fft, 16)");
+    if (Bt % 64 != 0) return bad(TRED_EUNSUPPORTED, "blk_ticks must be a multiple of 64");
+    if (!is_pow2(ft)) return bad(TRED_EINVAL, "time FFT size must be a power of two");
+    if (ft < 256 || ft > 2048) return bad(TRED_EUNSUPPORTED, "time FFT size must be in [256, 2048]");
+    if (ft < Bt + 64) return bad(TRED_EINVAL, "time FFT size must be >= blk_ticks + 64");
+    P->fs = fsx;
+    P->ft = ft;
+    P->ct = ft - Bt;
+    P->nc = (kticks + P->ct - 1) / P->ct;
+    if (P->nc > 4) return bad(TRED_EUNSUPPORTED, "more than 4 response pieces; raise fft[2]");
+    const int S = grid->sub[0] * grid->sub[1];
+    P->nch = P->mpcp ? (S + 1) / 2 : S;
+    P->qpad = (P->bo[0] * P->bo[1] + kTile - 1) / kTile * kTile;
+    const int64_t ppad = (Bx * By + kTile - 1) / kTile * kTile;
+    // workspace layout
+    int64_t o = 0;
+    P->off_tw_t = o;
+    o = align256(o + (int64_t)ft * 8);
+    P->off_tw_s = o;
+    o = align256(o + (int64_t)P->fs * 8);
+    P->off_chan = o;
+    P->off_rhat = o;
+    o = align256(o + (int64_t)P->nch * P->nc * P->fs * P->fs * ft * 8);
+    P->off_scratch_t = o;
+    const int64_t tbytes = align256((int64_t)batch * P->nch * ppad * ft * 8);
+    const int64_t ubytes = align256((int64_t)batch * P->nc * P->qpad * ft * 8);
+    // set-up scratch (binary64): PA, PB and two twiddle tables
+    const int64_t pa = (int64_t)P->nch * P->nc * kpix[0] * kpix[1] * ft * 16;
+    const int64_t pb = (int64_t)P->nch * P->nc * P->fs * kpix[1] * ft * 16;
+    const int64_t setup = align256(pa) + align256(pb) + align256((int64_t)(ft + P->fs) * 16) + 256;
+    const int64_t scr = std::max(tbytes + ubytes, setup);
+    P->off_scratch_u = o + tbytes;
+    o += scr;
+    P->ws_bytes = o;
+    P->ws = nullptr;
+    P->ready = 0;
+    *plan = P;
+    *workspace_bytes = o;
+    return TRED_OK;
+}
+
+extern "C" tred_status tred_conv_plan_info(const tred_conv_plan* P, int32_t fft[3], int32_t* pieces,
+                                           int32_t* channels, int32_t out[3]) {
+    TRED_REQUIRE(P != nullptr, "plan is NULL");
+    if (fft) {
+        fft[0] = P->fs;
+        fft[1] = P->fs;
+        fft[2] = P->ft;
+    }
+    if (pieces) *pieces = P->nc;
+    if (channels) *channels = P->nch;
+    if (out)
+        for (int a = 0; a < 3; ++a) out[a] = P->bo[a];
+    return TRED_OK;
+}
+
+extern "C" tred_status tred_conv_plan_set_response(tred_conv_plan* P, const float* resp,
+                                                   void* workspace, void* stream) {
+    TRED_REQUIRE(P && resp && workspace, "plan/resp/workspace is NULL");
+    TRED_REQUIRE(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    const int Kx = P->kpix[0], Ky = P->kpix[1], kt = P->kticks;
+    const int sx = P->grid.sub[0], sy = P->grid.sub[1];
+    char* scr = ws + P->off_scratch_t;
+    int64_t o = 0;
+    double2* PA = (double2*)(scr + o);
+    o += align256((int64_t)P->nch * P->nc * Kx * Ky * P->ft * 16);
+    double2* PB = (double2*)(scr + o);
+    o += align256((int64_t)P->nch * P->nc * P->fs * Ky * P->ft * 16);
+    double2* twdt = (double2*)(scr + o);
+    double2* twds = twdt + P->ft;
+    o += align256((int64_t)(P->ft + P->fs) * 16);
+    int* bad = (int*)(scr + o);
+    if (P->mpcp) {
+        if (hipMemsetAsync(bad, 0, sizeof(int), st) != hipSuccess)
+            return tred_fail(TRED_EDEVICE, "memset failed");
+        hipLaunchKernelGGL(k_symcheck, dim3(1024), dim3(256), 0, st, resp, Kx, Ky, sx, sy, kt, bad);
+        TRED_TRY(tred_check_launch("symmetry check"));
+        int hbad = 0;
+        if (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return tred_fail(TRED_EDEVICE, "symmetry check readback failed");
+        if (hbad != 0)
+            return tred_fail(TRED_EINVAL,
+                             "mirror-pair packing needs R[K-1-k][sub-1-j][t] == R[k][j][t] "
+                             "(%d entries differ)", hbad);
+    }
+    ConvArgs A = make_args(P);
+    const int mx = std::max(P->ft, P->fs);
+    hipLaunchKernelGGL(k_twiddles, dim3((mx + 255) / 256), dim3(256), 0, st,
+                       (float2*)(ws + P->off_tw_t), P->ft, (float2*)(ws + P->off_tw_s), P->fs, twdt,
+                       twds);
+    hipLaunchKernelGGL(k_rhat_time, dim3(8192), dim3(256), 0, st, resp, A, Kx, Ky, kt, twdt, PA);
+    hipLaunchKernelGGL(k_rhat_x, dim3(8192), dim3(256), 0, st, A, Kx, Ky, twds, PA, PB);
+    const int L = std::min(P->fs, 16);
+    const double scale = 1.0 / ((double)P->fs * P->fs * P->ft);
+    hipLaunchKernelGGL(k_rhat_y, dim3(8192), dim3(256), 0, st, A, Ky, L, scale, twds, PB,
+                       (float2*)(ws + P->off_rhat));
+    TRED_TRY(tred_check_launch("response spectra"));
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return tred_fail(TRED_EDEVICE, "response spectra: %s", hipGetErrorString(hipGetLastError()));
+    P->ws = workspace;
+    P->ready = 1;
+    return TRED_OK;
+}
+
+extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n_active,
+                                       int32_t cap, const float* blocks, float* out_blocks,
+                                       void* stream) {
+    TRED_REQUIRE(P && n_active, "plan/n_active is NULL");
+    TRED_REQUIRE(P->ready, "plan has no response (call tred_conv_plan_set_response)");
+    TRED_REQUIRE(cap >= 0, "cap must be >= 0");
+    if (cap == 0) return TRED_OK;
+    TRED_REQUIRE(blocks && out_blocks, "blocks/out_blocks is NULL");
+    TRED_REQUIRE(((uintptr_t)blocks & 15) == 0 && ((uintptr_t)out_blocks & 3) == 0,
+                 "blocks must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    ConvArgs A = make_args(P);
+    A.cap = cap;
+    char* ws = (char*)P->ws;
+    const float2* twt = (const float2*)(ws + P->off_tw_t);
+    const float2* tws = (const float2*)(ws + P->off_tw_s);
+    const float2* rhat = (const float2*)(ws + P->off_rhat);
+    float2* T = (float2*)(ws + P->off_scratch_t);
+    float2* U = (float2*)(ws + P->off_scratch_u);
+    for (int b0 = 0; b0 < cap; b0 += P->batch) {
+        const int nb = std::min(P->batch, cap - b0);
+        TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
+            return launch_time_fwd<decltype(ftc)::value>(A, b0, nb, n_active, blocks, twt, T, st);
+        }));
+        tred_status s;
+        switch (P->fs) {
+            case 8: s = launch_space<8, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 16: s = launch_space<16, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 32: s = launch_space<32, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            default: s = launch_space<64, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+        }
+        TRED_TRY(s);
+        TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
+            return launch_time_inv<decltype(ftc)::value>(A, b0, nb, n_active, U, twt, out_blocks, st);
+        }));
+    }
+    return TRED_OK;
+}
+
+extern "C" void tred_conv_plan_destroy(tred_conv_plan* P) { delete P; }

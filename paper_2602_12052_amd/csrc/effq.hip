@@ -1,0 +1,478 @@
+// Transport, quadrature windows and effective charge of line-segment depositions
+// (Sec. II-A; Sec. II-C eqs. cub, trilinear, eff_q, qline and the point-like limit).
+#include <cmath>
+
+#include "tred_internal.hpp"
+#include "validate.hpp"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Discrete decisions: a fixed chain of correctly rounded binary32 operations.
+// Division and square root are evaluated in binary64 and rounded once to
+// binary32, which equals the correctly rounded binary32 result (53 >= 2*24 + 2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float div_rn(float a, float b) { return (float)((double)a / (double)b); }
+__device__ __forceinline__ float sqrt_rn(float a) { return (float)sqrt((double)a); }
+
+__device__ __forceinline__ int32_t floor_to_int(float v) {
+    float f = floorf(v);
+    f = fminf(fmaxf(f, -16777216.0f), 16777216.0f);
+    return (int32_t)f;
+}
+
+struct Win {
+    int32_t lo[3], hi[3];
+    int point;
+};
+
+__device__ Win window_f32(const tred_grid& g, const tred_physics& ph, const float* s) {
+#pragma clang fp contract(off)
+    Win w;
+    const float v = ph.v_drift;
+    const float t0 = div_rn(s[2], v);
+    const float t1 = div_rn(s[5], v);
+    float tm = (t0 + t1) * 0.5f;
+    if (tm < 0.0f) tm = 0.0f;
+    const float sT = sqrt_rn((2.0f * ph.diff_T) * tm);
+    const float sL = div_rn(sqrt_rn((2.0f * ph.diff_L) * tm), v);
+    const float sg[3] = {fmaxf(sT, ph.sigma_min[0]), fmaxf(sT, ph.sigma_min[1]),
+                         fmaxf(sL, ph.sigma_min[2])};
+    const float P0[3] = {s[0], s[1], t0};
+    const float P1[3] = {s[3], s[4], t1};
+    int point = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float h = g.spacing[a];
+        float u0 = div_rn(P0[a] - g.origin[a], h);
+        float u1 = div_rn(P1[a] - g.origin[a], h);
+        if (a == 2) {
+            u0 = u0 + 0.5f;
+            u1 = u1 + 0.5f;
+        }
+        const float e = ph.n_sigma * div_rn(sg[a], h);
+        const float umin = u0 < u1 ? u0 : u1;
+        const float umax = u0 < u1 ? u1 : u0;
+        w.lo[a] = floor_to_int(umin - e);
+        w.hi[a] = floor_to_int(umax + e);
+        const float dd = fabsf(P1[a] - P0[a]);
+        if (!(dd < ph.point_frac * sg[a])) point = 0;
+    }
+    w.point = point;
+    return w;
+}
+
+__device__ __forceinline__ int nfine(const tred_grid& g, int a) {
+    return a == 0 ? g.npix[0] * g.sub[0] : a == 1 ? g.npix[1] * g.sub[1] : g.nticks;
+}
+
+__global__ __launch_bounds__(256) void k_windows(tred_grid g, tred_physics ph, int64_t n,
+                                                 const float* __restrict__ seg,
+                                                 int32_t* __restrict__ fp,
+                                                 int64_t* __restrict__ off) {
+    int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d == 0) off[0] = 0;
+    if (d >= n) return;
+    float s[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) s[k] = seg[7 * d + k];
+    Win w = window_f32(g, ph, s);
+    int64_t vol = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int32_t N = nfine(g, a);
+        int32_t lo = max(w.lo[a] - 1, 0);
+        int32_t hi = min(w.hi[a] + 1, N - 1);
+        fp[6 * d + a] = lo;
+        fp[6 * d + 3 + a] = hi;
+        vol = hi < lo ? 0 : vol * (int64_t)(hi - lo + 1);
+    }
+    off[d + 1] = vol;
+}
+
+// In-place inclusive scan of a[1..n] by one workgroup of 1024 threads.
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int64_t u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_inplace(int64_t* __restrict__ a, int64_t n) {
+    constexpr int PER = 16;
+    __shared__ int64_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int64_t carry = 0;
+    for (int64_t base = 0; base < n; base += 1024 * PER) {
+        int64_t v[PER];
+        int64_t s = 0;
+        const int64_t i0 = base + (int64_t)tid * PER;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            v[k] = (i0 + k < n) ? a[1 + i0 + k] : 0;
+            s += v[k];
+        }
+        int64_t incl = wave_incl_scan(s, lane);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        if (wave == 0) {
+            int64_t t = lane < 16 ? wsum[lane] : 0;
+            t = wave_incl_scan(t, lane);
+            if (lane < 16) wsum[lane] = t;
+        }
+        __syncthreads();
+        int64_t run = carry + incl - s + (wave > 0 ? wsum[wave - 1] : 0);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            run += v[k];
+            if (i0 + k < n) a[1 + i0 + k] = run;
+        }
+        carry += wsum[15];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Effective charge
+// ---------------------------------------------------------------------------
+struct EffqParams {
+    tred_grid g;
+    tred_physics ph;
+    float xi[8];   // Gauss-Legendre nodes on [-1,1], ascending
+    float w[8];    // weights
+    float u[16];   // per-axis spread weights over the node stencil of one grid point
+};
+
+// erf(b) - erf(a), through erfc when both arguments share a sign (no cancellation
+// of the tails)
+__device__ __forceinline__ float erf_diff(float b, float a) {
+    if (a >= 0.0f && b >= 0.0f) return erfcf(a) - erfcf(b);
+    if (a <= 0.0f && b <= 0.0f) return erfcf(-b) - erfcf(-a);
+    return erff(b) - erff(a);
+}
+
+// Small 3-D index iterator advancing by a fixed stride (avoids per-element divisions).
+struct Idx3 {
+    int i, j, k;        // k fastest
+    int nj, nk;
+    int di, dj, dk;     // decomposition of the stride
+    __device__ void init(int start, int stride, int nj_, int nk_) {
+        nj = nj_;
+        nk = nk_;
+        k = start % nk;
+        int r = start / nk;
+        j = r % nj;
+        i = r / nj;
+        dk = stride % nk;
+        r = stride / nk;
+        dj = r % nj;
+        di = r / nj;
+    }
+    __device__ void next() {
+        k += dk;
+        int c = 0;
+        if (k >= nk) { k -= nk; c = 1; }
+        j += dj + c;
+        c = 0;
+        if (j >= nj) { j -= nj; c = 1; }
+        i += di + c;
+    }
+};
+
+template <int NGL, int CAP>
+__global__ __launch_bounds__(256) void k_effq(EffqParams P, int64_t n_dep,
+                                              const float* __restrict__ seg,
+                                              const int32_t* __restrict__ fp,
+                                              const int64_t* __restrict__ off,
+                                              float* __restrict__ val, int64_t val_cap,
+                                              double* __restrict__ charge_sum) {
+    constexpr int N3 = NGL * NGL * NGL;
+    constexpr int NPOS = NGL / 2;                 // nodes with xi > 0 in a cell
+    __shared__ float V[CAP];
+    __shared__ double red[4];
+    __shared__ float sxi[8], sw[8], su[16];
+    const int tid = threadIdx.x;
+    const tred_grid& g = P.g;
+    if (tid < 8) {
+        sxi[tid] = P.xi[tid];
+        sw[tid] = P.w[tid];
+    }
+    if (tid < 16) su[tid] = P.u[tid];
+    __syncthreads();
+
+    for (int64_t d = blockIdx.x; d < n_dep; d += gridDim.x) {
+        const int32_t* f = fp + 6 * d;
+        int F0[3] = {f[0], f[1], f[2]}, F1[3] = {f[3], f[4], f[5]};
+        if (F1[0] < F0[0] || F1[1] < F0[1] || F1[2] < F0[2]) continue;
+        const int64_t o0 = off[d], o1 = off[d + 1];
+        if (o1 > val_cap) continue;
+        float s[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) s[k] = seg[7 * d + k];
+        const Win W = window_f32(g, P.ph, s);
+
+        // transport (binary64 per deposition, Sec. II-A)
+        const double v = P.ph.v_drift;
+        const double t0 = (double)s[2] / v, t1 = (double)s[5] / v;
+        double tm = 0.5 * (t0 + t1);
+        if (tm < 0.0) tm = 0.0;
+        const double Qp = (double)s[6] * exp(-tm / (double)P.ph.lifetime);
+        const double sT = sqrt(2.0 * (double)P.ph.diff_T * tm);
+        const double sg[3] = {fmax(sT, (double)P.ph.sigma_min[0]), fmax(sT, (double)P.ph.sigma_min[1]),
+                              fmax(sqrt(2.0 * (double)P.ph.diff_L * tm) / v, (double)P.ph.sigma_min[2])};
+        const double h[3] = {g.spacing[0], g.spacing[1], g.spacing[2]};
+        const double D[3] = {(double)s[3] - (double)s[0], (double)s[4] - (double)s[1], t1 - t0};
+        // node coordinates relative to the segment start (line) or midpoint (point):
+        // r_a = base_a + ((c - lo_a) + xi/2) h_a
+        double base[3];
+        base[0] = (double)g.origin[0] + ((double)W.lo[0] + 0.5) * h[0] - (double)s[0];
+        base[1] = (double)g.origin[1] + ((double)W.lo[1] + 0.5) * h[1] - (double)s[1];
+        base[2] = (double)g.origin[2] + (double)W.lo[2] * h[2] - t0;
+        const bool point = W.point != 0;
+        float fb[3], fh[3], fd[3], isg2[3], gvec[3];
+        float inv_alpha = 0.f, kq = 0.f, pref;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            fb[a] = (float)(point ? base[a] - 0.5 * D[a] : base[a]);
+            fh[a] = (float)h[a];
+            fd[a] = (float)D[a];
+            isg2[a] = (float)(1.0 / (sg[a] * sg[a]));
+        }
+        if (point) {
+            pref = (float)(Qp * pow(2.0 * M_PI, -1.5) / (sg[0] * sg[1] * sg[2]));
+        } else {
+            double alpha = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                gvec[a] = (float)(D[a] / (sg[a] * sg[a]));
+                alpha += D[a] * D[a] / (sg[a] * sg[a]);
+            }
+            inv_alpha = (float)(1.0 / alpha);
+            kq = (float)sqrt(0.5 * alpha);
+            // Q / (4 pi Delta) with Delta = sigma_x sigma_y sigma_t sqrt(alpha)
+            pref = (float)(Qp / (4.0 * M_PI * sg[0] * sg[1] * sg[2] * sqrt(alpha)));
+        }
+        const float jac = (float)(h[0] * h[1] * h[2] / 8.0);
+
+        // node cells that can reach the footprint: window intersected with F +- 1
+        int C0[3], C1[3], Fs[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C0[a] = max(W.lo[a], F0[a] - 1);
+            C1[a] = min(W.hi[a], F1[a] + 1);
+            Fs[a] = F1[a] - F0[a] + 1;
+        }
+        // tile: whole footprint in x, y when it fits, as many ticks as fit
+        int T[3] = {Fs[0], Fs[1], Fs[2]};
+        auto ncell = [&](int a, int len) { return min(len + 2, C1[a] - C0[a] + 1); };
+        while (N3 * ncell(0, T[0]) * ncell(1, T[1]) * ncell(2, 1) > CAP && (T[0] > 1 || T[1] > 1)) {
+            if (T[0] >= T[1]) T[0] = (T[0] + 1) / 2;
+            else T[1] = (T[1] + 1) / 2;
+        }
+        {
+            int per = N3 * ncell(0, T[0]) * ncell(1, T[1]);
+            int tt = 1;
+            while (tt < Fs[2] && per * ncell(2, tt + 1) <= CAP) ++tt;
+            T[2] = tt;
+        }
+        const int64_t FY = Fs[1], FT = Fs[2];
+        double nsum = 0.0;
+
+        for (int X0 = F0[0]; X0 <= F1[0]; X0 += T[0])
+            for (int Y0 = F0[1]; Y0 <= F1[1]; Y0 += T[1])
+                for (int Z0 = F0[2]; Z0 <= F1[2]; Z0 += T[2]) {
+                    const int X1 = min(X0 + T[0] - 1, F1[0]);
+                    const int Y1 = min(Y0 + T[1] - 1, F1[1]);
+                    const int Z1 = min(Z0 + T[2] - 1, F1[2]);
+                    const int t0c[3] = {X0, Y0, Z0}, t1c[3] = {X1, Y1, Z1};
+                    int c0[3], nn[3], own0[3], own1[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        c0[a] = max(C0[a], t0c[a] - 1);
+                        const int c1 = min(C1[a], t1c[a] + 1);
+                        nn[a] = (c1 - c0[a] + 1) * NGL;
+                        // cells whose nodes this tile counts in the charge sum
+                        own0[a] = t0c[a] == F0[a] ? t0c[a] - 1 : t0c[a];
+                        own1[a] = t1c[a] == F1[a] ? t1c[a] + 1 : t1c[a];
+                    }
+                    const int total = nn[0] * nn[1] * nn[2];
+                    // 1) node charges w * q(node) into LDS
+                    {
+                        Idx3 it;
+                        it.init(tid, 256, nn[1], nn[2]);
+                        for (int i = tid; i < total; i += 256, it.next()) {
+                            const int cx = c0[0] + it.i / NGL, lx = it.i % NGL;
+                            const int cy = c0[1] + it.j / NGL, ly = it.j % NGL;
+                            const int ct = c0[2] + it.k / NGL, lt = it.k % NGL;
+                            const float rx = fb[0] + ((float)(cx - W.lo[0]) + 0.5f * sxi[lx]) * fh[0];
+                            const float ry = fb[1] + ((float)(cy - W.lo[1]) + 0.5f * sxi[ly]) * fh[1];
+                            const float rt = fb[2] + ((float)(ct - W.lo[2]) + 0.5f * sxi[lt]) * fh[2];
+                            float q;
+                            if (point) {
+                                const float e = rx * rx * isg2[0] + ry * ry * isg2[1] + rt * rt * isg2[2];
+                                q = pref * expf(-0.5f * e);
+                            } else {
+                                const float beta = rx * gvec[0] + ry * gvec[1] + rt * gvec[2];
+                                const float sst = beta * inv_alpha;       // closest point on the line
+                                const float px = rx - sst * fd[0], py = ry - sst * fd[1],
+                                            pt = rt - sst * fd[2];
+                                const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
+                                q = pref * expf(-0.5f * e) * erf_diff(kq * (1.0f - sst), -kq * sst);
+                            }
+                            const float vq = sw[lx] * sw[ly] * sw[lt] * jac * q;
+                            V[i] = vq;
+                            if (cx >= own0[0] && cx <= own1[0] && cy >= own0[1] && cy <= own1[1] &&
+                                ct >= own0[2] && ct <= own1[2])
+                                nsum += (double)vq;
+                        }
+                    }
+                    __syncthreads();
+                    // 2) each footprint cell gathers the spread of its 27-cell neighbourhood
+                    {
+                        const int nx = X1 - X0 + 1, ny = Y1 - Y0 + 1, nz = Z1 - Z0 + 1;
+                        const int count = nx * ny * nz;
+                        Idx3 it;
+                        it.init(tid, 256, ny, nz);
+                        for (int k = tid; k < count; k += 256, it.next()) {
+                            const int gx = X0 + it.i, gy = Y0 + it.j, gz = Z0 + it.k;
+                            const int fx = (gx - 1 - c0[0]) * NGL + (NGL - NPOS);
+                            const int fy = (gy - 1 - c0[1]) * NGL + (NGL - NPOS);
+                            const int fz = (gz - 1 - c0[2]) * NGL + (NGL - NPOS);
+                            constexpr int S = NGL + 2 * NPOS;
+                            const int ax0 = max(fx, 0), ax1 = min(fx + S - 1, nn[0] - 1);
+                            const int ay0 = max(fy, 0), ay1 = min(fy + S - 1, nn[1] - 1);
+                            const int az0 = max(fz, 0), az1 = min(fz + S - 1, nn[2] - 1);
+                            float acc = 0.0f;
+                            for (int x = ax0; x <= ax1; ++x) {
+                                float ay = 0.0f;
+                                for (int y = ay0; y <= ay1; ++y) {
+                                    const float* vr = V + (x * nn[1] + y) * nn[2];
+                                    float az = 0.0f;
+                                    for (int z = az0; z <= az1; ++z) az += su[z - fz] * vr[z];
+                                    ay += su[y - fy] * az;
+                                }
+                                acc += su[x - fx] * ay;
+                            }
+                            val[o0 + ((int64_t)(gx - F0[0]) * FY + (gy - F0[1])) * FT + (gz - F0[2])] = acc;
+                        }
+                    }
+                    __syncthreads();
+                }
+        if (charge_sum) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) nsum += __shfl_down(nsum, o, kWave);
+            if ((tid & 63) == 0) red[tid >> 6] = nsum;
+            __syncthreads();
+            if (tid == 0) atomicAdd(charge_sum, red[0] + red[1] + red[2] + red[3]);
+            __syncthreads();
+        }
+    }
+}
+
+// Gauss-Legendre rule by Newton iteration on P_n (three-term recurrence).
+void gl_rule(int n, double* xi, double* w) {
+    for (int i = 0; i < n; ++i) {
+        double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double p = 0, pm = 0, dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            p = 1.0;
+            pm = 0.0;
+            for (int k = 0; k < n; ++k) {
+                double pn = ((2.0 * k + 1.0) * x * p - k * pm) / (k + 1.0);
+                pm = p;
+                p = pn;
+            }
+            dp = n * (pm - x * p) / (1.0 - x * x);
+            double dx = p / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        p = 1.0;
+        pm = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double pn = ((2.0 * k + 1.0) * x * p - k * pm) / (k + 1.0);
+            pm = p;
+            p = pn;
+        }
+        dp = n * (pm - x * p) / (1.0 - x * x);
+        xi[n - 1 - i] = x;
+        w[n - 1 - i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+template <int NGL>
+void launch_effq(const EffqParams& P, int64_t n_dep, const float* seg, const int32_t* fp,
+                 const int64_t* off, float* val, int64_t val_cap, double* cs, hipStream_t st) {
+    constexpr int CAP = 16384;
+    int64_t grid = n_dep < (1 << 20) ? n_dep : (1 << 20);
+    hipLaunchKernelGGL((k_effq<NGL, CAP>), dim3((unsigned)grid), dim3(256), 0, st, P, n_dep, seg,
+                       fp, off, val, val_cap, cs);
+}
+
+}  // namespace
+
+extern "C" tred_status tred_effq_windows(const tred_grid* grid, const tred_physics* phys,
+                                         int64_t n_dep, const float* seg, int32_t* fp,
+                                         int64_t* off, void* stream) {
+    TRED_TRY(validate_grid(grid));
+    TRED_TRY(validate_physics(phys));
+    TRED_REQUIRE(n_dep >= 0, "n_dep must be >= 0");
+    TRED_REQUIRE(off != nullptr, "off is NULL");
+    TRED_REQUIRE(n_dep == 0 || (seg != nullptr && fp != nullptr), "seg/fp is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t nb = (n_dep + 255) / 256;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(k_windows, dim3((unsigned)nb), dim3(256), 0, st, *grid, *phys, n_dep, seg,
+                       fp, off);
+    TRED_TRY(tred_check_launch("tred_effq_windows"));
+    if (n_dep > 0) {
+        hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, st, off, n_dep);
+        TRED_TRY(tred_check_launch("tred_effq_windows scan"));
+    }
+    return TRED_OK;
+}
+
+extern "C" tred_status tred_effq(const tred_grid* grid, const tred_physics* phys, int64_t n_dep,
+                                 const float* seg, const int32_t* fp, const int64_t* off,
+                                 float* val, int64_t val_cap, double* charge_sum, void* stream) {
+    TRED_TRY(validate_grid(grid));
+    TRED_TRY(validate_physics(phys));
+    TRED_REQUIRE(phys->point_frac > 0.0f, "physics.point_frac must be > 0 for the line form");
+    TRED_REQUIRE(n_dep >= 0, "n_dep must be >= 0");
+    TRED_REQUIRE(val_cap >= 0, "val_cap must be >= 0");
+    if (n_dep == 0) return TRED_OK;
+    TRED_REQUIRE(seg && fp && off, "seg/fp/off is NULL");
+    TRED_REQUIRE(val != nullptr || val_cap == 0, "val is NULL");
+    EffqParams P;
+    P.g = *grid;
+    P.ph = *phys;
+    double xi[8], w[8];
+    const int n = phys->n_gl;
+    gl_rule(n, xi, w);
+    for (int i = 0; i < 8; ++i) {
+        P.xi[i] = i < n ? (float)xi[i] : 0.f;
+        P.w[i] = i < n ? (float)w[i] : 0.f;
+    }
+    // stencil of grid point g: nodes with xi > 0 of cell g-1 (weight |xi|/2), all
+    // nodes of cell g (1 - |xi|/2), nodes with xi < 0 of cell g+1 (|xi|/2)
+    const int npos = n / 2;
+    int k = 0;
+    for (int l = n - npos; l < n; ++l) P.u[k++] = (float)(std::fabs(xi[l]) / 2.0);
+    for (int l = 0; l < n; ++l) P.u[k++] = (float)(1.0 - std::fabs(xi[l]) / 2.0);
+    for (int l = 0; l < npos; ++l) P.u[k++] = (float)(std::fabs(xi[l]) / 2.0);
+    for (; k < 16; ++k) P.u[k] = 0.f;
+    hipStream_t st = (hipStream_t)stream;
+    switch (n) {
+        case 1: launch_effq<1>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
+        case 2: launch_effq<2>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
+        case 3: launch_effq<3>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
+        case 4: launch_effq<4>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
+        case 5: launch_effq<5>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
+        case 6: launch_effq<6>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
+        case 7: launch_effq<7>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
+        default: launch_effq<8>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
+    }
+    return tred_check_launch("tred_effq");
+}

@@ -1,0 +1,179 @@
+// Overlap-add of the block outputs onto unique electrodes (Sec. III-B: reduction of
+// overlapping outputs by summation; Fig. 1, "bin & accumulate on unique electrodes").
+// Each waveform sample gathers the outputs of the (at most a few) active bins whose
+// output footprint covers it, so every sample is written once, without atomics.
+#include <algorithm>
+
+#include "tred_internal.hpp"
+#include "validate.hpp"
+
+namespace {
+
+struct ScatArgs {
+    int32_t npx, npy, Bx, By, Bt, hx, hy, kt;
+    int32_t nb[3];
+    int32_t box, boy, bot;
+    int32_t lwf;        // waveform length nticks + kticks - 1
+    int32_t cap, pix_cap;
+    int64_t vout;
+};
+
+__global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// per active bin: mark the pixels of its output footprint, record the bin's slot
+__global__ __launch_bounds__(256) void k_mark_pix(ScatArgs S, const int32_t* __restrict__ keys,
+                                                  const int32_t* __restrict__ n_active,
+                                                  int32_t* __restrict__ pmap,
+                                                  int32_t* __restrict__ bmap) {
+    const int na = min(*n_active, S.cap);
+    for (int i = blockIdx.x; i < na; i += gridDim.x) {
+        const int bx = keys[3 * i], by = keys[3 * i + 1], bt = keys[3 * i + 2];
+        if (threadIdx.x == 0) bmap[((int64_t)bx * S.nb[1] + by) * S.nb[2] + bt] = i;
+        const int x0 = max(0, bx * S.Bx - S.hx), x1 = min(S.npx - 1, bx * S.Bx + S.Bx - 1 + S.hx);
+        const int y0 = max(0, by * S.By - S.hy), y1 = min(S.npy - 1, by * S.By + S.By - 1 + S.hy);
+        const int ny = y1 - y0 + 1;
+        const int cnt = (x1 - x0 + 1) * ny;
+        for (int k = threadIdx.x; k < cnt; k += blockDim.x)
+            pmap[(int64_t)(x0 + k / ny) * S.npy + (y0 + k % ny)] = 1;
+    }
+}
+
+__device__ __forceinline__ int wave_incl_scan_i32(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// compaction of the marked pixels in id order: pix list, pmap -> slot or -1, n_pix
+__global__ __launch_bounds__(1024) void k_compact_pix(ScatArgs S, int32_t* __restrict__ pmap,
+                                                      int32_t* __restrict__ pix,
+                                                      int32_t* __restrict__ n_pix) {
+    __shared__ int wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tot = (int64_t)S.npx * S.npy;
+    int carry = 0;
+    for (int64_t base = 0; base < tot; base += 1024) {
+        const int64_t i = base + tid;
+        const int f = (i < tot && pmap[i] != 0) ? 1 : 0;
+        const int incl = wave_incl_scan_i32(f, lane);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        if (wave == 0) {
+            int t = lane < 16 ? wsum[lane] : 0;
+            t = wave_incl_scan_i32(t, lane);
+            if (lane < 16) wsum[lane] = t;
+        }
+        __syncthreads();
+        const int slot = carry + incl - f + (wave > 0 ? wsum[wave - 1] : 0);
+        if (i < tot) {
+            if (f && slot < S.pix_cap) pix[slot] = (int32_t)i;
+            pmap[i] = (f && slot < S.pix_cap) ? slot : -1;
+        }
+        carry += wsum[15];
+        __syncthreads();
+    }
+    if (tid == 0) *n_pix = carry;
+}
+
+// one workgroup per (pixel slot, 256-tick tile)
+__global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __restrict__ pix,
+                                                const int32_t* __restrict__ n_pix,
+                                                const int32_t* __restrict__ bmap,
+                                                const float* __restrict__ outb,
+                                                float* __restrict__ wf) {
+    const int slot = blockIdx.x;
+    if (slot >= min(*n_pix, S.pix_cap)) return;
+    const int p = pix[slot];
+    const int px = p / S.npy, py = p % S.npy;
+    const int T0 = blockIdx.y * 256;
+    const int T = T0 + threadIdx.x;
+    // bins whose output footprint contains this pixel: b*B - h <= p <= b*B + B - 1 + h
+    const int bx0 = max(0, (px - S.hx - S.Bx + 1 + S.Bx * 4096) / S.Bx - 4096);
+    const int bx1 = min(S.nb[0] - 1, (px + S.hx) / S.Bx);
+    const int by0 = max(0, (py - S.hy - S.By + 1 + S.By * 4096) / S.By - 4096);
+    const int by1 = min(S.nb[1] - 1, (py + S.hy) / S.By);
+    // bins whose ticks [bt Bt, bt Bt + bot) meet the tile [T0, T0 + 256)
+    const int bt0 = max(0, (T0 - S.bot + 1 + S.Bt * 4096) / S.Bt - 4096);
+    const int bt1 = min(S.nb[2] - 1, (T0 + 255) / S.Bt);
+    float acc = 0.0f;
+    for (int bx = bx0; bx <= bx1; ++bx)
+        for (int by = by0; by <= by1; ++by) {
+            const int qx = px - bx * S.Bx + S.hx, qy = py - by * S.By + S.hy;
+            if (qx < 0 || qx >= S.box || qy < 0 || qy >= S.boy) continue;
+            for (int bt = bt0; bt <= bt1; ++bt) {
+                const int b = bmap[((int64_t)bx * S.nb[1] + by) * S.nb[2] + bt];
+                if (b < 0) continue;
+                const int t = T - bt * S.Bt;
+                if (t >= 0 && t < S.bot)
+                    acc += outb[(int64_t)b * S.vout + ((int64_t)qx * S.boy + qy) * S.bot + t];
+            }
+        }
+    if (T < S.lwf) wf[(int64_t)slot * S.lwf + T] = acc;
+}
+
+ScatArgs make_sargs(const tred_conv_plan* P) {
+    ScatArgs S;
+    S.npx = P->grid.npix[0];
+    S.npy = P->grid.npix[1];
+    S.Bx = P->blk.blk_pix[0];
+    S.By = P->blk.blk_pix[1];
+    S.Bt = P->blk.blk_ticks;
+    S.hx = (P->kpix[0] - 1) / 2;
+    S.hy = (P->kpix[1] - 1) / 2;
+    S.kt = P->kticks;
+    for (int a = 0; a < 3; ++a) S.nb[a] = nblk_axis(&P->grid, &P->blk, a);
+    S.box = P->bo[0];
+    S.boy = P->bo[1];
+    S.bot = P->bo[2];
+    S.lwf = P->grid.nticks + P->kticks - 1;
+    S.vout = (int64_t)S.box * S.boy * S.bot;
+    return S;
+}
+
+}  // namespace
+
+extern "C" int64_t tred_scatter_workspace(const tred_conv_plan* P) {
+    if (!P) return -1;
+    const int64_t nbt = (int64_t)nblk_axis(&P->grid, &P->blk, 0) * nblk_axis(&P->grid, &P->blk, 1) *
+                        nblk_axis(&P->grid, &P->blk, 2);
+    return ((int64_t)P->grid.npix[0] * P->grid.npix[1] + nbt) * 4;
+}
+
+extern "C" tred_status tred_scatter_waveforms(const tred_conv_plan* P, const int32_t* keys,
+                                              const int32_t* n_active, int32_t cap,
+                                              const float* out_blocks, int32_t* pix, int32_t* n_pix,
+                                              float* wf, int32_t pix_cap, void* work,
+                                              void* stream) {
+    TRED_REQUIRE(P && n_active && n_pix && work, "plan/n_active/n_pix/work is NULL");
+    TRED_REQUIRE(cap >= 0 && pix_cap >= 0, "capacities must be >= 0");
+    TRED_REQUIRE(cap == 0 || (keys && out_blocks), "keys/out_blocks is NULL");
+    TRED_REQUIRE(pix_cap == 0 || (pix && wf), "pix/wf is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    ScatArgs S = make_sargs(P);
+    S.cap = cap;
+    S.pix_cap = pix_cap;
+    int32_t* pmap = (int32_t*)work;
+    const int64_t npix_tot = (int64_t)S.npx * S.npy;
+    int32_t* bmap = pmap + npix_tot;
+    const int64_t nbt = (int64_t)S.nb[0] * S.nb[1] * S.nb[2];
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((npix_tot + 255) / 256, 4096)),
+                       dim3(256), 0, st, pmap, npix_tot, 0);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((nbt + 255) / 256, 4096)), dim3(256),
+                       0, st, bmap, nbt, -1);
+    if (cap > 0)
+        hipLaunchKernelGGL(k_mark_pix, dim3((unsigned)std::min(cap, 65536)), dim3(256), 0, st, S,
+                           keys, n_active, pmap, bmap);
+    hipLaunchKernelGGL(k_compact_pix, dim3(1), dim3(1024), 0, st, S, pmap, pix, n_pix);
+    TRED_TRY(tred_check_launch("tred_scatter_waveforms compact"));
+    if (pix_cap > 0)
+        hipLaunchKernelGGL(k_gather, dim3(pix_cap, (S.lwf + 255) / 256), dim3(256), 0, st, S, pix,
+                           n_pix, bmap, out_blocks, wf);
+    return tred_check_launch("tred_scatter_waveforms");
+}

@@ -1,0 +1,244 @@
+// Internal helpers of the gfx950 library: status handling, complex arithmetic,
+// in-register DFT codelets and the per-wavefront Stockham FFT used on the time axis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tred.h"
+
+// ---------------------------------------------------------------------------
+// host-side status helpers (api.cpp)
+// ---------------------------------------------------------------------------
+tred_status tred_fail(tred_status s, const char* fmt, ...);
+tred_status tred_check_launch(const char* what);
+
+#define TRED_REQUIRE(cond, ...)                                      \
+    do {                                                             \
+        if (!(cond)) return tred_fail(TRED_EINVAL, __VA_ARGS__);     \
+    } while (0)
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// complex arithmetic on float2
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i
+__device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
+// multiply by +i
+__device__ __forceinline__ float2 cmul_pi(float2 a) { return make_float2(-a.y, a.x); }
+
+// ---------------------------------------------------------------------------
+// Forward DFT codelets in registers, natural order in and out:
+// X[k] = sum_n x[n] exp(-2 pi i n k / R).
+// Twiddle constants are the correctly rounded binary32 values of cos/sin of
+// multiples of pi/8.
+// ---------------------------------------------------------------------------
+namespace cst {
+constexpr float r2 = 0.70710678118654752f;   // cos(pi/4)
+constexpr float c8 = 0.92387953251128676f;   // cos(pi/8)
+constexpr float s8 = 0.38268343236508977f;   // sin(pi/8)
+}  // namespace cst
+
+// multiply by exp(-2 pi i k / R) for compile-time k, R (R divides 16)
+template <int R, int K>
+__device__ __forceinline__ float2 wconst(float2 a) {
+    constexpr int k16 = ((K * (16 / R)) % 16 + 16) % 16;  // angle in units of 2 pi / 16
+    if constexpr (k16 == 0) return a;
+    else if constexpr (k16 == 4) return cmul_mi(a);
+    else if constexpr (k16 == 8) return make_float2(-a.x, -a.y);
+    else if constexpr (k16 == 12) return cmul_pi(a);
+    else if constexpr (k16 == 2) return make_float2(cst::r2 * (a.x + a.y), cst::r2 * (a.y - a.x));
+    else if constexpr (k16 == 6) return make_float2(cst::r2 * (a.y - a.x), -cst::r2 * (a.x + a.y));
+    else if constexpr (k16 == 10) return make_float2(-cst::r2 * (a.x + a.y), cst::r2 * (a.x - a.y));
+    else if constexpr (k16 == 14) return make_float2(cst::r2 * (a.x - a.y), cst::r2 * (a.x + a.y));
+    else {
+        // generic: cos(2 pi k/16), sin(2 pi k/16) for odd k
+        constexpr float cs[16] = {1.f, cst::c8, cst::r2, cst::s8, 0.f, -cst::s8, -cst::r2, -cst::c8,
+                                  -1.f, -cst::c8, -cst::r2, -cst::s8, 0.f, cst::s8, cst::r2, cst::c8};
+        constexpr float sn[16] = {0.f, cst::s8, cst::r2, cst::c8, 1.f, cst::c8, cst::r2, cst::s8,
+                                  0.f, -cst::s8, -cst::r2, -cst::c8, -1.f, -cst::c8, -cst::r2, -cst::s8};
+        // exp(-i theta) = cos - i sin
+        return cmul(a, make_float2(cs[k16], -sn[k16]));
+    }
+}
+
+template <int R>
+struct Dft;
+
+template <>
+struct Dft<1> {
+    __device__ __forceinline__ static void run(float2*) {}
+};
+
+template <>
+struct Dft<2> {
+    __device__ __forceinline__ static void run(float2* x) {
+        float2 a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    }
+};
+
+template <>
+struct Dft<4> {
+    __device__ __forceinline__ static void run(float2* x) {
+        float2 s02 = cadd(x[0], x[2]), d02 = csub(x[0], x[2]);
+        float2 s13 = cadd(x[1], x[3]), d13 = csub(x[1], x[3]);
+        x[0] = cadd(s02, s13);
+        x[2] = csub(s02, s13);
+        x[1] = cadd(d02, cmul_mi(d13));
+        x[3] = csub(d02, cmul_mi(d13));
+    }
+};
+
+// radix-2 split of an R-point DFT into two R/2-point DFTs (R = 8, 16)
+template <int R>
+struct Dft {
+    template <int K>
+    __device__ __forceinline__ static void comb(float2* x, const float2* e, const float2* o) {
+        if constexpr (K < R / 2) {
+            float2 t = wconst<R, K>(o[K]);
+            x[K] = cadd(e[K], t);
+            x[K + R / 2] = csub(e[K], t);
+            comb<K + 1>(x, e, o);
+        }
+    }
+    __device__ __forceinline__ static void run(float2* x) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = x[2 * i];
+            o[i] = x[2 * i + 1];
+        }
+        Dft<R / 2>::run(e);
+        Dft<R / 2>::run(o);
+        comb<0>(x, e, o);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Per-wavefront Stockham FFT of length N = 64 * M (M in {4, 8, 16, 32, 64}).
+// On entry lane l holds x[l + 64 m] in v[m]; on exit X[l + 64 m] (forward DFT,
+// natural order). `buf` is the wave's private LDS scratch of kFftLds<N> floats;
+// `tw` is a table of exp(-2 pi i k / N), k < N (global or LDS).
+// Radix sequence: N = R1 * R2 * ... with every radix <= 16.
+// Stage (radix R, Ns = product of earlier radices): butterfly j reads
+// in[j + r N/R], multiplies by exp(-2 pi i r (j mod Ns) / (Ns R)), takes an
+// R-point DFT and writes out[(j / Ns) Ns R + j mod Ns + r Ns].
+// ---------------------------------------------------------------------------
+template <int N>
+struct FftPlan;
+template <> struct FftPlan<256>  { static constexpr int R[4] = {4, 4, 4, 4}; static constexpr int S = 4; };
+template <> struct FftPlan<512>  { static constexpr int R[4] = {8, 8, 8, 1}; static constexpr int S = 3; };
+template <> struct FftPlan<1024> { static constexpr int R[4] = {16, 16, 4, 1}; static constexpr int S = 3; };
+template <> struct FftPlan<2048> { static constexpr int R[4] = {16, 16, 8, 1}; static constexpr int S = 3; };
+template <> struct FftPlan<4096> { static constexpr int R[4] = {16, 16, 16, 1}; static constexpr int S = 3; };
+
+// padded LDS index: one pad word per 16 (keeps stride-16 accesses conflict free)
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+template <int N>
+constexpr int kFftLds = 2 * (N + N / 16);
+
+template <int N, int R, int NS, bool FIRST>
+__device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* tw, int lane) {
+    constexpr int M = N / kWave;
+    constexpr int NB = N / R;            // butterflies in this stage
+    constexpr int PER = NB / kWave;      // butterflies per lane
+    static_assert(PER >= 1 && PER * R == M, "radix does not match the lane data");
+    float* re = buf;
+    float* im = buf + (N + N / 16);
+    float2 u[M];
+    if constexpr (FIRST) {
+        // inputs in[j + r N/R] with j = lane + 64 i: register i + r * PER
+#pragma unroll
+        for (int m = 0; m < M; ++m) u[m] = v[m];
+    } else {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            int j = lane + kWave * i;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int idx = lpad(j + r * NB);
+                u[i * R + r] = make_float2(re[idx], im[idx]);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        int j = lane + kWave * i;
+        float2 x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = FIRST ? u[i + r * PER] : u[i * R + r];
+        if constexpr (NS > 1) {
+            int jm = j % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * jm * (N / (NS * R))]);
+        }
+        Dft<R>::run(x);
+        int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int idx = lpad(base + r * NS);
+            re[idx] = x[r].x;
+            im[idx] = x[r].y;
+        }
+    }
+    __syncthreads();
+}
+
+template <int N>
+__device__ __forceinline__ void wave_fft(float2* v, float* buf, const float2* tw, int lane) {
+    using P = FftPlan<N>;
+    constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
+    fft_stage<N, R0, 1, true>(v, buf, tw, lane);
+    fft_stage<N, R1, R0, false>(v, buf, tw, lane);
+    if constexpr (P::S >= 3) fft_stage<N, R2, R0 * R1, false>(v, buf, tw, lane);
+    if constexpr (P::S >= 4) fft_stage<N, R3, R0 * R1 * R2, false>(v, buf, tw, lane);
+    constexpr int M = N / kWave;
+    const float* re = buf;
+    const float* im = buf + (N + N / 16);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        int idx = lpad(lane + kWave * m);
+        v[m] = make_float2(re[idx], im[idx]);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Plan object (host side)
+// ---------------------------------------------------------------------------
+struct tred_conv_plan {
+    tred_grid grid;
+    tred_blocking blk;
+    int32_t kpix[2];
+    int32_t kticks;
+    int32_t fs;          // spatial FFT size (square)
+    int32_t ft;          // time FFT size
+    int32_t ct;          // response ticks per piece
+    int32_t nc;          // response pieces
+    int32_t nch;         // transformed channels (pairs under MPCP)
+    int32_t mpcp;
+    int32_t batch;
+    int32_t bo[3];       // output block extent
+    int32_t qpad;        // output pixels per block padded to the tile of 8
+    // workspace layout (byte offsets)
+    int64_t off_tw_t, off_tw_s, off_rhat, off_chan, off_scratch_t, off_scratch_u;
+    int64_t ws_bytes;
+    void* ws;            // bound by set_response
+    int ready;
+};
+
+constexpr int kTile = 8;   // pixels per interleaved tile of the spectral scratch

@@ -1,0 +1,353 @@
+"""Thin Python binding of libtred.so (the gfx950 HIP library).
+
+Every function marshals torch device tensors into the C ABI of ``include/tred.h``
+and raises on a non-OK status; all arithmetic runs in the library's kernels.
+There is no fallback: if the library is missing or no GPU is present, calls fail.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtred.so")
+
+TRED_OK, TRED_EINVAL, TRED_ECAPACITY, TRED_EDEVICE, TRED_EUNSUPPORTED = range(5)
+TRED_CONV_MPCP = 1
+
+
+class TredError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tred status {status}: {msg}")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("spacing", C.c_float * 3), ("npix", C.c_int32 * 2),
+                ("sub", C.c_int32 * 2), ("nticks", C.c_int32)]
+
+
+class Physics(C.Structure):
+    _fields_ = [("v_drift", C.c_float), ("lifetime", C.c_float), ("diff_T", C.c_float),
+                ("diff_L", C.c_float), ("sigma_min", C.c_float * 3), ("n_sigma", C.c_float),
+                ("point_frac", C.c_float), ("n_gl", C.c_int32)]
+
+
+class Blocking(C.Structure):
+    _fields_ = [("blk_pix", C.c_int32 * 2), ("blk_ticks", C.c_int32)]
+
+
+def grid_struct(g) -> Grid:
+    if isinstance(g, Grid):
+        return g
+    return Grid((C.c_float * 3)(*g.origin), (C.c_float * 3)(*g.spacing), (C.c_int32 * 2)(*g.npix),
+                (C.c_int32 * 2)(*g.sub), int(g.nticks))
+
+
+def physics_struct(p) -> Physics:
+    if isinstance(p, Physics):
+        return p
+    return Physics(p.v_drift, p.lifetime, p.diff_T, p.diff_L, (C.c_float * 3)(*p.sigma_min),
+                   p.n_sigma, p.point_frac, int(p.n_gl))
+
+
+def blocking_struct(b) -> Blocking:
+    if isinstance(b, Blocking):
+        return b
+    return Blocking((C.c_int32 * 2)(*b.blk_pix), int(b.blk_ticks))
+
+
+EXPORTS = [
+    "tred_status_string", "tred_last_error", "tred_abi_version", "tred_effq_windows", "tred_effq",
+    "tred_block_count", "tred_block_bin_workspace", "tred_block_bin", "tred_conv_plan_create",
+    "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_block_conv",
+    "tred_scatter_workspace", "tred_scatter_waveforms", "tred_conv_plan_destroy",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libtred.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2602_12052_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, U32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+    L.tred_status_string.argtypes = [C.c_int]
+    L.tred_status_string.restype = C.c_char_p
+    L.tred_last_error.restype = C.c_char_p
+    L.tred_abi_version.restype = C.c_int
+    L.tred_effq_windows.argtypes = [P, P, I64, P, P, P, P]
+    L.tred_effq.argtypes = [P, P, I64, P, P, P, P, I64, P, P]
+    L.tred_block_count.argtypes = [P, P]
+    L.tred_block_count.restype = I32
+    L.tred_block_bin_workspace.argtypes = [P, P]
+    L.tred_block_bin_workspace.restype = I64
+    L.tred_block_bin.argtypes = [P, P, I64, P, P, P, I64, P, P, P, I32, P, P]
+    L.tred_conv_plan_create.argtypes = [P, P, P, I32, P, U32, I32, C.POINTER(C.c_void_p),
+                                        C.POINTER(C.c_int64)]
+    L.tred_conv_plan_set_response.argtypes = [P, P, P, P]
+    L.tred_conv_plan_info.argtypes = [P, P, P, P, P]
+    L.tred_block_conv.argtypes = [P, P, I32, P, P, P]
+    L.tred_scatter_workspace.argtypes = [P]
+    L.tred_scatter_workspace.restype = I64
+    L.tred_scatter_waveforms.argtypes = [P, P, P, I32, P, P, P, P, I32, P, P]
+    L.tred_conv_plan_destroy.argtypes = [P]
+    L.tred_conv_plan_destroy.restype = None
+    for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
+                 "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_block_conv",
+                 "tred_scatter_waveforms"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != TRED_OK:
+        raise TredError(status, lib().tred_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _dt(t, dtype, name):
+    if t is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+# ---------------------------------------------------------------------------
+# C-ABI wrappers (same names, torch tensors in place of pointers)
+# ---------------------------------------------------------------------------
+
+
+def tred_effq_windows(grid, phys, seg, fp, off, stream=None):
+    import torch
+    _dt(seg, torch.float32, "seg"), _dt(fp, torch.int32, "fp"), _dt(off, torch.int64, "off")
+    g, p = grid_struct(grid), physics_struct(phys)
+    n = seg.shape[0] if seg is not None else 0
+    _check(lib().tred_effq_windows(C.byref(g), C.byref(p), n, _ptr(seg), _ptr(fp), _ptr(off),
+                                   _stream(stream)))
+
+
+def tred_effq(grid, phys, seg, fp, off, val, charge_sum=None, stream=None):
+    import torch
+    _dt(val, torch.float32, "val"), _dt(charge_sum, torch.float64, "charge_sum")
+    g, p = grid_struct(grid), physics_struct(phys)
+    n = seg.shape[0]
+    _check(lib().tred_effq(C.byref(g), C.byref(p), n, _ptr(seg), _ptr(fp), _ptr(off), _ptr(val),
+                           val.numel(), _ptr(charge_sum), _stream(stream)))
+
+
+def tred_block_count(grid, blocking) -> int:
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    return int(lib().tred_block_count(C.byref(g), C.byref(b)))
+
+
+def tred_block_bin_workspace(grid, blocking) -> int:
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    return int(lib().tred_block_bin_workspace(C.byref(g), C.byref(b)))
+
+
+def tred_block_bin(grid, blocking, fp, off, val, keys, n_active, blocks, work, stream=None):
+    """keys/blocks may be None to only count the active bins (cap = 0)."""
+    import torch
+    _dt(keys, torch.int32, "keys"), _dt(n_active, torch.int32, "n_active")
+    _dt(blocks, torch.float32, "blocks")
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    n = fp.shape[0]
+    cap = 0 if keys is None else keys.shape[0]
+    if blocks is not None and blocks.shape[0] < cap:
+        raise ValueError("blocks has fewer rows than keys")
+    _check(lib().tred_block_bin(C.byref(g), C.byref(b), n, _ptr(fp), _ptr(off), _ptr(val),
+                                val.numel(), _ptr(keys), _ptr(n_active), _ptr(blocks), cap,
+                                _ptr(work), _stream(stream)))
+
+
+class ConvPlan:
+    """Owner of a tred_conv_plan and its device workspace."""
+
+    def __init__(self, grid, blocking, kpix, kticks, fft=None, mpcp=True, batch=64):
+        import torch
+        self.grid, self.blocking = grid_struct(grid), blocking_struct(blocking)
+        kp = (C.c_int32 * 2)(*kpix)
+        ff = (C.c_int32 * 3)(*(fft or (0, 0, 0)))
+        h = C.c_void_p()
+        ws = C.c_int64()
+        _check(lib().tred_conv_plan_create(C.byref(self.grid), C.byref(self.blocking), kp,
+                                           int(kticks), ff, TRED_CONV_MPCP if mpcp else 0,
+                                           int(batch), C.byref(h), C.byref(ws)))
+        self.handle = h
+        self.kpix, self.kticks, self.mpcp = tuple(kpix), int(kticks), bool(mpcp)
+        self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device="cuda")
+        info = self.info()
+        self.fft, self.pieces, self.channels, self.out_shape = info
+
+    def info(self):
+        f = (C.c_int32 * 3)()
+        o = (C.c_int32 * 3)()
+        pcs = C.c_int32()
+        ch = C.c_int32()
+        _check(lib().tred_conv_plan_info(self.handle, f, C.byref(pcs), C.byref(ch), o))
+        return tuple(f), int(pcs.value), int(ch.value), tuple(o)
+
+    def _ws_ptr(self):
+        p = self.workspace.data_ptr()
+        return (p + 255) // 256 * 256
+
+    def set_response(self, resp, stream=None):
+        import torch
+        _dt(resp, torch.float32, "resp")
+        _check(lib().tred_conv_plan_set_response(self.handle, _ptr(resp), self._ws_ptr(),
+                                                 _stream(stream)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and self.handle.value:
+                lib().tred_conv_plan_destroy(self.handle)
+                self.handle = C.c_void_p()
+        except Exception:
+            pass
+
+
+def tred_block_conv(plan: ConvPlan, n_active, blocks, out_blocks, stream=None):
+    import torch
+    _dt(out_blocks, torch.float32, "out_blocks")
+    cap = blocks.shape[0]
+    if out_blocks.shape[0] < cap:
+        raise ValueError("out_blocks has fewer rows than blocks")
+    _check(lib().tred_block_conv(plan.handle, _ptr(n_active), cap, _ptr(blocks), _ptr(out_blocks),
+                                 _stream(stream)))
+
+
+def tred_scatter_workspace(plan: ConvPlan) -> int:
+    return int(lib().tred_scatter_workspace(plan.handle))
+
+
+def tred_scatter_waveforms(plan: ConvPlan, keys, n_active, out_blocks, pix, n_pix, wf, work,
+                           stream=None):
+    import torch
+    _dt(pix, torch.int32, "pix"), _dt(n_pix, torch.int32, "n_pix"), _dt(wf, torch.float32, "wf")
+    cap = keys.shape[0]
+    _check(lib().tred_scatter_waveforms(plan.handle, _ptr(keys), _ptr(n_active), cap,
+                                        _ptr(out_blocks), _ptr(pix), _ptr(n_pix), _ptr(wf),
+                                        pix.shape[0], _ptr(work), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Whole path
+# ---------------------------------------------------------------------------
+
+
+class Pipeline:
+    """Buffers and plan for one event shape; run() enqueues the five calls with no
+    host synchronisation (capacities fixed at construction)."""
+
+    def __init__(self, grid, phys, blocking, kpix, kticks, resp, n_dep, val_cap, block_cap,
+                 pix_cap, fft=None, mpcp=True, batch=64):
+        import torch
+        dev = "cuda"
+        self.grid, self.phys, self.blocking = grid_struct(grid), physics_struct(phys), \
+            blocking_struct(blocking)
+        self.n_dep = int(n_dep)
+        self.plan = ConvPlan(grid, blocking, kpix, kticks, fft, mpcp, batch)
+        self.plan.set_response(resp)
+        self.fp = torch.empty((self.n_dep, 6), dtype=torch.int32, device=dev)
+        self.off = torch.empty(self.n_dep + 1, dtype=torch.int64, device=dev)
+        self.val = torch.empty(int(val_cap), dtype=torch.float32, device=dev)
+        self.charge_sum = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.keys = torch.empty((int(block_cap), 3), dtype=torch.int32, device=dev)
+        self.n_active = torch.zeros(1, dtype=torch.int32, device=dev)
+        g, b = self.grid, self.blocking
+        vblk = b.blk_pix[0] * g.sub[0] * b.blk_pix[1] * g.sub[1] * b.blk_ticks
+        self.blocks = torch.empty((int(block_cap), vblk), dtype=torch.float32, device=dev)
+        o = self.plan.out_shape
+        self.out_blocks = torch.empty((int(block_cap), o[0] * o[1] * o[2]), dtype=torch.float32,
+                                      device=dev)
+        self.bin_work = torch.empty(max(4, tred_block_bin_workspace(g, b)), dtype=torch.uint8,
+                                    device=dev)
+        self.pix = torch.empty(int(pix_cap), dtype=torch.int32, device=dev)
+        self.n_pix = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.lwf = g.nticks + int(kticks) - 1
+        self.wf = torch.empty((int(pix_cap), self.lwf), dtype=torch.float32, device=dev)
+        self.scat_work = torch.empty(max(4, tred_scatter_workspace(self.plan)), dtype=torch.uint8,
+                                     device=dev)
+
+    def run(self, seg, stream=None, stop_after: Optional[str] = None):
+        tred_effq_windows(self.grid, self.phys, seg, self.fp, self.off, stream)
+        self.charge_sum.zero_()
+        tred_effq(self.grid, self.phys, seg, self.fp, self.off, self.val, self.charge_sum, stream)
+        if stop_after == "effq":
+            return
+        tred_block_bin(self.grid, self.blocking, self.fp, self.off, self.val, self.keys,
+                       self.n_active, self.blocks, self.bin_work, stream)
+        if stop_after == "bin":
+            return
+        tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
+        tred_scatter_waveforms(self.plan, self.keys, self.n_active, self.out_blocks, self.pix,
+                               self.n_pix, self.wf, self.scat_work, stream)
+
+    def results(self):
+        """Host copies of the outputs (synchronises)."""
+        import torch
+        torch.cuda.synchronize()
+        na = int(self.n_active.item())
+        npx = int(self.n_pix.item())
+        nval = int(self.off[-1].item())
+        return dict(fp=self.fp.cpu().numpy(), off=self.off.cpu().numpy(),
+                    val=self.val[:min(nval, self.val.numel())].cpu().numpy(),
+                    charge_sum=float(self.charge_sum.item()), n_active=na,
+                    keys=self.keys[:min(na, self.keys.shape[0])].cpu().numpy(), n_pix=npx,
+                    pix=self.pix[:min(npx, self.pix.shape[0])].cpu().numpy(),
+                    wf=self.wf[:min(npx, self.pix.shape[0])].cpu().numpy())
+
+
+def size_event(grid, phys, blocking, kpix, seg):
+    """Capacities of one event: exact patch length and active-bin count (footprint
+    step plus a counting pass of the binning, then one synchronisation), and the
+    host bound min(region pixels, bins x output pixels per bin) for the pixels."""
+    import torch
+    n = seg.shape[0]
+    fp = torch.empty((n, 6), dtype=torch.int32, device="cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    tred_effq_windows(grid, phys, seg, fp, off)
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    na = torch.zeros(1, dtype=torch.int32, device="cuda")
+    work = torch.empty(max(4, tred_block_bin_workspace(g, b)), dtype=torch.uint8, device="cuda")
+    dummy = torch.empty(1, dtype=torch.float32, device="cuda")
+    tred_block_bin(g, b, fp, off, dummy, None, na, None, work)
+    torch.cuda.synchronize()
+    val_cap = int(off[-1].item())
+    block_cap = int(na.item())
+    per = (b.blk_pix[0] + kpix[0] - 1) * (b.blk_pix[1] + kpix[1] - 1)
+    pix_cap = min(int(g.npix[0]) * int(g.npix[1]), block_cap * per)
+    return max(val_cap, 1), max(block_cap, 1), max(pix_cap, 1)
+
+
+def simulate(seg, resp, grid, phys, blocking, kpix, kticks, fft=None, mpcp=True, batch=64):
+    """One event through the whole path; returns host numpy outputs."""
+    val_cap, block_cap, pix_cap = size_event(grid, phys, blocking, kpix, seg)
+    pl = Pipeline(grid, phys, blocking, kpix, kticks, resp, seg.shape[0], val_cap, block_cap,
+                  pix_cap, fft, mpcp, batch)
+    pl.run(seg)
+    return pl.results()

@@ -1,0 +1,138 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the header
+declares, and host-side validation rejects bad arguments before enqueuing work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2602_12052_amd import tred
+    tred.lib()
+    return tred
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "tred.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tred_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(T):
+    names = header_functions()
+    assert len(names) >= 15
+    L = T.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(T.EXPORTS)
+
+
+def test_abi_version_and_status_strings(T):
+    L = T.lib()
+    assert L.tred_abi_version() == 1
+    assert L.tred_status_string(0) == b"ok"
+    assert L.tred_status_string(1) == b"invalid argument"
+    assert L.tred_status_string(99) == b"unknown status"
+
+
+def _cfg():
+    return W.cfg_plain_small()
+
+
+def test_validation_rejects_bad_structs(T):
+    L = T.lib()
+    cfg = _cfg()
+    g = T.grid_struct(cfg.grid)
+    p = T.physics_struct(cfg.physics)
+    off = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    bad = T.grid_struct(cfg.grid)
+    bad.npix[0] = 0
+    assert L.tred_effq_windows(C.byref(bad), C.byref(p), 1, off, off, off, None) == T.TRED_EINVAL
+    assert b"npix" in L.tred_last_error()
+    bp = T.physics_struct(cfg.physics)
+    bp.n_gl = 9
+    assert L.tred_effq_windows(C.byref(g), C.byref(bp), 1, off, off, off, None) == T.TRED_EINVAL
+    bp = T.physics_struct(cfg.physics)
+    bp.v_drift = -1.0
+    assert L.tred_effq_windows(C.byref(g), C.byref(bp), 1, off, off, off, None) == T.TRED_EINVAL
+    assert L.tred_effq_windows(C.byref(g), C.byref(p), -1, off, off, off, None) == T.TRED_EINVAL
+    assert L.tred_effq_windows(None, C.byref(p), 1, off, off, off, None) == T.TRED_EINVAL
+    bp = T.physics_struct(cfg.physics)
+    bp.point_frac = 0.0
+    assert L.tred_effq(C.byref(g), C.byref(bp), 1, off, off, off, off, 10, None, None) == T.TRED_EINVAL
+
+
+def test_block_count_and_workspace(T):
+    cfg = _cfg()
+    assert T.tred_block_count(cfg.grid, cfg.blocking) == 8 * 8 * 49
+    assert T.tred_block_bin_workspace(cfg.grid, cfg.blocking) == 8 * 8 * 49 * 4
+    cfg2 = W.cfg_module()
+    assert T.tred_block_count(cfg2.grid, cfg2.blocking) == 16 * 16 * 13
+
+
+def _plan(T, cfg, kpix=None, kticks=None, fft=(0, 0, 0), flags=1, batch=4):
+    g = T.grid_struct(cfg.grid)
+    b = T.blocking_struct(cfg.blocking)
+    kp = (C.c_int32 * 2)(*(kpix or cfg.kpix))
+    ff = (C.c_int32 * 3)(*fft)
+    h = C.c_void_p()
+    ws = C.c_int64()
+    st = T.lib().tred_conv_plan_create(C.byref(g), C.byref(b), kp, kticks or cfg.kticks, ff, flags,
+                                       batch, C.byref(h), C.byref(ws))
+    return st, h, ws.value
+
+
+def test_plan_create_resolves_sizes(T):
+    cfg = _cfg()
+    st, h, ws = _plan(T, cfg, fft=(8, 8, 256))
+    assert st == 0 and ws > 0
+    f = (C.c_int32 * 3)()
+    o = (C.c_int32 * 3)()
+    pcs, ch = C.c_int32(), C.c_int32()
+    assert T.lib().tred_conv_plan_info(h, f, C.byref(pcs), C.byref(ch), o) == 0
+    assert tuple(f) == (8, 8, 256) and pcs.value == 2 and ch.value == 50
+    assert tuple(o) == (8, 8, 327)
+    T.lib().tred_conv_plan_destroy(h)
+    st, h, ws = _plan(T, cfg)       # defaults: smallest sizes, one piece
+    T.lib().tred_conv_plan_info(h, f, C.byref(pcs), C.byref(ch), o)
+    assert tuple(f) == (8, 8, 512) and pcs.value == 1
+    T.lib().tred_conv_plan_destroy(h)
+    st, h, ws = _plan(T, cfg, flags=0)
+    T.lib().tred_conv_plan_info(h, f, C.byref(pcs), C.byref(ch), o)
+    assert ch.value == 100
+    T.lib().tred_conv_plan_destroy(h)
+    cfg2 = W.cfg_module()
+    st, h, ws = _plan(T, cfg2, fft=(64, 64, 1024))
+    T.lib().tred_conv_plan_info(h, f, C.byref(pcs), C.byref(ch), o)
+    assert st == 0 and pcs.value == 4 and tuple(o) == (36, 36, 2559)
+    T.lib().tred_conv_plan_destroy(h)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(kpix=(4, 5)), 1),                 # even response extent
+    (dict(fft=(8, 8, 100)), 1),             # not a power of two
+    (dict(fft=(8, 8, 128)), 4),             # below the supported time sizes
+    (dict(fft=(8, 16, 256)), 4),            # non-square spatial FFT
+    (dict(fft=(4, 4, 256)), 1),             # spatial FFT smaller than the output
+    (dict(fft=(8, 8, 256), kticks=2000), 4),  # more than four response pieces
+    (dict(flags=2), 1),                     # unknown flag
+    (dict(batch=0), 1),
+])
+def test_plan_create_rejects(T, kw, expect):
+    st, h, ws = _plan(T, _cfg(), **kw)
+    assert st == expect, T.lib().tred_last_error()
+    assert not h.value
+
+
+def test_block_conv_requires_response(T):
+    st, h, ws = _plan(T, _cfg(), fft=(8, 8, 256))
+    na = C.c_void_p(0x1000)
+    assert T.lib().tred_block_conv(h, na, 4, na, na, None) == T.TRED_EINVAL
+    assert b"set_response" in T.lib().tred_last_error()
+    T.lib().tred_conv_plan_destroy(h)

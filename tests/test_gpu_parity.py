@@ -1,0 +1,321 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs. Integer outputs (footprints, offsets, active-bin keys, pixel sets)
+must be bit-exact; floating-point outputs (patches, blocks, waveforms) must be
+within rel-L2 1e-5 of the binary64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(x, ref):
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2602_12052_amd import tred
+    tred.lib()
+    return tred
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def small_cfg(npix=6, sub=3, nticks=200, blk=(2, 2, 64), kpix=(3, 5), kticks=100, fft=(8, 8, 256),
+              n=20, seed=1, length=(0.01, 0.1)):
+    h = W.PITCH / sub
+    g = W.Grid(origin=(0.0, 0.0, 0.0), spacing=(h, h, W.TICK), npix=(npix, npix), sub=(sub, sub),
+               nticks=nticks)
+    ph = W.Physics(sigma_min=(0.5 * h, 0.5 * h, 0.5 * W.TICK))
+    zmax = nticks * W.TICK * ph.v_drift
+    seg = W.gen_uniform_segments(n, (npix * W.PITCH, npix * W.PITCH), (0.0, zmax),
+                                 length_range=length, seed=seed)
+    return g, ph, W.Blocking(blk[:2], blk[2]), kpix, kticks, fft, seg
+
+
+def gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp=True, batch=8, block_cap=None):
+    say(f"  gpu path: npix={g.npix} sub={g.sub} nticks={g.nticks} blk={blk.blk_pix}x{blk.blk_ticks}"
+        f" K={kpix}x{kticks} fft={fft} n={seg.shape[0]} mpcp={mpcp}")
+    sd = dev(seg)
+    val_cap, bcap, pix_cap = T.size_event(g, ph, blk, kpix, sd)
+    pl = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap,
+                    block_cap or bcap, pix_cap, fft, mpcp, batch)
+    pl.run(sd)
+    return pl.results()
+
+
+def oracle_path(orc, g, ph, blk, kpix, kticks, resp, seg):
+    return orc.simulate(g, ph, blk, kpix, kticks, resp, seg)
+
+
+def compare_all(r, o, tol=TOL):
+    assert np.array_equal(r["fp"], o["fp"])
+    assert np.array_equal(r["off"], o["off"])
+    assert rel_l2(r["val"], o["val"]) < tol, rel_l2(r["val"], o["val"])
+    assert r["n_active"] == len(o["keys"])
+    assert np.array_equal(r["keys"], o["keys"])
+    assert r["n_pix"] == len(o["pix"])
+    assert np.array_equal(r["pix"], o["pix"])
+    e = rel_l2(r["wf"], o["wf"])
+    say(f"  rel-L2 effq {rel_l2(r['val'], o['val']):.2e}  waveforms {e:.2e}")
+    assert e < tol
+    assert abs(r["charge_sum"] - o["node_sums"].sum()) < 1e-6 * abs(o["node_sums"].sum())
+
+
+# ---------------------------------------------------------------------------
+
+
+def test_footprints_bitexact_adversarial(T, orc):
+    """Windows and offsets bit-exact on random segments snapped to cell edges +- 1 ulp."""
+    import torch
+    say("test_footprints_bitexact_adversarial")
+    cfg = W.cfg_plain_small()
+    g, ph = cfg.grid, cfg.physics
+    rng = np.random.default_rng(5)
+    n = 20000
+    seg = W.gen_segments(cfg).copy()
+    seg = np.concatenate([seg] * 20)[:n]
+    h = np.float32(g.spacing[0])
+    k = rng.integers(0, 320, (n, 2)).astype(np.float32)
+    snap = (k * h).astype(np.float32)
+    nudge = rng.integers(-2, 3, (n, 2))
+    for c in range(2):
+        snap[:, c] = np.array([np.nextafter(v, np.float32(np.inf) if s > 0 else np.float32(-np.inf))
+                               if s != 0 else v for v, s in zip(snap[:, c], nudge[:, c])], np.float32)
+    seg[:, 0] = snap[:, 0]
+    seg[:, 1] = snap[:, 1]
+    zt = (rng.integers(0, 6250, n) * np.float32(0.05) * np.float32(0.16)).astype(np.float32)
+    seg[:, 2] = zt
+    fp = torch.empty((n, 6), dtype=torch.int32, device="cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    T.tred_effq_windows(g, ph, dev(seg), fp, off)
+    ofp, ooff, _ = orc.footprints(g, ph, seg)
+    assert np.array_equal(fp.cpu().numpy(), ofp)
+    assert np.array_equal(off.cpu().numpy(), ooff)
+
+
+@pytest.mark.parametrize("name,kw,mpcp", [
+    ("odd-sub-one-piece", dict(), True),
+    ("odd-sub-plain", dict(), False),
+    ("two-pieces", dict(kticks=300, n=25, seed=2), True),
+    ("fs16", dict(npix=8, blk=(4, 4, 64), kpix=(9, 9), kticks=120, fft=(16, 16, 256), seed=3), True),
+    ("fs32", dict(npix=16, blk=(8, 8, 64), kpix=(21, 21), kticks=150, fft=(32, 32, 256), n=15,
+                  seed=4), True),
+    ("fs64", dict(npix=32, nticks=1100, blk=(16, 16, 512), kpix=(21, 21), kticks=600,
+                  fft=(64, 64, 1024), n=20, seed=5), True),
+    ("sub10-three-pieces", dict(npix=8, sub=10, nticks=400, blk=(4, 4, 128), kpix=(5, 5), kticks=300,
+                                fft=(8, 8, 256), n=12, seed=6), True),
+    ("sub4-even-plain", dict(npix=6, sub=4, nticks=256, blk=(3, 3, 64), kpix=(3, 3), kticks=64,
+                             fft=(8, 8, 256), n=15, seed=7), False),
+])
+def test_small_paths_match_oracle(T, orc, name, kw, mpcp):
+    say(f"test_small_paths_match_oracle[{name}]")
+    g, ph, blk, kpix, kticks, fft, seg = small_cfg(**kw)
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=11)
+    r = gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp=mpcp, batch=3)
+    o = oracle_path(orc, g, ph, blk, kpix, kticks, resp, seg)
+    compare_all(r, o)
+
+
+def test_conv_delta_response_plain(T, orc):
+    """A single unit entry in the response copies the charge to one offset (plain path)."""
+    say("test_conv_delta_response_plain")
+    g, ph, blk, kpix, kticks, fft, seg = small_cfg(n=10, seed=8)
+    resp = W.delta_response(kpix, g.sub, kticks, 2, 1, 1, 2, 37)
+    r = gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp=False)
+    o = oracle_path(orc, g, ph, blk, kpix, kticks, resp, seg)
+    compare_all(r, o)
+
+
+def test_mpcp_rejects_asymmetric_response(T):
+    say("test_mpcp_rejects_asymmetric_response")
+    g, ph, blk, kpix, kticks, fft, seg = small_cfg()
+    resp = W.delta_response(kpix, g.sub, kticks, 2, 1, 1, 2, 37)
+    plan = T.ConvPlan(g, blk, kpix, kticks, fft, mpcp=True, batch=2)
+    with pytest.raises(T.TredError) as e:
+        plan.set_response(dev(resp))
+    assert e.value.status == T.TRED_EINVAL
+
+
+def test_plain_small_event_end_to_end(T, orc):
+    """1,000 segments in 32x32 pixels, 5x5x200 response, 4x4x128 bins: both packings."""
+    say("test_plain_small_event_end_to_end")
+    cfg = W.cfg_plain_small()
+    seg = W.gen_segments(cfg)
+    resp = W.synthetic_response(cfg.kpix, cfg.grid.sub, cfg.kticks)
+    o = oracle_path(orc, cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, resp, seg)
+    for mpcp in (True, False):
+        r = gpu_path(T, cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, cfg.fft, seg,
+                     resp, mpcp=mpcp, batch=512)
+        compare_all(r, o)
+
+
+def test_block_values_match_oracle(T, orc):
+    import torch
+    say("test_block_values_match_oracle")
+    cfg = W.cfg_plain_small()
+    g, ph, blk = cfg.grid, cfg.physics, cfg.blocking
+    seg = W.gen_segments(cfg, seed=3)
+    sd = dev(seg)
+    val_cap, bcap, _ = T.size_event(g, ph, blk, cfg.kpix, sd)
+    fp = torch.empty((seg.shape[0], 6), dtype=torch.int32, device="cuda")
+    off = torch.empty(seg.shape[0] + 1, dtype=torch.int64, device="cuda")
+    val = torch.empty(val_cap, dtype=torch.float32, device="cuda")
+    T.tred_effq_windows(g, ph, sd, fp, off)
+    T.tred_effq(g, ph, sd, fp, off, val)
+    keys = torch.empty((bcap, 3), dtype=torch.int32, device="cuda")
+    na = torch.zeros(1, dtype=torch.int32, device="cuda")
+    vb = blk.blk_pix[0] * 10 * blk.blk_pix[1] * 10 * blk.blk_ticks
+    blocks = torch.empty((bcap, vb), dtype=torch.float32, device="cuda")
+    work = torch.empty(T.tred_block_bin_workspace(g, blk), dtype=torch.uint8, device="cuda")
+    T.tred_block_bin(g, blk, fp, off, val, keys, na, blocks, work)
+    torch.cuda.synchronize()
+    ofp, ooff, _ = orc.footprints(g, ph, seg)
+    oval, _ = orc.effq(g, ph, seg, ofp, ooff)
+    okeys = orc.block_keys(g, blk, ofp)
+    n = int(na.item())
+    assert n == len(okeys)
+    assert np.array_equal(keys[:n].cpu().numpy(), okeys)
+    rng = np.random.default_rng(0)
+    pick = rng.choice(n, size=min(40, n), replace=False)
+    got = blocks[torch.from_numpy(pick).cuda()].cpu().numpy()
+    ref = np.stack([orc.block_values(g, blk, ofp, ooff, oval, okeys[i]).ravel() for i in pick])
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 blocks {e:.2e}")
+    assert e < TOL
+
+
+def test_empty_and_outside_events(T, orc):
+    say("test_empty_and_outside_events")
+    g, ph, blk, kpix, kticks, fft, seg = small_cfg()
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=11)
+    # all segments beyond the readout window
+    far = seg.copy()
+    far[:, 2] += 100.0
+    far[:, 5] += 100.0
+    r = gpu_path(T, g, ph, blk, kpix, kticks, fft, far, resp)
+    assert r["n_active"] == 0 and r["n_pix"] == 0
+    assert (r["off"] == 0).all()
+    # no segments at all
+    r = gpu_path(T, g, ph, blk, kpix, kticks, fft, far[:0], resp)
+    assert r["n_active"] == 0 and r["n_pix"] == 0 and r["off"].tolist() == [0]
+
+
+def test_block_capacity_truncation(T, orc):
+    """With fewer block slots than active bins the count reports the full number and
+    only the first `cap` bins (in key order) are produced."""
+    say("test_block_capacity_truncation")
+    g, ph, blk, kpix, kticks, fft, seg = small_cfg(n=30, seed=9)
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=11)
+    o = oracle_path(orc, g, ph, blk, kpix, kticks, resp, seg)
+    cap = max(1, len(o["keys"]) // 2)
+    r = gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, block_cap=cap)
+    assert r["n_active"] == len(o["keys"])
+    assert np.array_equal(r["keys"], o["keys"][:cap])
+    pix = orc.pix_set(g, blk, kpix, o["keys"][:cap])
+    assert np.array_equal(r["pix"], pix)
+
+
+# ---------------------------------------------------------------------------
+# module-scale event at full size: exact integer outputs, sampled floating point
+# ---------------------------------------------------------------------------
+
+
+@pytest.fixture(scope="module")
+def module_run(T):
+    say("module-scale event (1e5 depositions, 256x256 pixels, 21x21x2048 response)")
+    cfg = W.cfg_module()
+    seg = W.gen_segments(cfg)
+    resp = W.synthetic_response(cfg.kpix, cfg.grid.sub, cfg.kticks)
+    r = gpu_path(T, cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, cfg.fft, seg, resp,
+                 mpcp=True, batch=64)
+    return cfg, seg, resp, r
+
+
+def test_module_integer_outputs_bitexact(module_run, orc):
+    say("test_module_integer_outputs_bitexact")
+    cfg, seg, resp, r = module_run
+    ofp, ooff, _ = orc.footprints(cfg.grid, cfg.physics, seg)
+    assert np.array_equal(r["fp"], ofp)
+    assert np.array_equal(r["off"], ooff)
+    okeys = orc.block_keys(cfg.grid, cfg.blocking, ofp)
+    assert r["n_active"] == len(okeys)
+    assert np.array_equal(r["keys"], okeys)
+    pix = orc.pix_set(cfg.grid, cfg.blocking, cfg.kpix, okeys)
+    assert np.array_equal(r["pix"], pix)
+    say(f"  active bins {len(okeys)} of {16 * 16 * 13}, pixels {len(pix)}")
+
+
+def test_module_sampled_patches(module_run, orc):
+    say("test_module_sampled_patches")
+    cfg, seg, resp, r = module_run
+    rng = np.random.default_rng(1)
+    pick = np.sort(rng.choice(seg.shape[0], 300, replace=False))
+    fp, off = r["fp"], r["off"]
+    got, ref = [], []
+    for d in pick:
+        pv, _ = orc.effq_patch(cfg.grid, cfg.physics, seg[d], fp[d])
+        ref.append(pv.ravel())
+        got.append(r["val"][off[d]:off[d + 1]])
+    e = rel_l2(np.concatenate(got), np.concatenate(ref))
+    say(f"  rel-L2 sampled patches {e:.2e}")
+    assert e < TOL
+
+
+def test_module_sampled_waveforms(module_run, orc):
+    """Waveform samples at the collection peak of pixels under sampled depositions."""
+    say("test_module_sampled_waveforms")
+    cfg, seg, resp, r = module_run
+    g = cfg.grid
+    rng = np.random.default_rng(2)
+    ofp, ooff, _ = orc.footprints(g, cfg.physics, seg)
+    pts = []
+    for d in rng.choice(seg.shape[0], 6, replace=False):
+        px = int(0.5 * (seg[d, 0] + seg[d, 3]) / W.PITCH)
+        py = int(0.5 * (seg[d, 1] + seg[d, 4]) / W.PITCH)
+        t0 = int(0.5 * (seg[d, 2] + seg[d, 5]) / cfg.physics.v_drift / W.TICK)
+        for dt in (int(0.9 * cfg.kticks) - 3, int(0.9 * cfg.kticks), int(0.5 * cfg.kticks)):
+            if 0 <= px < g.npix[0] and 0 <= py < g.npix[1] and t0 + dt < g.nticks + cfg.kticks - 1:
+                pts.append((px, py, t0 + dt))
+    pts = np.array(pts)
+    near = orc.select_near(ofp, g.sub, cfg.kpix, cfg.kticks, pts)
+    say(f"  {len(pts)} samples, {len(near)} contributing depositions")
+    sub_fp = ofp[near]
+    vol = np.prod(np.maximum(sub_fp[:, 3:] - sub_fp[:, :3] + 1, 0), axis=1)
+    sub_off = np.concatenate([[0], np.cumsum(vol)]).astype(np.int64)
+    sval, _ = orc.effq(g, cfg.physics, seg[near], sub_fp, sub_off)
+    ids = pts[:, 0] * g.npix[1] + pts[:, 1]
+    ref = orc.waveform_points(g, cfg.kpix, cfg.kticks, resp, sub_fp, sub_off, sval,
+                              np.stack([ids, pts[:, 2]], 1))
+    slot = np.searchsorted(r["pix"], ids)
+    assert (r["pix"][slot] == ids).all()
+    got = r["wf"][slot, pts[:, 2]]
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 sampled waveforms {e:.2e} (|ref| max {np.abs(ref).max():.3e})")
+    assert e < TOL
