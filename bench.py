@@ -1,0 +1,279 @@
+"""Benchmark: depositions/s of the whole hot path on one MI355X.
+
+A step is one pass of the path over one synthetic module-scale event (1e5 line
+depositions from muon-like tracks and shower blobs in a 256 x 256-pixel region,
+21 x 21 x 2048 field response, 16 x 16-pixel x 512-tick bins):
+
+  tred_effq_windows -> tred_effq -> tred_block_bin -> tred_block_conv -> tred_scatter_waveforms
+
+Inputs (depositions, response spectra) are resident in HBM before the timed region;
+the convolution plan is built once, untimed. Prints one JSON line.
+"""
+import argparse
+import ctypes as C
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector: 256 CU x 128 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
+
+
+class HipEvents:
+    """hipEvent_t handles through libamdhip64 (recorded on the launch stream)."""
+
+    def __init__(self, n):
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.ev = []
+        for _ in range(n):
+            e = C.c_void_p()
+            if self.hip.hipEventCreate(C.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.ev.append(e)
+
+    def record(self, i, stream):
+        self.hip.hipEventRecord(self.ev[i], stream)
+
+    def ms(self, a, b):
+        self.hip.hipEventSynchronize(self.ev[b])
+        out = C.c_float()
+        self.hip.hipEventElapsedTime(C.byref(out), self.ev[a], self.ev[b])
+        return float(out.value)
+
+    def handles(self, idx):
+        return [self.ev[i].value for i in idx]
+
+
+def fft_flops(n, nnz=None):
+    """5 n log2 n for an n-point complex FFT; with only nnz leading nonzero inputs the
+    first log2(n / nnz') stages (nnz' the next power of two) are copies and free."""
+    stages = int(round(math.log2(n)))
+    if nnz:
+        stages -= int(round(math.log2(n / (1 << int(math.ceil(math.log2(max(nnz, 1))))))))
+    return 5.0 * n * stages
+
+
+def conv_flops_per_block(blk, sub, kpix, kticks, fft, mpcp):
+    """Algorithmic FLOPs of the three convolution stages for one bin."""
+    Bx, By, Bt = blk
+    fs, ft = fft[0], fft[2]
+    nch = (sub[0] * sub[1] + 1) // 2 if mpcp else sub[0] * sub[1]
+    ct = ft - Bt
+    nc = -(-kticks // ct)
+    box, boy = Bx + kpix[0] - 1, By + kpix[1] - 1
+    tf = nch * Bx * By * fft_flops(ft, Bt)
+    per_f = nch * (By * fft_flops(fs, Bx) + fs * fft_flops(fs, By) + nc * fs * fs * 8) + \
+        nc * (fs * fft_flops(fs) + boy * fft_flops(fs))
+    sp = ft * per_f
+    ti = nc * box * boy * fft_flops(ft)
+    return dict(tf=tf, sp=sp, ti=ti, total=tf + sp + ti)
+
+
+def src_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profile_traffic(kernel_key, sha):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel_key)
+        if not e or e.get("source_sha") != sha:
+            return None
+        return float(e["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(cfg, seg, resp, n_sample, seed=0):
+    """The FP64 oracle (effective charge, binning, direct convolution) on a random
+    sample of the event's depositions, timed on the host cores."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(seg.shape[0], n_sample, replace=False))
+    sub = seg[pick]
+    t = time.perf_counter()
+    oracle.simulate(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, resp, sub)
+    dt = time.perf_counter() - t
+    return dict(value=n_sample / dt, unit="depositions/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{n_sample} random depositions of the same event (seed {seed}), whole path "
+                       f"(effective charge, binning, direct convolution, waveforms): {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=40)
+    ap.add_argument("--plain", action="store_true", help="complex-of-real packing instead of MPCP")
+    ap.add_argument("--scratch-gb", type=float, default=100.0,
+                    help="bound on the convolution scratch (sets the bins per pass)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path is "
+              f"single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_probe:
+        n = 1 << 30
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
+
+    import workloads as W
+    from paper_2602_12052_amd import tred
+
+    cfg = W.cfg_module(args.seed)
+    seg = W.gen_segments(cfg)
+    resp = W.synthetic_response(cfg.kpix, cfg.grid.sub, cfg.kticks)
+    dev_seg = torch.from_numpy(seg).cuda()
+    dev_resp = torch.from_numpy(resp).cuda()
+    mpcp = not args.plain
+    val_cap, block_cap, pix_cap = tred.size_event(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix,
+                                                  dev_seg)
+    Bx, By = cfg.blocking.blk_pix
+    Bt = cfg.blocking.blk_ticks
+    fs, ft = cfg.fft[0], cfg.fft[2]
+    nch = 50 if mpcp else 100
+    nc = -(-cfg.kticks // (ft - Bt))
+    box, boy = Bx + cfg.kpix[0] - 1, By + cfg.kpix[1] - 1
+    per_block_scratch = (nch * Bx * By + nc * box * boy) * ft * 8
+    batch = max(1, min(block_cap, int(args.scratch_gb * 1e9 // per_block_scratch)))
+    pl = tred.Pipeline(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, dev_resp,
+                       seg.shape[0], val_cap, block_cap, pix_cap, cfg.fft, mpcp, batch)
+    stream = torch.cuda.current_stream().cuda_stream
+    ev = HipEvents(12)
+    pl.plan.set_timing(ev.handles(range(6, 12)))
+    print(f"# module event: {seg.shape[0]} depositions, {block_cap} active bins of "
+          f"{tred.tred_block_count(cfg.grid, cfg.blocking)}, patch cells {val_cap}, "
+          f"bins per conv pass {batch}", file=sys.stderr, flush=True)
+
+    def step(record=False):
+        if record:
+            ev.record(0, stream)
+        tred.tred_effq_windows(pl.grid, pl.phys, dev_seg, pl.fp, pl.off, stream)
+        pl.charge_sum.zero_()
+        tred.tred_effq(pl.grid, pl.phys, dev_seg, pl.fp, pl.off, pl.val, pl.charge_sum, stream)
+        if record:
+            ev.record(1, stream)
+        tred.tred_block_bin(pl.grid, pl.blocking, pl.fp, pl.off, pl.val, pl.keys, pl.n_active,
+                            pl.blocks, pl.bin_work, stream)
+        if record:
+            ev.record(2, stream)
+        tred.tred_block_conv(pl.plan, pl.n_active, pl.blocks, pl.out_blocks, stream)
+        if record:
+            ev.record(3, stream)
+        tred.tred_scatter_waveforms(pl.plan, pl.keys, pl.n_active, pl.out_blocks, pl.pix,
+                                    pl.n_pix, pl.wf, pl.scat_work, stream)
+        if record:
+            ev.record(4, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    per_step, stages, conv_stages = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(record=True)
+        per_step.append(ev.ms(0, 4))
+        stages.append([ev.ms(0, 1), ev.ms(1, 2), ev.ms(2, 3), ev.ms(3, 4)])
+        conv_stages.append([ev.ms(6, 7), ev.ms(8, 9), ev.ms(10, 11)])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    n_dep = seg.shape[0]
+    n_act = int(pl.n_active.item())
+    n_pix = int(pl.n_pix.item())
+    ms_per_step = 1e3 * wall / args.steps
+    value = n_dep / (wall / args.steps)
+    stages = np.array(stages)
+    conv_stages = np.array(conv_stages)
+
+    fl = conv_flops_per_block((Bx, By, Bt), cfg.grid.sub, cfg.kpix, cfg.kticks, cfg.fft, mpcp)
+    sp_blocks = min(batch, n_act)
+    sp_ms = float(conv_stages[:, 1].mean())
+    achieved = fl["sp"] * sp_blocks / (sp_ms * 1e-3) / 1e12
+    sha = src_sha(["paper_2602_12052_amd/csrc/conv.hip", "paper_2602_12052_amd/csrc/tred_internal.hpp"])
+    traffic = profile_traffic("k_sp", sha)
+    vblk = Bx * cfg.grid.sub[0] * By * cfg.grid.sub[1] * Bt
+    vout = box * boy * (Bt + cfg.kticks - 1)
+    lwf = cfg.grid.nticks + cfg.kticks - 1
+    b_alg = 28 * n_dep + 4 * resp.size + 8 * n_act * vblk + 8 * n_act * vout + 4 * n_pix * lwf
+
+    out = {
+        "metric": "depositions/s (effq+block FFT conv) and % HBM roofline; rel-L2 vs FP64 oracle",
+        "value": value,
+        "unit": "depositions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "module-scale event: 1e5 line depositions (40 tracks at 0.5 mm steps + "
+                        "20 shower blobs), 256x256 pixels x 6250 ticks, 10x10 impacts/pixel, "
+                        "response 21x21 px x 2048 ticks, bins 16x16 px x 512 ticks",
+            "n_dep": n_dep, "active_bins": n_act, "bins_total": 16 * 16 * 13,
+            "active_fraction": n_act / (16 * 16 * 13), "pixels": n_pix,
+            "fft": list(cfg.fft), "response_pieces": nc,
+            "packing": "mirror-pair" if mpcp else "complex-of-real", "bins_per_conv_pass": batch,
+        },
+        "step_ms": {"p50": float(np.median(per_step)), "p99": float(np.percentile(per_step, 99))},
+        "stage_ms": {"effq_windows+effq": float(stages[:, 0].mean()), "block_bin": float(stages[:, 1].mean()),
+                     "block_conv": float(stages[:, 2].mean()), "scatter": float(stages[:, 3].mean()),
+                     "conv_time_fwd": float(conv_stages[:, 0].mean()),
+                     "conv_space_mac": float(conv_stages[:, 1].mean()),
+                     "conv_time_inv": float(conv_stages[:, 2].mean())},
+        "roofline": {
+            "kernel": "k_sp (spatial transforms + spectral multiply-accumulate)",
+            "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
+            "flops_per_launch": fl["sp"] * sp_blocks, "avg_launch_ms": sp_ms,
+        },
+        "hbm": {"algorithmic_bytes_per_step": b_alg,
+                "frac_of_peak_per_step": b_alg / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)},
+        "charge_sum_fp64": float(pl.charge_sum.item()),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, seg, resp, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -188,6 +188,14 @@ tred_status tred_conv_plan_set_response(tred_conv_plan* plan, const float* resp,
  * number of transformed channels, output block extent out[3]. Any pointer may be NULL. */
 tred_status tred_conv_plan_info(const tred_conv_plan* plan, int32_t fft[3], int32_t* pieces,
                                 int32_t* channels, int32_t out[3]);
+/* Optional stage timing (profiling aid, not part of the computation): events points
+ * to six hipEvent_t created by the caller; tred_block_conv then records events[2s]
+ * and events[2s+1] on its stream before and after the launches of stage s in its
+ * first pass over the bins (s = 0: time-axis forward transforms; 1: spatial
+ * transforms and spectral multiply-accumulate; 2: time-axis inverse transforms and
+ * overlap-add of the response pieces). With batch >= cap each stage is one launch.
+ * events = NULL switches timing off. */
+tred_status tred_conv_plan_set_timing(tred_conv_plan* plan, void* const* events);
 /* out_blocks [cap][blk_pix[0]+kpix[0]-1][blk_pix[1]+kpix[1]-1][blk_ticks+kticks-1]. */
 tred_status tred_block_conv(const tred_conv_plan* plan, const int32_t* n_active, int32_t cap,
                             const float* blocks, float* out_blocks, void* stream);

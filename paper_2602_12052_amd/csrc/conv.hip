@@ -216,9 +216,12 @@ __global__ __launch_bounds__(256) void k_sp(ConvArgs A, int b0, const int32_t* _
                                             float2* __restrict__ U) {
     constexpr int RS = FS / L, TPF = FS * RS, NF = 256 / TPF;
     extern __shared__ float2 sm[];
-    const int bl = blockIdx.y, b = b0 + bl;
+    // bins vary fastest across the grid: the workgroups running at one time share the
+    // frequency slab of the response spectra, which then comes from L2 / the last-level
+    // cache instead of being streamed from HBM once per bin
+    const int bl = blockIdx.x, b = b0 + bl;
     if (b >= min(*n_active, A.cap)) return;
-    const int f0 = blockIdx.x * NF;
+    const int f0 = blockIdx.y * NF;
     const int tid = threadIdx.x, fl = tid / TPF, item = tid % TPF;
     const int kx = item / RS, ry = item % RS;
     const int By = A.By, Bx = A.Bx, CHX = A.chx, ppad = A.ppad, box = A.box, boy = A.boy;
@@ -525,7 +528,7 @@ tred_status launch_space(const ConvArgs& A, int b0, int nb, const int32_t* na, c
     constexpr int RS = FS / L, NF = 256 / (FS * RS);
     const size_t lds = (size_t)(FS + A.ldsA + A.ldsB) * sizeof(float2);
     allow_lds(k_sp<FS, L>, lds);
-    hipLaunchKernelGGL((k_sp<FS, L>), dim3(A.ft / NF, nb), dim3(256), lds, st, A, b0, na, T, rhat,
+    hipLaunchKernelGGL((k_sp<FS, L>), dim3(nb, A.ft / NF), dim3(256), lds, st, A, b0, na, T, rhat,
                        tws, U);
     return tred_check_launch("tred_block_conv space");
 }
@@ -706,11 +709,17 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
     const float2* rhat = (const float2*)(ws + P->off_rhat);
     float2* T = (float2*)(ws + P->off_scratch_t);
     float2* U = (float2*)(ws + P->off_scratch_u);
+    auto mark = [&](int b0, int k) {
+        if (P->timing && b0 == 0) (void)hipEventRecord(P->ev[k], st);
+    };
     for (int b0 = 0; b0 < cap; b0 += P->batch) {
         const int nb = std::min(P->batch, cap - b0);
+        mark(b0, 0);
         TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
             return launch_time_fwd<decltype(ftc)::value>(A, b0, nb, n_active, blocks, twt, T, st);
         }));
+        mark(b0, 1);
+        mark(b0, 2);
         tred_status s;
         switch (P->fs) {
             case 8: s = launch_space<8, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
@@ -719,10 +728,27 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
             default: s = launch_space<64, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
         }
         TRED_TRY(s);
+        mark(b0, 3);
+        mark(b0, 4);
         TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
             return launch_time_inv<decltype(ftc)::value>(A, b0, nb, n_active, U, twt, out_blocks, st);
         }));
+        mark(b0, 5);
     }
+    return TRED_OK;
+}
+
+extern "C" tred_status tred_conv_plan_set_timing(tred_conv_plan* P, void* const* events) {
+    TRED_REQUIRE(P != nullptr, "plan is NULL");
+    if (!events) {
+        P->timing = 0;
+        return TRED_OK;
+    }
+    for (int k = 0; k < 6; ++k) {
+        TRED_REQUIRE(events[k] != nullptr, "events[%d] is NULL", k);
+        P->ev[k] = (hipEvent_t)events[k];
+    }
+    P->timing = 1;
     return TRED_OK;
 }
 

@@ -239,6 +239,8 @@ struct tred_conv_plan {
     int64_t ws_bytes;
     void* ws;            // bound by set_response
     int ready;
+    hipEvent_t ev[6];    // optional stage timing
+    int timing;
 };
 
 constexpr int kTile = 8;   // pixels per interleaved tile of the spectral scratch

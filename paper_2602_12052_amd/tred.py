@@ -63,7 +63,8 @@ def blocking_struct(b) -> Blocking:
 EXPORTS = [
     "tred_status_string", "tred_last_error", "tred_abi_version", "tred_effq_windows", "tred_effq",
     "tred_block_count", "tred_block_bin_workspace", "tred_block_bin", "tred_conv_plan_create",
-    "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_block_conv",
+    "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
+    "tred_block_conv",
     "tred_scatter_workspace", "tred_scatter_waveforms", "tred_conv_plan_destroy",
 ]
 
@@ -94,6 +95,7 @@ def lib():
                                         C.POINTER(C.c_int64)]
     L.tred_conv_plan_set_response.argtypes = [P, P, P, P]
     L.tred_conv_plan_info.argtypes = [P, P, P, P, P]
+    L.tred_conv_plan_set_timing.argtypes = [P, P]
     L.tred_block_conv.argtypes = [P, P, I32, P, P, P]
     L.tred_scatter_workspace.argtypes = [P]
     L.tred_scatter_workspace.restype = I64
@@ -101,7 +103,8 @@ def lib():
     L.tred_conv_plan_destroy.argtypes = [P]
     L.tred_conv_plan_destroy.restype = None
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
-                 "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_block_conv",
+                 "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
+    "tred_block_conv",
                  "tred_scatter_waveforms"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -220,6 +223,14 @@ class ConvPlan:
         _dt(resp, torch.float32, "resp")
         _check(lib().tred_conv_plan_set_response(self.handle, _ptr(resp), self._ws_ptr(),
                                                  _stream(stream)))
+
+    def set_timing(self, events):
+        """events: six hipEvent_t handles (ints) or None."""
+        if events is None:
+            _check(lib().tred_conv_plan_set_timing(self.handle, None))
+        else:
+            arr = (C.c_void_p * 6)(*events)
+            _check(lib().tred_conv_plan_set_timing(self.handle, arr))
 
     def __del__(self):
         try:
