@@ -14,6 +14,7 @@
 // tick offset c * ct.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 
 #include "tred_internal.hpp"
@@ -26,7 +27,6 @@ struct ConvArgs {
     int32_t nch, nc, ct, ft, fs;
     int32_t ppad, qpad, box, boy, bot;
     int32_t mpcp, chx, cap;
-    int32_t ldsA, ldsB;       // k_sp LDS region sizes (float2)
     int64_t vblk, vout;
 };
 
@@ -205,32 +205,67 @@ __global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* _
 // is split as k = r + RS m (RS = fs / L): for each r an L-point DFT of the inputs
 // twiddled by exp(-2 pi i n r / fs). Its inverse with pruned outputs runs the same
 // split backwards (L-point inverse DFTs, then an RS-point combination).
-// One workgroup of 256 threads handles NF = 256 / (fs RS) consecutive frequencies;
-// thread (fl, kx, ry) owns the spectrum column kx, ky = ry + RS m of frequency f0+fl.
+// A workgroup handles NB bins at NF = 256 / (fs RS) consecutive frequencies; lanes
+// are interleaved by bin, so neighbouring lanes hold the same spectrum column of
+// different bins and one load of the response spectra serves all NB bins.
+// Thread (fl, kx, ry, bin) owns column kx, ky = ry + RS m of frequency f0 + fl.
+// LDS rows that lanes index with a stride use odd padded strides (bank conflicts).
 // ---------------------------------------------------------------------------
-template <int FS, int L>
-__global__ __launch_bounds__(256) void k_sp(ConvArgs A, int b0, const int32_t* __restrict__ n_active,
-                                            const float2* __restrict__ T,
-                                            const float2* __restrict__ rhat,
-                                            const float2* __restrict__ tws,
-                                            float2* __restrict__ U) {
-    constexpr int RS = FS / L, TPF = FS * RS, NF = 256 / TPF;
+struct SpLds {
+    int P1, GL, YB;          // padded strides: abuf row (By), inverse rows (L), y rows (boy)
+    int zsz, asz, fwd, gsz, g2sz, ysz, y2sz, A, B, per_bin;
+};
+
+__host__ __device__ inline SpLds sp_lds(int FS, int L, int NF, int CHX, int By, int ppad, int box,
+                                        int boy) {
+    SpLds s;
+    const int RS = FS / L;
+    s.P1 = (By % 2 == 0) ? By + 1 : By;
+    s.GL = L + 1;
+    s.YB = (boy % 2 == 0) ? boy + 1 : boy;
+    s.zsz = CHX * NF * ppad;
+    s.asz = CHX * NF * FS * s.P1;
+    s.fwd = s.zsz + s.asz;
+    s.gsz = NF * FS * RS * s.GL;
+    s.g2sz = NF * boy * RS * s.GL;
+    s.ysz = NF * FS * s.YB;
+    s.y2sz = NF * box * s.YB;
+    s.A = s.fwd > s.gsz ? (s.fwd > s.g2sz ? s.fwd : s.g2sz) : (s.gsz > s.g2sz ? s.gsz : s.g2sz);
+    s.B = s.ysz > s.y2sz ? s.ysz : s.y2sz;
+    s.per_bin = s.A + s.B;
+    return s;
+}
+
+template <int FS, int L, int NB>
+__global__ __launch_bounds__(256 * NB) void k_sp(ConvArgs A, int b0, int nbp,
+                                                 const int32_t* __restrict__ n_active,
+                                                 const float2* __restrict__ T,
+                                                 const float2* __restrict__ rhat,
+                                                 const float2* __restrict__ tws,
+                                                 float2* __restrict__ U) {
+    constexpr int RS = FS / L, TPF = FS * RS, NF = 256 / TPF, NT = 256 * NB;
     extern __shared__ float2 sm[];
     // bins vary fastest across the grid: the workgroups running at one time share the
     // frequency slab of the response spectra, which then comes from L2 / the last-level
-    // cache instead of being streamed from HBM once per bin
-    const int bl = blockIdx.x, b = b0 + bl;
-    if (b >= min(*n_active, A.cap)) return;
+    // cache instead of being streamed from HBM once per bin.
+    // Bins of this pass: local index bl < nbp (scratch slots), global b0 + bl < n_active.
+    const int na = min(*n_active, A.cap);
+    const int nvalid = min(nbp, na - b0);
+    if ((int)blockIdx.x * NB >= nvalid) return;
     const int f0 = blockIdx.y * NF;
-    const int tid = threadIdx.x, fl = tid / TPF, item = tid % TPF;
+    const int tid = threadIdx.x;
+    const int me = tid % NB;
+    const int t2 = tid / NB;
+    const int fl = t2 / TPF, item = t2 % TPF;
     const int kx = item / RS, ry = item % RS;
     const int By = A.By, Bx = A.Bx, CHX = A.chx, ppad = A.ppad, box = A.box, boy = A.boy;
     const int ptiles = ppad / kTile;
-    float2* twl = sm;                 // exp(-2 pi i k / fs)
-    float2* regA = sm + FS;
-    float2* regB = regA + A.ldsA;
-    float2* zbuf = regA;                              // [CHX][NF][ppad]
-    float2* abuf = regA + CHX * NF * ppad;            // [CHX][NF][FS][By]
+    const int blocal0 = blockIdx.x * NB;
+    const SpLds Ls = sp_lds(FS, L, NF, CHX, By, ppad, box, boy);
+    const int P1 = Ls.P1, GL = Ls.GL, YB = Ls.YB;
+    float2* twl = sm;                        // exp(-2 pi i k / fs)
+    auto regA = [&](int bs) { return sm + FS + bs * Ls.per_bin; };
+    auto regB = [&](int bs) { return sm + FS + bs * Ls.per_bin + Ls.A; };
     if (tid < FS) twl[tid] = tws[tid];
 
     float2 acc[4][L];
@@ -241,53 +276,59 @@ __global__ __launch_bounds__(256) void k_sp(ConvArgs A, int b0, const int32_t* _
     __syncthreads();
 
     for (int j0 = 0; j0 < A.nch; j0 += CHX) {
-        // stage the time spectra of CHX channels at frequencies f0 .. f0+NF-1
-        const int nld = CHX * ptiles * NF * kTile;
-        for (int i = tid; i < nld; i += 256) {
+        // stage the time spectra: zbuf[bin][cx][fl][p]
+        const int nld = NB * CHX * ptiles * NF * kTile;
+        for (int i = tid; i < nld; i += NT) {
             const int pi = i % kTile;
             int r = i / kTile;
             const int fl2 = r % NF;
             r /= NF;
             const int pt = r % ptiles;
-            const int cx = r / ptiles;
+            r /= ptiles;
+            const int cx = r % CHX;
+            const int bs = r / CHX;
             const int ch = j0 + cx;
+            const int bl = blocal0 + bs;
             float2 z = make_float2(0.f, 0.f);
-            if (ch < A.nch)
+            if (ch < A.nch && bl < nvalid)
                 z = T[((((int64_t)bl * A.nch + ch) * ptiles + pt) * A.ft + f0 + fl2) * kTile + pi];
-            zbuf[(cx * NF + fl2) * ppad + pt * kTile + pi] = z;
+            regA(bs)[(cx * NF + fl2) * ppad + pt * kTile + pi] = z;
         }
         __syncthreads();
-        // x pass: for each (channel, frequency, py, rx): L-point DFT over px
-        const int nx = CHX * NF * By * RS;
-        for (int i = tid; i < nx; i += 256) {
-            const int rx = i % RS;
-            int r = i / RS;
+        // x pass: for each (bin, channel, frequency, py, rx): L-point DFT over px,
+        // abuf[bin][cx][fl][kx][py] with row stride P1
+        const int nx = CHX * NF * By * RS * NB;
+        for (int i = tid; i < nx; i += NT) {
+            const int bs = i % NB;
+            int r = i / NB;
+            const int rx = r % RS;
+            r /= RS;
             const int py = r % By;
             r /= By;
             const int fl2 = r % NF;
             const int cx = r / NF;
-            const float2* zr = zbuf + (cx * NF + fl2) * ppad;
+            const float2* zr = regA(bs) + (cx * NF + fl2) * ppad;
             float2 s[L];
 #pragma unroll
             for (int n = 0; n < L; ++n)
                 s[n] = n < Bx ? cmul(zr[n * By + py], twl[(n * rx) % FS]) : make_float2(0.f, 0.f);
             Dft<L>::run(s);
-            float2* ar = abuf + ((cx * NF + fl2) * FS) * By + py;
+            float2* ar = regA(bs) + Ls.zsz + (cx * NF + fl2) * FS * P1 + py;
 #pragma unroll
-            for (int m = 0; m < L; ++m) ar[(rx + RS * m) * By] = s[m];
+            for (int m = 0; m < L; ++m) ar[(rx + RS * m) * P1] = s[m];
         }
         __syncthreads();
         // y pass and multiply-accumulate, one channel at a time
         for (int cx = 0; cx < CHX; ++cx) {
             const int ch = j0 + cx;
             if (ch >= A.nch) break;
-            const float2* ar = abuf + ((cx * NF + fl) * FS + kx) * By;
+            const float2* ar = regA(me) + Ls.zsz + ((cx * NF + fl) * FS + kx) * P1;
             float2 s[L];
 #pragma unroll
             for (int n = 0; n < L; ++n)
                 s[n] = n < By ? cmul(ar[n], twl[(n * ry) % FS]) : make_float2(0.f, 0.f);
             Dft<L>::run(s);
-            const float2* rh = rhat + ((int64_t)ch * A.nc * L * A.ft + f0) * TPF + tid;
+            const float2* rh = rhat + ((int64_t)ch * A.nc * L * A.ft + f0 + fl) * TPF + item;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 if (c < A.nc) {
@@ -308,27 +349,30 @@ __global__ __launch_bounds__(256) void k_sp(ConvArgs A, int b0, const int32_t* _
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         if (c >= A.nc) break;
-        float2* gbuf = regA;    // [NF][FS][RS][L]
-        float2* ybuf = regB;    // [NF][FS][boy]
         {
+            // gbuf[bin][fl][kx][ry][n0]
             float2 s[L];
 #pragma unroll
             for (int m = 0; m < L; ++m) s[m] = cconj(acc[c][m]);
             Dft<L>::run(s);
-            float2* gr = gbuf + ((fl * FS + kx) * RS + ry) * L;
+            float2* gr = regA(me) + ((fl * FS + kx) * RS + ry) * GL;
 #pragma unroll
             for (int n0 = 0; n0 < L; ++n0) gr[n0] = cmulc(cconj(s[n0]), twl[(n0 * ry) % FS]);
         }
         __syncthreads();
-        // combine over ry -> y-inverse at qy = n0 + L n1 < boy
-        for (int i = tid; i < NF * FS * L; i += 256) {
+        // combine over ry -> y-inverse at qy = n0 + L n1 < boy: ybuf[bin][fl][kx][qy]
+        for (int i = tid; i < NF * FS * L * NB; i += NT) {
             const int n0 = i % L;
             int r = i / L;
+            const int bs = r % NB;
+            r /= NB;
             const int kx2 = r % FS;
             const int fl2 = r / FS;
+            const float2* gr = regA(bs) + ((fl2 * FS + kx2) * RS) * GL + n0;
             float2 col[RS];
 #pragma unroll
-            for (int rr = 0; rr < RS; ++rr) col[rr] = gbuf[((fl2 * FS + kx2) * RS + rr) * L + n0];
+            for (int rr = 0; rr < RS; ++rr) col[rr] = gr[rr * GL];
+            float2* yr = regB(bs) + (fl2 * FS + kx2) * YB;
 #pragma unroll
             for (int n1 = 0; n1 < RS; ++n1) {
                 const int qy = n0 + L * n1;
@@ -336,36 +380,42 @@ __global__ __launch_bounds__(256) void k_sp(ConvArgs A, int b0, const int32_t* _
                     float2 y = col[0];
 #pragma unroll
                     for (int rr = 1; rr < RS; ++rr) y = cadd(y, cmulc(col[rr], twl[(n1 * rr * L) % FS]));
-                    ybuf[(fl2 * FS + kx2) * boy + qy] = y;
+                    yr[qy] = y;
                 }
             }
         }
         __syncthreads();
-        // x-inverse: L-point inverse DFTs over kx = rx + RS m
-        float2* g2 = regA;      // [NF][boy][RS][L]
-        for (int i = tid; i < NF * boy * RS; i += 256) {
-            const int rx = i % RS;
-            int r = i / RS;
+        // x-inverse: L-point inverse DFTs over kx = rx + RS m: g2[bin][fl][qy][rx][n0]
+        for (int i = tid; i < NF * boy * RS * NB; i += NT) {
+            const int bs = i % NB;
+            int r = i / NB;
+            const int rx = r % RS;
+            r /= RS;
             const int qy = r % boy;
             const int fl2 = r / boy;
+            const float2* yr = regB(bs) + (fl2 * FS + rx) * YB + qy;
             float2 s[L];
 #pragma unroll
-            for (int m = 0; m < L; ++m) s[m] = cconj(ybuf[(fl2 * FS + rx + RS * m) * boy + qy]);
+            for (int m = 0; m < L; ++m) s[m] = cconj(yr[RS * m * YB]);
             Dft<L>::run(s);
-            float2* gr = g2 + ((fl2 * boy + qy) * RS + rx) * L;
+            float2* gr = regA(bs) + ((fl2 * boy + qy) * RS + rx) * GL;
 #pragma unroll
             for (int n0 = 0; n0 < L; ++n0) gr[n0] = cmulc(cconj(s[n0]), twl[(n0 * rx) % FS]);
         }
         __syncthreads();
-        float2* y2 = regB;      // [NF][box][boy]
-        for (int i = tid; i < NF * boy * L; i += 256) {
+        // combine over rx -> y2[bin][fl][qx][qy]
+        for (int i = tid; i < NF * boy * L * NB; i += NT) {
             const int n0 = i % L;
             int r = i / L;
+            const int bs = r % NB;
+            r /= NB;
             const int qy = r % boy;
             const int fl2 = r / boy;
+            const float2* gr = regA(bs) + ((fl2 * boy + qy) * RS) * GL + n0;
             float2 col[RS];
 #pragma unroll
-            for (int rr = 0; rr < RS; ++rr) col[rr] = g2[((fl2 * boy + qy) * RS + rr) * L + n0];
+            for (int rr = 0; rr < RS; ++rr) col[rr] = gr[rr * GL];
+            float2* yr = regB(bs) + fl2 * box * YB + qy;
 #pragma unroll
             for (int n1 = 0; n1 < RS; ++n1) {
                 const int qx = n0 + L * n1;
@@ -373,7 +423,7 @@ __global__ __launch_bounds__(256) void k_sp(ConvArgs A, int b0, const int32_t* _
                     float2 y = col[0];
 #pragma unroll
                     for (int rr = 1; rr < RS; ++rr) y = cadd(y, cmulc(col[rr], twl[(n1 * rr * L) % FS]));
-                    y2[(fl2 * box + qx) * boy + qy] = y;
+                    yr[qx * YB] = y;
                 }
             }
         }
@@ -381,18 +431,23 @@ __global__ __launch_bounds__(256) void k_sp(ConvArgs A, int b0, const int32_t* _
         // I[q] = Re Y[q] + Im Y[q'] with q' the point reflection within the block output
         // (Re Y(t) + Im Y'(t) = Re(Y(t) - i Y'(t)), taken after the inverse time FFT)
         const int nq = box * boy;
-        for (int i = tid; i < qtiles * NF * kTile; i += 256) {
+        for (int i = tid; i < NB * qtiles * NF * kTile; i += NT) {
             const int qi = i % kTile;
             int r = i / kTile;
             const int fl2 = r % NF;
-            const int qt = r / NF;
+            r /= NF;
+            const int qt = r % qtiles;
+            const int bs = r / qtiles;
+            const int bl = blocal0 + bs;
+            if (bl >= nvalid) continue;
             const int q = qt * kTile + qi;
             float2 vq = make_float2(0.f, 0.f);
             if (q < nq) {
                 const int qx = q / boy, qy = q % boy;
-                vq = y2[(fl2 * box + qx) * boy + qy];
+                const float2* y2 = regB(bs) + fl2 * box * YB;
+                vq = y2[qx * YB + qy];
                 if (A.mpcp) {
-                    const float2 yb = y2[(fl2 * box + (box - 1 - qx)) * boy + (boy - 1 - qy)];
+                    const float2 yb = y2[(box - 1 - qx) * YB + (boy - 1 - qy)];
                     vq = make_float2(vq.x + yb.y, vq.y - yb.x);
                 }
             }
@@ -484,11 +539,7 @@ ConvArgs make_args(const tred_conv_plan* P) {
     const int L = std::min(A.fs, 16);
     const int RS = A.fs / L;
     const int NF = 256 / (A.fs * RS);
-    const int64_t fwd = (int64_t)A.chx * NF * A.ppad + (int64_t)A.chx * NF * A.fs * A.By;
-    const int64_t g1 = (int64_t)NF * A.fs * A.fs;
-    const int64_t g2 = (int64_t)NF * A.boy * A.fs;
-    A.ldsA = (int32_t)std::max(fwd, std::max(g1, g2));
-    A.ldsB = (int32_t)std::max((int64_t)NF * A.fs * A.boy, (int64_t)NF * A.box * A.boy);
+    (void)NF;
     A.vblk = (int64_t)A.Bx * A.sx * A.NYf * A.Bt;
     A.vout = (int64_t)A.box * A.boy * A.bot;
     return A;
@@ -522,15 +573,25 @@ tred_status launch_time_inv(const ConvArgs& A, int b0, int nb, const int32_t* na
     return tred_check_launch("tred_block_conv time inverse");
 }
 
-template <int FS, int L>
-tred_status launch_space(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
-                         const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
+template <int FS, int L, int NB>
+tred_status launch_space_nb(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
+                            const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
     constexpr int RS = FS / L, NF = 256 / (FS * RS);
-    const size_t lds = (size_t)(FS + A.ldsA + A.ldsB) * sizeof(float2);
-    allow_lds(k_sp<FS, L>, lds);
-    hipLaunchKernelGGL((k_sp<FS, L>), dim3(nb, A.ft / NF), dim3(256), lds, st, A, b0, na, T, rhat,
-                       tws, U);
+    const SpLds Ls = sp_lds(FS, L, NF, A.chx, A.By, A.ppad, A.box, A.boy);
+    const size_t lds = (size_t)(FS + NB * Ls.per_bin) * sizeof(float2);
+    if (lds > 160 * 1024) return tred_fail(TRED_EUNSUPPORTED, "spatial stage needs %zu B of LDS", lds);
+    allow_lds(k_sp<FS, L, NB>, lds);
+    hipLaunchKernelGGL((k_sp<FS, L, NB>), dim3((nb + NB - 1) / NB, A.ft / NF), dim3(256 * NB), lds,
+                       st, A, b0, nb, na, T, rhat, tws, U);
     return tred_check_launch("tred_block_conv space");
+}
+
+template <int FS, int L>
+tred_status launch_space(const ConvArgs& A, int nbins_wg, int b0, int nb, const int32_t* na,
+                         const float2* T, const float2* rhat, const float2* tws, float2* U,
+                         hipStream_t st) {
+    if (nbins_wg == 2) return launch_space_nb<FS, L, 2>(A, b0, nb, na, T, rhat, tws, U, st);
+    return launch_space_nb<FS, L, 1>(A, b0, nb, na, T, rhat, tws, U, st);
 }
 
 template <typename F>
@@ -567,6 +628,9 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     P->kticks = kticks;
     P->mpcp = (flags & TRED_CONV_MPCP) ? 1 : 0;
     P->batch = batch;
+    // bins per workgroup of the spatial stage (1 or 2); a tuning knob
+    P->sp_bins = 1;
+    if (const char* e = getenv("TRED_SP_BINS")) P->sp_bins = atoi(e) == 2 ? 2 : 1;
     const int Bx = blocking->blk_pix[0], By = blocking->blk_pix[1], Bt = blocking->blk_ticks;
     P->bo[0] = Bx + kpix[0] - 1;
     P->bo[1] = By + kpix[1] - 1;
@@ -721,11 +785,12 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
         mark(b0, 1);
         mark(b0, 2);
         tred_status s;
+        const int nbw = P->sp_bins;
         switch (P->fs) {
-            case 8: s = launch_space<8, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 16: s = launch_space<16, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 32: s = launch_space<32, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            default: s = launch_space<64, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 8: s = launch_space<8, 8>(A, nbw, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 16: s = launch_space<16, 16>(A, nbw, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 32: s = launch_space<32, 16>(A, nbw, b0, nb, n_active, T, rhat, tws, U, st); break;
+            default: s = launch_space<64, 16>(A, nbw, b0, nb, n_active, T, rhat, tws, U, st); break;
         }
         TRED_TRY(s);
         mark(b0, 3);

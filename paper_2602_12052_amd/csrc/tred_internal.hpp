@@ -232,6 +232,7 @@ struct tred_conv_plan {
     int32_t nch;         // transformed channels (pairs under MPCP)
     int32_t mpcp;
     int32_t batch;
+    int32_t sp_bins;     // bins per workgroup in the spatial stage
     int32_t bo[3];       // output block extent
     int32_t qpad;        // output pixels per block padded to the tile of 8
     // workspace layout (byte offsets)
