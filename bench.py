@@ -57,11 +57,12 @@ class HipEvents:
 
 
 def fft_flops(n, nnz=None):
-    """5 n log2 n for an n-point complex FFT; with only nnz leading nonzero inputs the
-    first log2(n / nnz') stages (nnz' the next power of two) are copies and free."""
-    stages = int(round(math.log2(n)))
-    if nnz:
-        stages -= int(round(math.log2(n / (1 << int(math.ceil(math.log2(max(nnz, 1))))))))
+    """5 n log2 n for an n-point complex FFT. For a power-of-two n with only nnz
+    leading nonzero inputs the first log2(n / nnz') stages (nnz' the next power of
+    two) are copies and free; other sizes get no pruning credit."""
+    stages = math.log2(n)
+    if nnz and n & (n - 1) == 0:
+        stages -= math.log2(n / (1 << int(math.ceil(math.log2(max(nnz, 1))))))
     return 5.0 * n * stages
 
 

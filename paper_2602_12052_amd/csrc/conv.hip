@@ -201,19 +201,18 @@ __global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* _
 
 // ---------------------------------------------------------------------------
 // k_sp: spatial transforms and the spectral multiply-accumulate, per time frequency.
-// The fs-point transform along an axis with at most L = min(fs, 16) nonzero inputs
-// is split as k = r + RS m (RS = fs / L): for each r an L-point DFT of the inputs
-// twiddled by exp(-2 pi i n r / fs). Its inverse with pruned outputs runs the same
+// The fs-point transform along an axis with at most B <= 2L nonzero inputs
+// (L in {8, 16} divides fs) is split as k = r + RS m (RS = fs / L): for each r an
+// L-point DFT of y[n] = sum_t x[n + tL] exp(-2 pi i (n + tL) r / fs) (inputs beyond
+// L folded onto the L-periodic kernel). Its inverse with pruned outputs runs the
 // split backwards (L-point inverse DFTs, then an RS-point combination).
-// A workgroup handles NB bins at NF = 256 / (fs RS) consecutive frequencies; lanes
-// are interleaved by bin, so neighbouring lanes hold the same spectrum column of
-// different bins and one load of the response spectra serves all NB bins.
-// Thread (fl, kx, ry, bin) owns column kx, ky = ry + RS m of frequency f0 + fl.
+// A workgroup handles one bin at NF consecutive frequencies; thread (fl, kx, ry)
+// owns spectrum column kx, ky = ry + RS m of frequency f0 + fl.
 // LDS rows that lanes index with a stride use odd padded strides (bank conflicts).
 // ---------------------------------------------------------------------------
 struct SpLds {
     int P1, GL, YB;          // padded strides: abuf row (By), inverse rows (L), y rows (boy)
-    int zsz, asz, fwd, gsz, g2sz, ysz, y2sz, A, B, per_bin;
+    int zsz, asz, fwd, gsz, g2sz, ysz, y2sz, A, B, total;
 };
 
 __host__ __device__ inline SpLds sp_lds(int FS, int L, int NF, int CHX, int By, int ppad, int box,
@@ -232,41 +231,51 @@ __host__ __device__ inline SpLds sp_lds(int FS, int L, int NF, int CHX, int By, 
     s.y2sz = NF * box * s.YB;
     s.A = s.fwd > s.gsz ? (s.fwd > s.g2sz ? s.fwd : s.g2sz) : (s.gsz > s.g2sz ? s.gsz : s.g2sz);
     s.B = s.ysz > s.y2sz ? s.ysz : s.y2sz;
-    s.per_bin = s.A + s.B;
+    s.total = FS + s.A + s.B;
     return s;
 }
 
-template <int FS, int L, int NB>
-__global__ __launch_bounds__(256 * NB) void k_sp(ConvArgs A, int b0, int nbp,
-                                                 const int32_t* __restrict__ n_active,
-                                                 const float2* __restrict__ T,
-                                                 const float2* __restrict__ rhat,
-                                                 const float2* __restrict__ tws,
-                                                 float2* __restrict__ U) {
-    constexpr int RS = FS / L, TPF = FS * RS, NF = 256 / TPF, NT = 256 * NB;
+template <int FS, int L>
+struct SpShape {
+    static constexpr int RS = FS / L;
+    static constexpr int TPF = FS * RS;                       // threads per frequency
+    static constexpr int NF = TPF >= 256 ? 1 : (TPF > 128 ? 1 : (TPF > 64 ? 2 : 256 / TPF));
+    static constexpr int NT = (NF * TPF + 63) / 64 * 64;      // threads per workgroup
+};
+
+template <int FS, int L>
+__global__ __launch_bounds__((SpShape<FS, L>::NT)) void k_sp(ConvArgs A, int b0, int nbp,
+                                                          const int32_t* __restrict__ n_active,
+                                                          const float2* __restrict__ T,
+                                                          const float2* __restrict__ rhat,
+                                                          const float2* __restrict__ tws,
+                                                          float2* __restrict__ U) {
+    using S = SpShape<FS, L>;
+    constexpr int RS = S::RS, TPF = S::TPF, NF = S::NF, NT = S::NT;
+    constexpr int FOLD = 2;
     extern __shared__ float2 sm[];
     // bins vary fastest across the grid: the workgroups running at one time share the
     // frequency slab of the response spectra, which then comes from L2 / the last-level
     // cache instead of being streamed from HBM once per bin.
     // Bins of this pass: local index bl < nbp (scratch slots), global b0 + bl < n_active.
     const int na = min(*n_active, A.cap);
-    const int nvalid = min(nbp, na - b0);
-    if ((int)blockIdx.x * NB >= nvalid) return;
+    const int bl = blockIdx.x;
+    if (bl >= min(nbp, na - b0)) return;
     const int f0 = blockIdx.y * NF;
     const int tid = threadIdx.x;
-    const int me = tid % NB;
-    const int t2 = tid / NB;
-    const int fl = t2 / TPF, item = t2 % TPF;
+    const bool active = tid < NF * TPF;      // threads past NF*TPF only help in strided loops
+    const int fl = active ? tid / TPF : 0, item = tid % TPF;
     const int kx = item / RS, ry = item % RS;
     const int By = A.By, Bx = A.Bx, CHX = A.chx, ppad = A.ppad, box = A.box, boy = A.boy;
     const int ptiles = ppad / kTile;
-    const int blocal0 = blockIdx.x * NB;
     const SpLds Ls = sp_lds(FS, L, NF, CHX, By, ppad, box, boy);
     const int P1 = Ls.P1, GL = Ls.GL, YB = Ls.YB;
     float2* twl = sm;                        // exp(-2 pi i k / fs)
-    auto regA = [&](int bs) { return sm + FS + bs * Ls.per_bin; };
-    auto regB = [&](int bs) { return sm + FS + bs * Ls.per_bin + Ls.A; };
-    if (tid < FS) twl[tid] = tws[tid];
+    float2* regA = sm + FS;
+    float2* regB = regA + Ls.A;
+    float2* zbuf = regA;                     // [CHX][NF][ppad]
+    float2* abuf = regA + Ls.zsz;            // [CHX][NF][FS][P1]
+    for (int i = tid; i < FS; i += NT) twl[i] = tws[i];
 
     float2 acc[4][L];
 #pragma unroll
@@ -276,67 +285,75 @@ __global__ __launch_bounds__(256 * NB) void k_sp(ConvArgs A, int b0, int nbp,
     __syncthreads();
 
     for (int j0 = 0; j0 < A.nch; j0 += CHX) {
-        // stage the time spectra: zbuf[bin][cx][fl][p]
-        const int nld = NB * CHX * ptiles * NF * kTile;
+        // stage the time spectra of CHX channels at frequencies f0 .. f0+NF-1
+        const int nld = CHX * ptiles * NF * kTile;
         for (int i = tid; i < nld; i += NT) {
             const int pi = i % kTile;
             int r = i / kTile;
             const int fl2 = r % NF;
             r /= NF;
             const int pt = r % ptiles;
-            r /= ptiles;
-            const int cx = r % CHX;
-            const int bs = r / CHX;
+            const int cx = r / ptiles;
             const int ch = j0 + cx;
-            const int bl = blocal0 + bs;
             float2 z = make_float2(0.f, 0.f);
-            if (ch < A.nch && bl < nvalid)
+            if (ch < A.nch)
                 z = T[((((int64_t)bl * A.nch + ch) * ptiles + pt) * A.ft + f0 + fl2) * kTile + pi];
-            regA(bs)[(cx * NF + fl2) * ppad + pt * kTile + pi] = z;
+            zbuf[(cx * NF + fl2) * ppad + pt * kTile + pi] = z;
         }
         __syncthreads();
-        // x pass: for each (bin, channel, frequency, py, rx): L-point DFT over px,
-        // abuf[bin][cx][fl][kx][py] with row stride P1
-        const int nx = CHX * NF * By * RS * NB;
+        // x pass: for each (channel, frequency, py, rx): L-point DFT over the folded px
+        const int nx = CHX * NF * By * RS;
         for (int i = tid; i < nx; i += NT) {
-            const int bs = i % NB;
-            int r = i / NB;
-            const int rx = r % RS;
-            r /= RS;
+            const int rx = i % RS;
+            int r = i / RS;
             const int py = r % By;
             r /= By;
             const int fl2 = r % NF;
             const int cx = r / NF;
-            const float2* zr = regA(bs) + (cx * NF + fl2) * ppad;
+            const float2* zr = zbuf + (cx * NF + fl2) * ppad + py;
             float2 s[L];
 #pragma unroll
-            for (int n = 0; n < L; ++n)
-                s[n] = n < Bx ? cmul(zr[n * By + py], twl[(n * rx) % FS]) : make_float2(0.f, 0.f);
+            for (int n = 0; n < L; ++n) {
+                s[n] = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int t = 0; t < FOLD; ++t) {
+                    const int px = n + t * L;
+                    if (px < Bx) s[n] = cadd(s[n], cmul(zr[px * By], twl[(px * rx) % FS]));
+                }
+            }
             Dft<L>::run(s);
-            float2* ar = regA(bs) + Ls.zsz + (cx * NF + fl2) * FS * P1 + py;
+            float2* ar = abuf + (cx * NF + fl2) * FS * P1 + py;
 #pragma unroll
             for (int m = 0; m < L; ++m) ar[(rx + RS * m) * P1] = s[m];
         }
         __syncthreads();
         // y pass and multiply-accumulate, one channel at a time
-        for (int cx = 0; cx < CHX; ++cx) {
-            const int ch = j0 + cx;
-            if (ch >= A.nch) break;
-            const float2* ar = regA(me) + Ls.zsz + ((cx * NF + fl) * FS + kx) * P1;
-            float2 s[L];
+        if (active) {
+            for (int cx = 0; cx < CHX; ++cx) {
+                const int ch = j0 + cx;
+                if (ch >= A.nch) break;
+                const float2* ar = abuf + ((cx * NF + fl) * FS + kx) * P1;
+                float2 s[L];
 #pragma unroll
-            for (int n = 0; n < L; ++n)
-                s[n] = n < By ? cmul(ar[n], twl[(n * ry) % FS]) : make_float2(0.f, 0.f);
-            Dft<L>::run(s);
-            const float2* rh = rhat + ((int64_t)ch * A.nc * L * A.ft + f0 + fl) * TPF + item;
+                for (int n = 0; n < L; ++n) {
+                    s[n] = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (c < A.nc) {
+                    for (int t = 0; t < FOLD; ++t) {
+                        const int py = n + t * L;
+                        if (py < By) s[n] = cadd(s[n], cmul(ar[py], twl[(py * ry) % FS]));
+                    }
+                }
+                Dft<L>::run(s);
+                const float2* rh = rhat + ((int64_t)ch * A.nc * L * A.ft + f0 + fl) * TPF + item;
 #pragma unroll
-                    for (int m = 0; m < L; ++m) {
-                        const float2 w = rh[((int64_t)(c * L + m) * A.ft) * TPF];
-                        acc[c][m].x += s[m].x * w.x - s[m].y * w.y;
-                        acc[c][m].y += s[m].x * w.y + s[m].y * w.x;
+                for (int c = 0; c < 4; ++c) {
+                    if (c < A.nc) {
+#pragma unroll
+                        for (int m = 0; m < L; ++m) {
+                            const float2 w = rh[((int64_t)(c * L + m) * A.ft) * TPF];
+                            acc[c][m].x += s[m].x * w.x - s[m].y * w.y;
+                            acc[c][m].y += s[m].x * w.y + s[m].y * w.x;
+                        }
                     }
                 }
             }
@@ -349,30 +366,29 @@ __global__ __launch_bounds__(256 * NB) void k_sp(ConvArgs A, int b0, int nbp,
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         if (c >= A.nc) break;
-        {
-            // gbuf[bin][fl][kx][ry][n0]
+        float2* gbuf = regA;    // [NF][FS][RS][GL]
+        float2* ybuf = regB;    // [NF][FS][YB]
+        if (active) {
             float2 s[L];
 #pragma unroll
             for (int m = 0; m < L; ++m) s[m] = cconj(acc[c][m]);
             Dft<L>::run(s);
-            float2* gr = regA(me) + ((fl * FS + kx) * RS + ry) * GL;
+            float2* gr = gbuf + ((fl * FS + kx) * RS + ry) * GL;
 #pragma unroll
             for (int n0 = 0; n0 < L; ++n0) gr[n0] = cmulc(cconj(s[n0]), twl[(n0 * ry) % FS]);
         }
         __syncthreads();
-        // combine over ry -> y-inverse at qy = n0 + L n1 < boy: ybuf[bin][fl][kx][qy]
-        for (int i = tid; i < NF * FS * L * NB; i += NT) {
+        // combine over ry -> y-inverse at qy = n0 + L n1 < boy
+        for (int i = tid; i < NF * FS * L; i += NT) {
             const int n0 = i % L;
             int r = i / L;
-            const int bs = r % NB;
-            r /= NB;
             const int kx2 = r % FS;
             const int fl2 = r / FS;
-            const float2* gr = regA(bs) + ((fl2 * FS + kx2) * RS) * GL + n0;
+            const float2* gr = gbuf + ((fl2 * FS + kx2) * RS) * GL + n0;
             float2 col[RS];
 #pragma unroll
             for (int rr = 0; rr < RS; ++rr) col[rr] = gr[rr * GL];
-            float2* yr = regB(bs) + (fl2 * FS + kx2) * YB;
+            float2* yr = ybuf + (fl2 * FS + kx2) * YB;
 #pragma unroll
             for (int n1 = 0; n1 < RS; ++n1) {
                 const int qy = n0 + L * n1;
@@ -385,37 +401,34 @@ __global__ __launch_bounds__(256 * NB) void k_sp(ConvArgs A, int b0, int nbp,
             }
         }
         __syncthreads();
-        // x-inverse: L-point inverse DFTs over kx = rx + RS m: g2[bin][fl][qy][rx][n0]
-        for (int i = tid; i < NF * boy * RS * NB; i += NT) {
-            const int bs = i % NB;
-            int r = i / NB;
-            const int rx = r % RS;
-            r /= RS;
+        // x-inverse: L-point inverse DFTs over kx = rx + RS m
+        float2* g2 = regA;      // [NF][boy][RS][GL]
+        for (int i = tid; i < NF * boy * RS; i += NT) {
+            const int rx = i % RS;
+            int r = i / RS;
             const int qy = r % boy;
             const int fl2 = r / boy;
-            const float2* yr = regB(bs) + (fl2 * FS + rx) * YB + qy;
+            const float2* yr = ybuf + (fl2 * FS + rx) * YB + qy;
             float2 s[L];
 #pragma unroll
             for (int m = 0; m < L; ++m) s[m] = cconj(yr[RS * m * YB]);
             Dft<L>::run(s);
-            float2* gr = regA(bs) + ((fl2 * boy + qy) * RS + rx) * GL;
+            float2* gr = g2 + ((fl2 * boy + qy) * RS + rx) * GL;
 #pragma unroll
             for (int n0 = 0; n0 < L; ++n0) gr[n0] = cmulc(cconj(s[n0]), twl[(n0 * rx) % FS]);
         }
         __syncthreads();
-        // combine over rx -> y2[bin][fl][qx][qy]
-        for (int i = tid; i < NF * boy * L * NB; i += NT) {
+        float2* y2 = regB;      // [NF][box][YB]
+        for (int i = tid; i < NF * boy * L; i += NT) {
             const int n0 = i % L;
             int r = i / L;
-            const int bs = r % NB;
-            r /= NB;
             const int qy = r % boy;
             const int fl2 = r / boy;
-            const float2* gr = regA(bs) + ((fl2 * boy + qy) * RS) * GL + n0;
+            const float2* gr = g2 + ((fl2 * boy + qy) * RS) * GL + n0;
             float2 col[RS];
 #pragma unroll
             for (int rr = 0; rr < RS; ++rr) col[rr] = gr[rr * GL];
-            float2* yr = regB(bs) + fl2 * box * YB + qy;
+            float2* yr = y2 + fl2 * box * YB + qy;
 #pragma unroll
             for (int n1 = 0; n1 < RS; ++n1) {
                 const int qx = n0 + L * n1;
@@ -431,23 +444,19 @@ __global__ __launch_bounds__(256 * NB) void k_sp(ConvArgs A, int b0, int nbp,
         // I[q] = Re Y[q] + Im Y[q'] with q' the point reflection within the block output
         // (Re Y(t) + Im Y'(t) = Re(Y(t) - i Y'(t)), taken after the inverse time FFT)
         const int nq = box * boy;
-        for (int i = tid; i < NB * qtiles * NF * kTile; i += NT) {
+        for (int i = tid; i < qtiles * NF * kTile; i += NT) {
             const int qi = i % kTile;
             int r = i / kTile;
             const int fl2 = r % NF;
-            r /= NF;
-            const int qt = r % qtiles;
-            const int bs = r / qtiles;
-            const int bl = blocal0 + bs;
-            if (bl >= nvalid) continue;
+            const int qt = r / NF;
             const int q = qt * kTile + qi;
             float2 vq = make_float2(0.f, 0.f);
             if (q < nq) {
                 const int qx = q / boy, qy = q % boy;
-                const float2* y2 = regB(bs) + fl2 * box * YB;
-                vq = y2[qx * YB + qy];
+                const float2* yy = y2 + fl2 * box * YB;
+                vq = yy[qx * YB + qy];
                 if (A.mpcp) {
-                    const float2 yb = y2[(box - 1 - qx) * YB + (boy - 1 - qy)];
+                    const float2 yb = yy[(box - 1 - qx) * YB + (boy - 1 - qy)];
                     vq = make_float2(vq.x + yb.y, vq.y - yb.x);
                 }
             }
@@ -511,6 +520,22 @@ int pow2_at_least(int v, int lo) {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// supported spatial transform sizes and the length of their register sub-DFTs
+int spatial_sub_length(int fs) {
+    switch (fs) {
+        case 8: case 24: case 40: return 8;
+        case 16: case 32: case 48: case 64: return 16;
+        default: return 0;
+    }
+}
+
+int spatial_size_at_least(int n) {
+    const int sizes[] = {8, 16, 24, 32, 40, 48, 64};
+    for (int s : sizes)
+        if (s >= n) return s;
+    return 128;  // rejected by the caller
+}
+
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
 ConvArgs make_args(const tred_conv_plan* P) {
@@ -536,10 +561,6 @@ ConvArgs make_args(const tred_conv_plan* P) {
     A.mpcp = P->mpcp;
     A.chx = std::max(1, A.fs / A.By);
     A.cap = 0;
-    const int L = std::min(A.fs, 16);
-    const int RS = A.fs / L;
-    const int NF = 256 / (A.fs * RS);
-    (void)NF;
     A.vblk = (int64_t)A.Bx * A.sx * A.NYf * A.Bt;
     A.vout = (int64_t)A.box * A.boy * A.bot;
     return A;
@@ -573,25 +594,17 @@ tred_status launch_time_inv(const ConvArgs& A, int b0, int nb, const int32_t* na
     return tred_check_launch("tred_block_conv time inverse");
 }
 
-template <int FS, int L, int NB>
-tred_status launch_space_nb(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
-                            const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
-    constexpr int RS = FS / L, NF = 256 / (FS * RS);
-    const SpLds Ls = sp_lds(FS, L, NF, A.chx, A.By, A.ppad, A.box, A.boy);
-    const size_t lds = (size_t)(FS + NB * Ls.per_bin) * sizeof(float2);
-    if (lds > 160 * 1024) return tred_fail(TRED_EUNSUPPORTED, "spatial stage needs %zu B of LDS", lds);
-    allow_lds(k_sp<FS, L, NB>, lds);
-    hipLaunchKernelGGL((k_sp<FS, L, NB>), dim3((nb + NB - 1) / NB, A.ft / NF), dim3(256 * NB), lds,
-                       st, A, b0, nb, na, T, rhat, tws, U);
-    return tred_check_launch("tred_block_conv space");
-}
-
 template <int FS, int L>
-tred_status launch_space(const ConvArgs& A, int nbins_wg, int b0, int nb, const int32_t* na,
-                         const float2* T, const float2* rhat, const float2* tws, float2* U,
-                         hipStream_t st) {
-    if (nbins_wg == 2) return launch_space_nb<FS, L, 2>(A, b0, nb, na, T, rhat, tws, U, st);
-    return launch_space_nb<FS, L, 1>(A, b0, nb, na, T, rhat, tws, U, st);
+tred_status launch_space(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
+                         const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
+    using S = SpShape<FS, L>;
+    const SpLds Ls = sp_lds(FS, L, S::NF, A.chx, A.By, A.ppad, A.box, A.boy);
+    const size_t lds = (size_t)Ls.total * sizeof(float2);
+    if (lds > 160 * 1024) return tred_fail(TRED_EUNSUPPORTED, "spatial stage needs %zu B of LDS", lds);
+    allow_lds(k_sp<FS, L>, lds);
+    hipLaunchKernelGGL((k_sp<FS, L>), dim3(nb, A.ft / S::NF), dim3(S::NT), lds, st, A, b0, nb, na, T,
+                       rhat, tws, U);
+    return tred_check_launch("tred_block_conv space");
 }
 
 template <typename F>
@@ -628,31 +641,29 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     P->kticks = kticks;
     P->mpcp = (flags & TRED_CONV_MPCP) ? 1 : 0;
     P->batch = batch;
-    // bins per workgroup of the spatial stage (1 or 2); a tuning knob
-    P->sp_bins = 1;
-    if (const char* e = getenv("TRED_SP_BINS")) P->sp_bins = atoi(e) == 2 ? 2 : 1;
     const int Bx = blocking->blk_pix[0], By = blocking->blk_pix[1], Bt = blocking->blk_ticks;
     P->bo[0] = Bx + kpix[0] - 1;
     P->bo[1] = By + kpix[1] - 1;
     P->bo[2] = Bt + kticks - 1;
-    int fsx = fft && fft[0] ? fft[0] : pow2_at_least(P->bo[0], 8);
-    int fsy = fft && fft[1] ? fft[1] : pow2_at_least(P->bo[1], 8);
+    int fsx = fft && fft[0] ? fft[0] : spatial_size_at_least(P->bo[0]);
+    int fsy = fft && fft[1] ? fft[1] : spatial_size_at_least(P->bo[1]);
     int ft = fft && fft[2] ? fft[2] : pow2_at_least(P->bo[2], 256);
     auto bad = [&](tred_status s, const char* msg) {
         delete P;
         return tred_fail(s, "%s", msg);
     };
-    if (!is_pow2(fsx) || !is_pow2(fsy) || fsx < P->bo[0] || fsy < P->bo[1])
-        return bad(TRED_EINVAL, "spatial FFT sizes must be powers of two >= blk_pix + kpix - 1");
-    if (fsx != fsy || fsx < 8 || fsx > 64)
-        return bad(TRED_EUNSUPPORTED, "spatial FFT sizes must be equal and in {8,16,32,64}");
-    const int L = std::min(fsx, 16);
-    if (Bx > L || By > L) return bad(TRED_EUNSUPPORTED, "blk_pix must be <= min(fft, 16)");
+    if (fsx < P->bo[0] || fsy < P->bo[1])
+        return bad(TRED_EINVAL, "spatial FFT sizes must be >= blk_pix + kpix - 1");
+    if (fsx != fsy || spatial_sub_length(fsx) == 0)
+        return bad(TRED_EUNSUPPORTED, "spatial FFT sizes must be equal and in {8,16,24,32,40,48,64}");
+    const int L = spatial_sub_length(fsx);
+    if (Bx > 2 * L || By > 2 * L) return bad(TRED_EUNSUPPORTED, "blk_pix too large for this FFT size");
     if (Bt % 64 != 0) return bad(TRED_EUNSUPPORTED, "blk_ticks must be a multiple of 64");
     if (!is_pow2(ft)) return bad(TRED_EINVAL, "time FFT size must be a power of two");
     if (ft < 256 || ft > 2048) return bad(TRED_EUNSUPPORTED, "time FFT size must be in [256, 2048]");
     if (ft < Bt + 64) return bad(TRED_EINVAL, "time FFT size must be >= blk_ticks + 64");
     P->fs = fsx;
+    P->ls = L;
     P->ft = ft;
     P->ct = ft - Bt;
     P->nc = (kticks + P->ct - 1) / P->ct;
@@ -742,7 +753,7 @@ extern "C" tred_status tred_conv_plan_set_response(tred_conv_plan* P, const floa
                        twds);
     hipLaunchKernelGGL(k_rhat_time, dim3(8192), dim3(256), 0, st, resp, A, Kx, Ky, kt, twdt, PA);
     hipLaunchKernelGGL(k_rhat_x, dim3(8192), dim3(256), 0, st, A, Kx, Ky, twds, PA, PB);
-    const int L = std::min(P->fs, 16);
+    const int L = P->ls;
     const double scale = 1.0 / ((double)P->fs * P->fs * P->ft);
     hipLaunchKernelGGL(k_rhat_y, dim3(8192), dim3(256), 0, st, A, Ky, L, scale, twds, PB,
                        (float2*)(ws + P->off_rhat));
@@ -785,12 +796,14 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
         mark(b0, 1);
         mark(b0, 2);
         tred_status s;
-        const int nbw = P->sp_bins;
         switch (P->fs) {
-            case 8: s = launch_space<8, 8>(A, nbw, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 16: s = launch_space<16, 16>(A, nbw, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 32: s = launch_space<32, 16>(A, nbw, b0, nb, n_active, T, rhat, tws, U, st); break;
-            default: s = launch_space<64, 16>(A, nbw, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 8: s = launch_space<8, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 16: s = launch_space<16, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 24: s = launch_space<24, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 32: s = launch_space<32, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 40: s = launch_space<40, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            case 48: s = launch_space<48, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
+            default: s = launch_space<64, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
         }
         TRED_TRY(s);
         mark(b0, 3);

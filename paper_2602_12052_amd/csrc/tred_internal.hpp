@@ -226,13 +226,13 @@ struct tred_conv_plan {
     int32_t kpix[2];
     int32_t kticks;
     int32_t fs;          // spatial FFT size (square)
+    int32_t ls;          // length of the register sub-DFTs of the spatial transform
     int32_t ft;          // time FFT size
     int32_t ct;          // response ticks per piece
     int32_t nc;          // response pieces
     int32_t nch;         // transformed channels (pairs under MPCP)
     int32_t mpcp;
     int32_t batch;
-    int32_t sp_bins;     // bins per workgroup in the spatial stage
     int32_t bo[3];       // output block extent
     int32_t qpad;        // output pixels per block padded to the tile of 8
     // workspace layout (byte offsets)

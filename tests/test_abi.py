@@ -112,6 +112,10 @@ def test_plan_create_resolves_sizes(T):
     T.lib().tred_conv_plan_info(h, f, C.byref(pcs), C.byref(ch), o)
     assert st == 0 and pcs.value == 4 and tuple(o) == (36, 36, 2559)
     T.lib().tred_conv_plan_destroy(h)
+    st, h, ws = _plan(T, cfg2, fft=(0, 0, 1024))     # smallest spatial size: 40
+    T.lib().tred_conv_plan_info(h, f, C.byref(pcs), C.byref(ch), o)
+    assert st == 0 and tuple(f) == (40, 40, 1024)
+    T.lib().tred_conv_plan_destroy(h)
 
 
 @pytest.mark.parametrize("kw,expect", [
@@ -120,6 +124,7 @@ def test_plan_create_resolves_sizes(T):
     (dict(fft=(8, 8, 128)), 4),             # below the supported time sizes
     (dict(fft=(8, 16, 256)), 4),            # non-square spatial FFT
     (dict(fft=(4, 4, 256)), 1),             # spatial FFT smaller than the output
+    (dict(fft=(12, 12, 256)), 4),           # spatial size without a kernel
     (dict(fft=(8, 8, 256), kticks=2000), 4),  # more than four response pieces
     (dict(flags=2), 1),                     # unknown flag
     (dict(batch=0), 1),

@@ -129,6 +129,12 @@ def test_footprints_bitexact_adversarial(T, orc):
                   seed=4), True),
     ("fs64", dict(npix=32, nticks=1100, blk=(16, 16, 512), kpix=(21, 21), kticks=600,
                   fft=(64, 64, 1024), n=20, seed=5), True),
+    ("fs40-fold", dict(npix=32, nticks=1100, blk=(16, 16, 512), kpix=(21, 21), kticks=600,
+                       fft=(40, 40, 1024), n=20, seed=12), True),
+    ("fs24-fold-plain", dict(npix=12, blk=(12, 12, 64), kpix=(11, 11), kticks=120,
+                             fft=(24, 24, 256), n=15, seed=13), False),
+    ("fs48", dict(npix=16, blk=(16, 16, 128), kpix=(15, 15), kticks=200, fft=(48, 48, 512), n=15,
+                  seed=14), True),
     ("sub10-three-pieces", dict(npix=8, sub=10, nticks=400, blk=(4, 4, 128), kpix=(5, 5), kticks=300,
                                 fft=(8, 8, 256), n=12, seed=6), True),
     ("sub4-even-plain", dict(npix=6, sub=4, nticks=256, blk=(3, 3, 64), kpix=(3, 3), kticks=64,

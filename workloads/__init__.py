@@ -115,14 +115,14 @@ def cfg_module(seed: int = 1) -> Config:
     21x21x2048 response, blocks of 16x16 pixels x 512 ticks."""
     g = _grid(256, 6250)
     return Config("module-1e5", g, _physics(g), Blocking((16, 16), 512), (21, 21), 2048,
-                  (64, 64, 1024), 100_000, "module", seed)
+                  (40, 40, 1024), 100_000, "module", seed)
 
 
 def cfg_diff(seed: int = 1) -> Config:
     """2e4 depositions in a 128x128-pixel region with the module-scale response."""
     g = _grid(128, 6250)
     return Config("diff-2e4", g, _physics(g), Blocking((16, 16), 512), (21, 21), 2048,
-                  (64, 64, 1024), 20_000, "module", seed)
+                  (40, 40, 1024), 20_000, "module", seed)
 
 
 # ----------------------------------------------------------------------------
