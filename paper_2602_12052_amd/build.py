@@ -29,25 +29,26 @@ def hipcc_flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP/C++ source of the library and link libtred.so."""
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every HIP/C++ source of the library and link libtred.so (or `out`)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build" if out == LIB else "_build_" + os.path.basename(out))
     os.makedirs(objdir, exist_ok=True)
     objs = []
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc] + hipcc_flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + hipcc_flags() + ["-D" + d for d in defines] + lang + \
+            ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         objs.append(obj)
     failed = []
     for src, p in procs:
-        out, _ = p.communicate()
-        text = out.decode(errors="replace")
+        log, _ = p.communicate()
+        text = log.decode(errors="replace")
         # hipcc's host pass does not know the packed-fp32 target feature: harmless
         lines = [l for l in text.splitlines() if "packed-fp32-ops" not in l and l.strip()]
         if p.returncode != 0:
@@ -57,11 +58,11 @@ def build(verbose: bool = False) -> str:
             print("\n".join(lines))
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -122,8 +122,9 @@ __global__ void k_rhat_x(ConvArgs A, int Kx, int Ky, const double2* __restrict__
     }
 }
 
-// R̂[ch][c][m][f][item] = scale * sum_ky PB[ch][c][kxf][ky][f] exp(-2 pi i ky kyf / fs),
-// item = kxf * RS + ry, kyf = ry + RS * m (the order in which k_sp holds spectra).
+// R̂[ch][f][c][m][item] = scale * sum_ky PB[ch][c][kxf][ky][f] exp(-2 pi i ky kyf / fs),
+// item = kxf * RS + ry, kyf = ry + RS * m (the order in which k_sp holds spectra: the
+// nc * L values a k_sp thread needs at one frequency lie at fixed offsets).
 __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2* __restrict__ twd,
                          const double2* __restrict__ PB, float2* __restrict__ rhat) {
     const int RS = A.fs / L;
@@ -133,9 +134,10 @@ __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2*
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = i;
         const int item = (int)(r % TPF); r /= TPF;
-        const int f = (int)(r % A.ft); r /= A.ft;
         const int m = (int)(r % L); r /= L;
-        const int64_t cc = r;
+        const int c = (int)(r % A.nc); r /= A.nc;
+        const int f = (int)(r % A.ft); r /= A.ft;
+        const int64_t cc = r * A.nc + c;  // ch * nc + c
         const int kxf = item / RS, ry = item % RS;
         const int kyf = ry + RS * m;
         double re = 0.0, im = 0.0;
@@ -243,8 +245,12 @@ struct SpShape {
     static constexpr int NT = (NF * TPF + 63) / 64 * 64;      // threads per workgroup
 };
 
+// Occupancy target: with 8-point sub-DFTs the accumulators fit 128 VGPRs and four
+// waves per SIMD hide the latency of the response-spectrum loads (measured faster than
+// three waves without spills); 16-point sub-DFTs keep the compiler's choice.
 template <int FS, int L>
-__global__ __launch_bounds__((SpShape<FS, L>::NT)) void k_sp(ConvArgs A, int b0, int nbp,
+__global__ __launch_bounds__((SpShape<FS, L>::NT)) __attribute__((amdgpu_waves_per_eu(L == 8 ? 4 : 1)))
+void k_sp(ConvArgs A, int b0, int nbp,
                                                           const int32_t* __restrict__ n_active,
                                                           const float2* __restrict__ T,
                                                           const float2* __restrict__ rhat,
@@ -282,11 +288,16 @@ __global__ __launch_bounds__((SpShape<FS, L>::NT)) void k_sp(ConvArgs A, int b0,
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int m = 0; m < L; ++m) acc[c][m] = make_float2(0.f, 0.f);
+    const int nld = CHX * ptiles * NF * kTile;
+    const int nx = CHX * NF * By * RS;
+    const int64_t tstride = (int64_t)ptiles * A.ft * kTile;   // one channel of T
+    const float2* Tb = T + (int64_t)bl * A.nch * tstride;
+    // response spectra of (channel, frequency): nc * L values per thread at fixed offsets
+    const int64_t rstride = (int64_t)A.nc * L * TPF;
     __syncthreads();
 
     for (int j0 = 0; j0 < A.nch; j0 += CHX) {
         // stage the time spectra of CHX channels at frequencies f0 .. f0+NF-1
-        const int nld = CHX * ptiles * NF * kTile;
         for (int i = tid; i < nld; i += NT) {
             const int pi = i % kTile;
             int r = i / kTile;
@@ -296,13 +307,11 @@ __global__ __launch_bounds__((SpShape<FS, L>::NT)) void k_sp(ConvArgs A, int b0,
             const int cx = r / ptiles;
             const int ch = j0 + cx;
             float2 z = make_float2(0.f, 0.f);
-            if (ch < A.nch)
-                z = T[((((int64_t)bl * A.nch + ch) * ptiles + pt) * A.ft + f0 + fl2) * kTile + pi];
+            if (ch < A.nch) z = Tb[ch * tstride + (pt * A.ft + f0 + fl2) * kTile + pi];
             zbuf[(cx * NF + fl2) * ppad + pt * kTile + pi] = z;
         }
         __syncthreads();
         // x pass: for each (channel, frequency, py, rx): L-point DFT over the folded px
-        const int nx = CHX * NF * By * RS;
         for (int i = tid; i < nx; i += NT) {
             const int rx = i % RS;
             int r = i / RS;
@@ -332,6 +341,7 @@ __global__ __launch_bounds__((SpShape<FS, L>::NT)) void k_sp(ConvArgs A, int b0,
             for (int cx = 0; cx < CHX; ++cx) {
                 const int ch = j0 + cx;
                 if (ch >= A.nch) break;
+                const float2* rh = rhat + ((int64_t)ch * A.ft + f0 + fl) * rstride + item;
                 const float2* ar = abuf + ((cx * NF + fl) * FS + kx) * P1;
                 float2 s[L];
 #pragma unroll
@@ -344,16 +354,21 @@ __global__ __launch_bounds__((SpShape<FS, L>::NT)) void k_sp(ConvArgs A, int b0,
                     }
                 }
                 Dft<L>::run(s);
-                const float2* rh = rhat + ((int64_t)ch * A.nc * L * A.ft + f0 + fl) * TPF + item;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     if (c < A.nc) {
+                        // one piece at a time: its L loads, then its L multiply-adds
+                        // (bounds the loads in flight and the registers they hold)
+                        float2 w[L];
+#pragma unroll
+                        for (int m = 0; m < L; ++m) w[m] = rh[(c * L + m) * TPF];
+                        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int m = 0; m < L; ++m) {
-                            const float2 w = rh[((int64_t)(c * L + m) * A.ft) * TPF];
-                            acc[c][m].x += s[m].x * w.x - s[m].y * w.y;
-                            acc[c][m].y += s[m].x * w.y + s[m].y * w.x;
+                            acc[c][m].x += s[m].x * w[m].x - s[m].y * w[m].y;
+                            acc[c][m].y += s[m].x * w[m].y + s[m].y * w[m].x;
                         }
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
             }
@@ -595,9 +610,16 @@ tred_status launch_time_inv(const ConvArgs& A, int b0, int nb, const int32_t* na
 }
 
 template <int FS, int L>
-tred_status launch_space(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
+tred_status launch_space(const ConvArgs& A0, int b0, int nb, const int32_t* na, const float2* T,
                          const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
     using S = SpShape<FS, L>;
+    constexpr int MAXIT = 2;   // per-thread staging / x-pass items the kernel unrolls
+    ConvArgs A = A0;
+    const int per_ch_ld = (A.ppad / kTile) * S::NF * kTile;
+    const int per_ch_x = S::NF * A.By * S::RS;
+    A.chx = std::min(std::max(1, FS / A.By),
+                     std::min(MAXIT * S::NT / per_ch_ld, MAXIT * S::NT / per_ch_x));
+    if (A.chx < 1) return tred_fail(TRED_EUNSUPPORTED, "bin too large for the spatial stage");
     const SpLds Ls = sp_lds(FS, L, S::NF, A.chx, A.By, A.ppad, A.box, A.boy);
     const size_t lds = (size_t)Ls.total * sizeof(float2);
     if (lds > 160 * 1024) return tred_fail(TRED_EUNSUPPORTED, "spatial stage needs %zu B of LDS", lds);

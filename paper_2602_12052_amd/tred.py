@@ -13,7 +13,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtred.so")
+# TRED_LIBRARY selects another build of the same library (A/B comparisons of kernels)
+LIB_PATH = os.environ.get("TRED_LIBRARY") or os.path.join(_HERE, "libtred.so")
 
 TRED_OK, TRED_EINVAL, TRED_ECAPACITY, TRED_EDEVICE, TRED_EUNSUPPORTED = range(5)
 TRED_CONV_MPCP = 1
