@@ -130,11 +130,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=40)
     ap.add_argument("--plain", action="store_true", help="complex-of-real packing instead of MPCP")
-    ap.add_argument("--scratch-gb", type=float, default=100.0,
+    ap.add_argument("--scratch-gb", type=float, default=None,
                     help="bound on the convolution scratch (sets the bins per pass)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
+    if args.scratch_gb is None:
+        from paper_2602_12052_amd import tred as _t
+        args.scratch_gb = _t.DEFAULT_CONV_SCRATCH / 1e9
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path is "
@@ -166,11 +169,10 @@ def main():
     Bx, By = cfg.blocking.blk_pix
     Bt = cfg.blocking.blk_ticks
     fs, ft = cfg.fft[0], cfg.fft[2]
-    nch = 50 if mpcp else 100
     nc = -(-cfg.kticks // (ft - Bt))
     box, boy = Bx + cfg.kpix[0] - 1, By + cfg.kpix[1] - 1
-    per_block_scratch = (nch * Bx * By + nc * box * boy) * ft * 8
-    batch = max(1, min(block_cap, int(args.scratch_gb * 1e9 // per_block_scratch)))
+    batch = tred.conv_batch(cfg.grid, cfg.blocking, cfg.kpix, cfg.kticks, cfg.fft, mpcp, block_cap,
+                            args.scratch_gb * 1e9)
     pl = tred.Pipeline(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, dev_resp,
                        seg.shape[0], val_cap, block_cap, pix_cap, cfg.fft, mpcp, batch)
     stream = torch.cuda.current_stream().cuda_stream

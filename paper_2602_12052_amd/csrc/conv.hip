@@ -20,6 +20,11 @@
 #include "tred_internal.hpp"
 #include "validate.hpp"
 
+// bins per workgroup of the prime-factor spatial stage with 8-point sub-DFTs
+#ifndef TRED_SPP_NB8
+#define TRED_SPP_NB8 2
+#endif
+
 namespace {
 
 struct ConvArgs {
@@ -27,6 +32,7 @@ struct ConvArgs {
     int32_t nch, nc, ct, ft, fs;
     int32_t ppad, qpad, box, boy, bot;
     int32_t mpcp, chx, cap;
+    int32_t e1, e2;      // row order of the response spectra: ky = (e1 m + e2 ry) mod fs
     int64_t vblk, vout;
 };
 
@@ -123,8 +129,9 @@ __global__ void k_rhat_x(ConvArgs A, int Kx, int Ky, const double2* __restrict__
 }
 
 // R̂[ch][f][c][m][item] = scale * sum_ky PB[ch][c][kxf][ky][f] exp(-2 pi i ky kyf / fs),
-// item = kxf * RS + ry, kyf = ry + RS * m (the order in which k_sp holds spectra: the
-// nc * L values a k_sp thread needs at one frequency lie at fixed offsets).
+// item = kxf * RS + ry, kyf = (e1 m + e2 ry) mod fs: the order in which the spatial
+// kernels hold spectra (k_sp: kyf = ry + RS m; k_spp: the prime-factor output map),
+// so that the nc * L values a thread needs at one frequency lie at fixed offsets.
 __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2* __restrict__ twd,
                          const double2* __restrict__ PB, float2* __restrict__ rhat) {
     const int RS = A.fs / L;
@@ -139,7 +146,7 @@ __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2*
         const int f = (int)(r % A.ft); r /= A.ft;
         const int64_t cc = r * A.nc + c;  // ch * nc + c
         const int kxf = item / RS, ry = item % RS;
-        const int kyf = ry + RS * m;
+        const int kyf = (A.e1 * m + A.e2 * ry) % A.fs;
         double re = 0.0, im = 0.0;
         for (int ky = 0; ky < Ky; ++ky) {
             const double2 a = PB[((cc * A.fs + kxf) * Ky + ky) * A.ft + f];
@@ -482,6 +489,316 @@ void k_sp(ConvArgs A, int b0, int nbp,
 }
 
 // ---------------------------------------------------------------------------
+// k_spp: the spatial stage for sizes fs = L * RS with gcd(L, RS) = 1 (8, 16, 24, 40,
+// 48), using the prime-factor index maps (Pfa): each L-point sub-DFT gathers its
+// inputs with the RS-point phase factors W_RS^(n2 k2) only (RS - 1 distinct values
+// per thread, held in registers), and no twiddles sit between the stages. Inputs are
+// zero-padded to NIN = L or 2 L per axis, so every loop is unrolled without branches.
+// A workgroup holds NB bins at NF frequencies; thread (fl, kx, k2) owns spectrum
+// column kx, rows ky = k_of(k1, k2), of every bin, so each response-spectrum load
+// feeds NB multiply-accumulates. The time spectra of the next channel are loaded
+// into registers while the current channel is transformed.
+// ---------------------------------------------------------------------------
+template <int FS, int L, int NIN, int NB>
+struct SppShape {
+    static constexpr int RS = FS / L;
+    static constexpr int TPF = FS * RS;
+    static constexpr int NF = TPF >= 128 ? 1 : (TPF > 64 ? 2 : 256 / TPF);
+    static constexpr int NT = (NF * TPF + 63) / 64 * 64;
+    static constexpr int NZ = NB * NF * NIN * NIN;            // staged inputs
+    static constexpr int ZPT = (NZ + NT - 1) / NT;           // per thread
+};
+
+struct SppLds {
+    int tw, P1, YB, zsz, asz, gsz, g2sz, ysz, y2sz, A, B, total;
+};
+
+__host__ __device__ inline int even_up(int v) { return (v + 1) & ~1; }
+
+template <int FS, int L, int NIN, int NB, int NF>
+__host__ __device__ inline SppLds spp_lds(int box, int boy) {
+    constexpr int RS = FS / L;
+    SppLds s;
+    s.tw = even_up(FS);
+    s.P1 = NIN + 2;                                   // even: rows are 16-byte aligned
+    s.YB = (boy % 2 == 0) ? boy + 1 : boy;            // odd: strided accesses spread over banks
+    s.zsz = NB * NF * NIN * NIN;
+    s.asz = NB * NF * FS * s.P1;
+    s.gsz = RS > 1 ? NB * NF * FS * L * RS : 0;
+    s.g2sz = RS > 1 ? NB * NF * boy * L * RS : 0;
+    s.ysz = NB * NF * FS * s.YB;
+    s.y2sz = NB * NF * box * s.YB;
+    int a = s.zsz + s.asz;
+    if (s.gsz > a) a = s.gsz;
+    const int a2 = RS > 1 ? s.g2sz : s.y2sz;           // with RS = 1 the x-inverse lands in A
+    if (a2 > a) a = a2;
+    int b = s.ysz;
+    if (RS > 1 && s.y2sz > b) b = s.y2sz;
+    s.A = even_up(a);
+    s.B = even_up(b);
+    s.total = s.tw + s.A + s.B;
+    return s;
+}
+
+template <int FS, int L, int NIN, int NB>
+__global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
+    ConvArgs A, int b0, int nbp, const int32_t* __restrict__ n_active,
+    const float2* __restrict__ T, const float2* __restrict__ rhat,
+    const float2* __restrict__ tws, float2* __restrict__ U) {
+    using S = SppShape<FS, L, NIN, NB>;
+    using P = Pfa<L, S::RS>;
+    constexpr int RS = S::RS, TPF = S::TPF, NF = S::NF, NT = S::NT, NZ = S::NZ, ZPT = S::ZPT;
+    static_assert(NIN % 2 == 0 && NIN <= 2 * L, "input padding");
+    extern __shared__ float4 sm4[];
+    float2* sm = (float2*)sm4;
+    // bins vary fastest across the grid (response spectra shared through L2)
+    const int na = min(*n_active, A.cap);
+    const int nloc = min(nbp, na - b0);
+    const int bl0 = blockIdx.x * NB;
+    if (bl0 >= nloc) return;
+    const int nbv = min(NB, nloc - bl0);
+    const int f0 = blockIdx.y * NF;
+    const int tid = threadIdx.x;
+    const bool active = tid < NF * TPF;
+    const int fl = active ? tid / TPF : 0, item = tid % TPF;
+    const int kx = item / RS, k2 = item % RS;
+    const int Bx = A.Bx, By = A.By, box = A.box, boy = A.boy;
+    const SppLds Ls = spp_lds<FS, L, NIN, NB, NF>(box, boy);
+    const int P1 = Ls.P1, YB = Ls.YB;
+    float2* twl = sm;                       // exp(-2 pi i k / fs)
+    float2* regA = sm + Ls.tw;
+    float2* regB = regA + Ls.A;
+    float2* zbuf = regA;                    // [NB][NF][NIN px][NIN py]
+    float2* abuf = regA + Ls.zsz;           // [NB][NF][FS kx][P1 py]
+    for (int i = tid; i < FS; i += NT) twl[i] = tws[i];
+
+    const int ptiles = A.ppad / kTile;
+    const int64_t tstride = (int64_t)ptiles * A.ft * kTile;   // one channel of T
+    const float2* Tb = T + (int64_t)bl0 * A.nch * tstride;
+    float2 zpre[ZPT];
+    auto load_T = [&](int ch) {
+#pragma unroll
+        for (int k = 0; k < ZPT; ++k) {
+            const int i = tid + k * NT;
+            zpre[k] = make_float2(0.f, 0.f);
+            if (i < NZ) {
+                const int py = i % NIN;
+                int r = i / NIN;
+                const int px = r % NIN;
+                r /= NIN;
+                const int fl2 = r % NF;
+                const int b = r / NF;
+                if (b < nbv && px < Bx && py < By) {
+                    const int p = px * By + py;
+                    zpre[k] = Tb[((int64_t)b * A.nch + ch) * tstride +
+                                 ((int64_t)(p / kTile) * A.ft + f0 + fl2) * kTile + p % kTile];
+                }
+            }
+        }
+    };
+    auto store_T = [&]() {
+#pragma unroll
+        for (int k = 0; k < ZPT; ++k) {
+            const int i = tid + k * NT;
+            if (i < NZ) zbuf[i] = zpre[k];
+        }
+    };
+
+    float2 acc[NB][4][L];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < L; ++m) acc[b][c][m] = make_float2(0.f, 0.f);
+    load_T(0);
+    __syncthreads();
+    float2 wy[RS];   // W_RS^(j k2) of this thread's rows
+#pragma unroll
+    for (int j = 0; j < RS; ++j) wy[j] = twl[((j * k2) % RS) * L];
+    store_T();
+    __syncthreads();
+    const int64_t rstride = (int64_t)A.nc * L * TPF;
+
+    for (int ch = 0; ch < A.nch; ++ch) {
+        // x pass: for each (bin, frequency, py, k2x) an L-point DFT over the gathered px
+        for (int i = tid; i < NB * NF * NIN * RS; i += NT) {
+            const int kk = i % RS;
+            int r = i / RS;
+            const int py = r % NIN;
+            const int bf = r / NIN;   // b * NF + fl2
+            float2 t[L];
+            if (py < By) {
+                const float2* zr = zbuf + bf * NIN * NIN + py;
+                float2 x[NIN];
+#pragma unroll
+                for (int px = 0; px < NIN; ++px) x[px] = zr[px * NIN];
+                float2 w[RS];
+#pragma unroll
+                for (int j = 0; j < RS; ++j) w[j] = twl[((j * kk) % RS) * L];
+                pfa_gather<L, RS, NIN>(x, w, t);
+                Dft<L>::run(t);
+            } else {
+#pragma unroll
+                for (int m = 0; m < L; ++m) t[m] = make_float2(0.f, 0.f);
+            }
+            float2* ar = abuf + bf * FS * P1 + py;
+#pragma unroll
+            for (int m = 0; m < L; ++m) ar[P::k_of(m, kk) * P1] = t[m];
+        }
+        __syncthreads();
+        if (ch + 1 < A.nch) load_T(ch + 1);
+        // y pass and multiply-accumulate with the response spectra of every piece
+        if (active) {
+            float2 s[NB][L];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float4* ar4 = (const float4*)(abuf + ((b * NF + fl) * FS + kx) * P1);
+                float2 x[NIN];
+#pragma unroll
+                for (int q = 0; q < NIN / 2; ++q) {
+                    const float4 v = ar4[q];
+                    x[2 * q] = make_float2(v.x, v.y);
+                    x[2 * q + 1] = make_float2(v.z, v.w);
+                }
+                pfa_gather<L, RS, NIN>(x, wy, s[b]);
+                Dft<L>::run(s[b]);
+            }
+            const float2* rh = rhat + ((int64_t)ch * A.ft + f0 + fl) * rstride + item;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c < A.nc) {
+                    float2 w[L];
+#pragma unroll
+                    for (int m = 0; m < L; ++m) w[m] = rh[(c * L + m) * TPF];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int m = 0; m < L; ++m) acc[b][c][m] = cfma(s[b][m], w[m], acc[b][c][m]);
+                }
+            }
+        }
+        if (ch + 1 < A.nch) store_T();
+        __syncthreads();
+    }
+
+    // inverse spatial transforms of every response piece and the mirror-pair unpacking
+    const int qtiles = A.qpad / kTile;
+    float2* gbuf = regA;                    // [NB][NF][FS kx][L n1][RS k2]
+    float2* ybuf = regB;                    // [NB][NF][FS kx][YB qy]
+    float2* g2 = regA;                      // [NB][NF][boy qy][L n1][RS k2]
+    float2* y2 = RS > 1 ? regB : regA;      // [NB][NF][box qx][YB qy]
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c >= A.nc) break;
+        // y-inverse, L-point stage over k1 (conj(DFT(conj .)) = inverse DFT)
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                float2 t[L];
+#pragma unroll
+                for (int m = 0; m < L; ++m) t[m] = cconj(acc[b][c][m]);
+                Dft<L>::run(t);
+                const int bf = b * NF + fl;
+                if constexpr (RS == 1) {
+                    float2* yr = ybuf + (bf * FS + kx) * YB;
+#pragma unroll
+                    for (int n = 0; n < L; ++n)
+                        if (n < boy) yr[n] = cconj(t[n]);
+                } else {
+                    float2* gr = gbuf + ((bf * FS + kx) * L) * RS + k2;
+#pragma unroll
+                    for (int n = 0; n < L; ++n) gr[n * RS] = t[n];   // conjugated partial sums
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (RS > 1) {
+            // y-inverse, RS-point stage over k2 -> qy = n_of(n1, n2) < boy
+            for (int i = tid; i < NB * NF * FS * L; i += NT) {
+                const int n1 = i % L;
+                const int r = i / L;   // bf * FS + kx
+                const float2* gr = gbuf + (r * L + n1) * RS;
+                float2 t[RS];
+#pragma unroll
+                for (int k = 0; k < RS; ++k) t[k] = gr[k];
+                Dft<RS>::run(t);
+                float2* yr = ybuf + r * YB;
+#pragma unroll
+                for (int n2 = 0; n2 < RS; ++n2) {
+                    const int qy = P::n_of(n1, n2);
+                    if (qy < boy) yr[qy] = cconj(t[n2]);
+                }
+            }
+            __syncthreads();
+        }
+        // x-inverse, L-point stage over kx = k_of(k1, k2x) for every qy
+        for (int i = tid; i < NB * NF * boy * RS; i += NT) {
+            const int kk = i % RS;
+            const int r = i / RS;     // bf * boy + qy
+            const int qy = r % boy, bf = r / boy;
+            const float2* yr = ybuf + bf * FS * YB + qy;
+            float2 t[L];
+#pragma unroll
+            for (int m = 0; m < L; ++m) t[m] = cconj(yr[P::k_of(m, kk) * YB]);
+            Dft<L>::run(t);
+            if constexpr (RS == 1) {
+#pragma unroll
+                for (int n = 0; n < L; ++n)
+                    if (n < box) y2[(bf * box + n) * YB + qy] = cconj(t[n]);
+            } else {
+                float2* gr = g2 + (r * L) * RS + kk;
+#pragma unroll
+                for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
+            }
+        }
+        __syncthreads();
+        if constexpr (RS > 1) {
+            for (int i = tid; i < NB * NF * boy * L; i += NT) {
+                const int n1 = i % L;
+                const int r = i / L;  // bf * boy + qy
+                const int qy = r % boy, bf = r / boy;
+                const float2* gr = g2 + (r * L + n1) * RS;
+                float2 t[RS];
+#pragma unroll
+                for (int k = 0; k < RS; ++k) t[k] = gr[k];
+                Dft<RS>::run(t);
+#pragma unroll
+                for (int n2 = 0; n2 < RS; ++n2) {
+                    const int qx = P::n_of(n1, n2);
+                    if (qx < box) y2[(bf * box + qx) * YB + qy] = cconj(t[n2]);
+                }
+            }
+            __syncthreads();
+        }
+        // I[q] = Re Y[q] + Im Y[q'] (mirror-pair unpacking, as in k_sp)
+        const int nq = box * boy;
+        for (int i = tid; i < NB * qtiles * NF * kTile; i += NT) {
+            const int qi = i % kTile;
+            int r = i / kTile;
+            const int fl2 = r % NF;
+            r /= NF;
+            const int qt = r % qtiles;
+            const int b = r / qtiles;
+            if (b >= nbv) continue;
+            const int q = qt * kTile + qi;
+            float2 vq = make_float2(0.f, 0.f);
+            if (q < nq) {
+                const int qx = q / boy, qy = q % boy;
+                const float2* yy = y2 + (b * NF + fl2) * box * YB;
+                vq = yy[qx * YB + qy];
+                if (A.mpcp) {
+                    const float2 yb = yy[(box - 1 - qx) * YB + (boy - 1 - qy)];
+                    vq = make_float2(vq.x + yb.y, vq.y - yb.x);
+                }
+            }
+            U[((((int64_t)(bl0 + b) * A.nc + c) * qtiles + qt) * A.ft + f0 + fl2) * kTile + qi] = vq;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_ti: inverse time FFT of each output pixel and response piece; the real part of
 // piece c lands at tick offset c * ct. The lane that owns tick a in piece c owned
 // it in every earlier piece (ct is a multiple of 64), so the overlap is added in
@@ -576,6 +893,20 @@ ConvArgs make_args(const tred_conv_plan* P) {
     A.mpcp = P->mpcp;
     A.chx = std::max(1, A.fs / A.By);
     A.cap = 0;
+    const int L = P->ls, RS = P->fs / P->ls;
+    if (P->pfa) {
+        // prime-factor output map k = (RS (RS^-1 mod L) k1 + L (L^-1 mod RS) k2) mod fs
+        int rsi = 0, li = 0;
+        for (int x = 0; x < L; ++x)
+            if ((RS * x) % L == 1 % L) { rsi = x; break; }
+        for (int x = 0; x < RS; ++x)
+            if ((L * x) % RS == 1 % RS) { li = x; break; }
+        A.e1 = (RS * rsi) % P->fs;
+        A.e2 = RS > 1 ? (L * li) % P->fs : 0;
+    } else {
+        A.e1 = RS;
+        A.e2 = 1;
+    }
     A.vblk = (int64_t)A.Bx * A.sx * A.NYf * A.Bt;
     A.vout = (int64_t)A.box * A.boy * A.bot;
     return A;
@@ -627,6 +958,47 @@ tred_status launch_space(const ConvArgs& A0, int b0, int nb, const int32_t* na, 
     hipLaunchKernelGGL((k_sp<FS, L>), dim3(nb, A.ft / S::NF), dim3(S::NT), lds, st, A, b0, nb, na, T,
                        rhat, tws, U);
     return tred_check_launch("tred_block_conv space");
+}
+
+template <int FS, int L, int NIN, int NB>
+tred_status launch_spp(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
+                       const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
+    using S = SppShape<FS, L, NIN, NB>;
+    const SppLds Ls = spp_lds<FS, L, NIN, NB, S::NF>(A.box, A.boy);
+    const size_t lds = (size_t)Ls.total * sizeof(float2);
+    if (lds > 160 * 1024) return tred_fail(TRED_EUNSUPPORTED, "spatial stage needs %zu B of LDS", lds);
+    allow_lds(k_spp<FS, L, NIN, NB>, lds);
+    hipLaunchKernelGGL((k_spp<FS, L, NIN, NB>), dim3((nb + NB - 1) / NB, A.ft / S::NF), dim3(S::NT),
+                       lds, st, A, b0, nb, na, T, rhat, tws, U);
+    return tred_check_launch("tred_block_conv space");
+}
+
+tred_status launch_space_any(const tred_conv_plan* P, const ConvArgs& A, int b0, int nb,
+                             const int32_t* na, const float2* T, const float2* rhat,
+                             const float2* tws, float2* U, hipStream_t st) {
+    constexpr int NB8 = TRED_SPP_NB8;
+    if (P->pfa) {
+        const bool two = P->nin == 2 * P->ls;
+        switch (P->fs) {
+            case 8: return launch_spp<8, 8, 8, 1>(A, b0, nb, na, T, rhat, tws, U, st);
+            case 16: return launch_spp<16, 16, 16, 1>(A, b0, nb, na, T, rhat, tws, U, st);
+            case 24:
+                return two ? launch_spp<24, 8, 16, NB8>(A, b0, nb, na, T, rhat, tws, U, st)
+                           : launch_spp<24, 8, 8, NB8>(A, b0, nb, na, T, rhat, tws, U, st);
+            case 40:
+                return two ? launch_spp<40, 8, 16, NB8>(A, b0, nb, na, T, rhat, tws, U, st)
+                           : launch_spp<40, 8, 8, NB8>(A, b0, nb, na, T, rhat, tws, U, st);
+            case 48:
+                return two ? launch_spp<48, 16, 32, 1>(A, b0, nb, na, T, rhat, tws, U, st)
+                           : launch_spp<48, 16, 16, 1>(A, b0, nb, na, T, rhat, tws, U, st);
+            default: return tred_fail(TRED_EUNSUPPORTED, "spatial size %d", P->fs);
+        }
+    }
+    switch (P->fs) {
+        case 32: return launch_space<32, 16>(A, b0, nb, na, T, rhat, tws, U, st);
+        case 64: return launch_space<64, 16>(A, b0, nb, na, T, rhat, tws, U, st);
+        default: return tred_fail(TRED_EUNSUPPORTED, "spatial size %d", P->fs);
+    }
 }
 
 template <typename F>
@@ -686,6 +1058,9 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     if (ft < Bt + 64) return bad(TRED_EINVAL, "time FFT size must be >= blk_ticks + 64");
     P->fs = fsx;
     P->ls = L;
+    P->pfa = (fsx % 32) != 0;   // 8, 16, 24, 40, 48: fs / L is 1 or odd, coprime to L
+    P->nin = std::max(Bx, By) <= L ? L : 2 * L;
+    P->spp_nb = L == 8 ? TRED_SPP_NB8 : 1;
     P->ft = ft;
     P->ct = ft - Bt;
     P->nc = (kticks + P->ct - 1) / P->ct;
@@ -817,17 +1192,7 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
         }));
         mark(b0, 1);
         mark(b0, 2);
-        tred_status s;
-        switch (P->fs) {
-            case 8: s = launch_space<8, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 16: s = launch_space<16, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 24: s = launch_space<24, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 32: s = launch_space<32, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 40: s = launch_space<40, 8>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            case 48: s = launch_space<48, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-            default: s = launch_space<64, 16>(A, b0, nb, n_active, T, rhat, tws, U, st); break;
-        }
-        TRED_TRY(s);
+        TRED_TRY(launch_space_any(P, A, b0, nb, n_active, T, rhat, tws, U, st));
         mark(b0, 3);
         mark(b0, 4);
         TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {

@@ -181,25 +181,36 @@ struct Idx3 {
     }
 };
 
-template <int NGL, int CAP>
-__global__ __launch_bounds__(256) void k_effq(EffqParams P, int64_t n_dep,
-                                              const float* __restrict__ seg,
-                                              const int32_t* __restrict__ fp,
-                                              const int64_t* __restrict__ off,
-                                              float* __restrict__ val, int64_t val_cap,
-                                              double* __restrict__ charge_sum) {
+// One workgroup of NT threads per deposition (grid-stride over depositions). The
+// footprint is cut into tiles; for a tile of cells [X0, X1] x [Y0, Y1] x [Z0, Z1]
+// the node charges w * q of the cells one beyond the tile on every side (zero for
+// cells outside the quadrature window) are evaluated once into LDS, so that the
+// spread stencil of every output cell (the S = NGL + 2 (NGL / 2) nodes per axis of
+// cells g-1, g, g+1 that reach g) lies inside the tile and the 3-D gather is fully
+// unrolled with constant offsets.
+template <int NGL, int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
+                                             const float* __restrict__ seg,
+                                             const int32_t* __restrict__ fp,
+                                             const int64_t* __restrict__ off,
+                                             float* __restrict__ val, int64_t val_cap,
+                                             double* __restrict__ charge_sum) {
     constexpr int N3 = NGL * NGL * NGL;
     constexpr int NPOS = NGL / 2;                 // nodes with xi > 0 in a cell
+    constexpr int S = NGL + 2 * NPOS;             // stencil nodes per axis
+    constexpr int NW = NT / kWave;
     __shared__ float V[CAP];
-    __shared__ double red[4];
-    __shared__ float sxi[8], sw[8], su[16];
+    __shared__ double red[NW];
+    __shared__ float sxi[8], sw[8];
     const int tid = threadIdx.x;
     const tred_grid& g = P.g;
     if (tid < 8) {
         sxi[tid] = P.xi[tid];
         sw[tid] = P.w[tid];
     }
-    if (tid < 16) su[tid] = P.u[tid];
+    float su[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) su[k] = P.u[k];
     __syncthreads();
 
     for (int64_t d = blockIdx.x; d < n_dep; d += gridDim.x) {
@@ -256,7 +267,7 @@ __global__ __launch_bounds__(256) void k_effq(EffqParams P, int64_t n_dep,
         }
         const float jac = (float)(h[0] * h[1] * h[2] / 8.0);
 
-        // node cells that can reach the footprint: window intersected with F +- 1
+        // cells whose nodes are evaluated: the quadrature window (intersected with F +- 1)
         int C0[3], C1[3], Fs[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -266,15 +277,14 @@ __global__ __launch_bounds__(256) void k_effq(EffqParams P, int64_t n_dep,
         }
         // tile: whole footprint in x, y when it fits, as many ticks as fit
         int T[3] = {Fs[0], Fs[1], Fs[2]};
-        auto ncell = [&](int a, int len) { return min(len + 2, C1[a] - C0[a] + 1); };
-        while (N3 * ncell(0, T[0]) * ncell(1, T[1]) * ncell(2, 1) > CAP && (T[0] > 1 || T[1] > 1)) {
+        while (N3 * (T[0] + 2) * (T[1] + 2) * 3 > CAP && (T[0] > 1 || T[1] > 1)) {
             if (T[0] >= T[1]) T[0] = (T[0] + 1) / 2;
             else T[1] = (T[1] + 1) / 2;
         }
         {
-            int per = N3 * ncell(0, T[0]) * ncell(1, T[1]);
+            const int per = N3 * (T[0] + 2) * (T[1] + 2);
             int tt = 1;
-            while (tt < Fs[2] && per * ncell(2, tt + 1) <= CAP) ++tt;
+            while (tt < Fs[2] && per * (tt + 3) <= CAP) ++tt;
             T[2] = tt;
         }
         const int64_t FY = Fs[1], FT = Fs[2];
@@ -287,75 +297,92 @@ __global__ __launch_bounds__(256) void k_effq(EffqParams P, int64_t n_dep,
                     const int Y1 = min(Y0 + T[1] - 1, F1[1]);
                     const int Z1 = min(Z0 + T[2] - 1, F1[2]);
                     const int t0c[3] = {X0, Y0, Z0}, t1c[3] = {X1, Y1, Z1};
-                    int c0[3], nn[3], own0[3], own1[3];
+                    int nn[3], own0[3], own1[3];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        c0[a] = max(C0[a], t0c[a] - 1);
-                        const int c1 = min(C1[a], t1c[a] + 1);
-                        nn[a] = (c1 - c0[a] + 1) * NGL;
+                        nn[a] = (t1c[a] - t0c[a] + 3) * NGL;   // cells t0c-1 .. t1c+1
                         // cells whose nodes this tile counts in the charge sum
-                        own0[a] = t0c[a] == F0[a] ? t0c[a] - 1 : t0c[a];
-                        own1[a] = t1c[a] == F1[a] ? t1c[a] + 1 : t1c[a];
+                        own0[a] = max(t0c[a] == F0[a] ? t0c[a] - 1 : t0c[a], C0[a]);
+                        own1[a] = min(t1c[a] == F1[a] ? t1c[a] + 1 : t1c[a], C1[a]);
                     }
                     const int total = nn[0] * nn[1] * nn[2];
-                    // 1) node charges w * q(node) into LDS
+                    // 1) node charges w * q(node) into LDS (zero outside the window)
                     {
                         Idx3 it;
-                        it.init(tid, 256, nn[1], nn[2]);
-                        for (int i = tid; i < total; i += 256, it.next()) {
-                            const int cx = c0[0] + it.i / NGL, lx = it.i % NGL;
-                            const int cy = c0[1] + it.j / NGL, ly = it.j % NGL;
-                            const int ct = c0[2] + it.k / NGL, lt = it.k % NGL;
-                            const float rx = fb[0] + ((float)(cx - W.lo[0]) + 0.5f * sxi[lx]) * fh[0];
-                            const float ry = fb[1] + ((float)(cy - W.lo[1]) + 0.5f * sxi[ly]) * fh[1];
-                            const float rt = fb[2] + ((float)(ct - W.lo[2]) + 0.5f * sxi[lt]) * fh[2];
-                            float q;
-                            if (point) {
-                                const float e = rx * rx * isg2[0] + ry * ry * isg2[1] + rt * rt * isg2[2];
-                                q = pref * expf(-0.5f * e);
-                            } else {
-                                const float beta = rx * gvec[0] + ry * gvec[1] + rt * gvec[2];
-                                const float sst = beta * inv_alpha;       // closest point on the line
-                                const float px = rx - sst * fd[0], py = ry - sst * fd[1],
-                                            pt = rt - sst * fd[2];
-                                const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
-                                q = pref * expf(-0.5f * e) * erf_diff(kq * (1.0f - sst), -kq * sst);
+                        it.init(tid, NT, nn[1], nn[2]);
+                        for (int i = tid; i < total; i += NT, it.next()) {
+                            const int cx = X0 - 1 + it.i / NGL, lx = it.i % NGL;
+                            const int cy = Y0 - 1 + it.j / NGL, ly = it.j % NGL;
+                            const int ct = Z0 - 1 + it.k / NGL, lt = it.k % NGL;
+                            const bool inside = cx >= C0[0] && cx <= C1[0] && cy >= C0[1] &&
+                                                cy <= C1[1] && ct >= C0[2] && ct <= C1[2];
+                            float vq = 0.0f;
+                            if (inside) {
+                                float xx, xy, xt, wt;
+                                if constexpr (NGL == 2) {
+                                    // nodes -+1/sqrt(3), weights 1
+                                    constexpr float xi2 = 0.57735026918962576f;
+                                    xx = lx ? xi2 : -xi2;
+                                    xy = ly ? xi2 : -xi2;
+                                    xt = lt ? xi2 : -xi2;
+                                    wt = 1.0f;
+                                } else {
+                                    xx = sxi[lx];
+                                    xy = sxi[ly];
+                                    xt = sxi[lt];
+                                    wt = sw[lx] * sw[ly] * sw[lt];
+                                }
+                                const float rx = fb[0] + ((float)(cx - W.lo[0]) + 0.5f * xx) * fh[0];
+                                const float ry = fb[1] + ((float)(cy - W.lo[1]) + 0.5f * xy) * fh[1];
+                                const float rt = fb[2] + ((float)(ct - W.lo[2]) + 0.5f * xt) * fh[2];
+                                float q;
+                                if (point) {
+                                    const float e = rx * rx * isg2[0] + ry * ry * isg2[1] + rt * rt * isg2[2];
+                                    q = pref * expf(-0.5f * e);
+                                } else {
+                                    const float beta = rx * gvec[0] + ry * gvec[1] + rt * gvec[2];
+                                    const float sst = beta * inv_alpha;       // closest point on the line
+                                    const float px = rx - sst * fd[0], py = ry - sst * fd[1],
+                                                pt = rt - sst * fd[2];
+                                    const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
+                                    q = pref * expf(-0.5f * e) * erf_diff(kq * (1.0f - sst), -kq * sst);
+                                }
+                                vq = wt * jac * q;
+                                if (cx >= own0[0] && cx <= own1[0] && cy >= own0[1] && cy <= own1[1] &&
+                                    ct >= own0[2] && ct <= own1[2])
+                                    nsum += (double)vq;
                             }
-                            const float vq = sw[lx] * sw[ly] * sw[lt] * jac * q;
                             V[i] = vq;
-                            if (cx >= own0[0] && cx <= own1[0] && cy >= own0[1] && cy <= own1[1] &&
-                                ct >= own0[2] && ct <= own1[2])
-                                nsum += (double)vq;
                         }
                     }
                     __syncthreads();
-                    // 2) each footprint cell gathers the spread of its 27-cell neighbourhood
+                    // 2) each footprint cell gathers the spread of its stencil nodes
                     {
                         const int nx = X1 - X0 + 1, ny = Y1 - Y0 + 1, nz = Z1 - Z0 + 1;
                         const int count = nx * ny * nz;
+                        const int sxs = nn[1] * nn[2], sys = nn[2];
                         Idx3 it;
-                        it.init(tid, 256, ny, nz);
-                        for (int k = tid; k < count; k += 256, it.next()) {
-                            const int gx = X0 + it.i, gy = Y0 + it.j, gz = Z0 + it.k;
-                            const int fx = (gx - 1 - c0[0]) * NGL + (NGL - NPOS);
-                            const int fy = (gy - 1 - c0[1]) * NGL + (NGL - NPOS);
-                            const int fz = (gz - 1 - c0[2]) * NGL + (NGL - NPOS);
-                            constexpr int S = NGL + 2 * NPOS;
-                            const int ax0 = max(fx, 0), ax1 = min(fx + S - 1, nn[0] - 1);
-                            const int ay0 = max(fy, 0), ay1 = min(fy + S - 1, nn[1] - 1);
-                            const int az0 = max(fz, 0), az1 = min(fz + S - 1, nn[2] - 1);
+                        it.init(tid, NT, ny, nz);
+                        for (int k = tid; k < count; k += NT, it.next()) {
+                            // first stencil node of cell g: node NGL - NPOS of cell g - 1
+                            const float* vb = V + (it.i * NGL + (NGL - NPOS)) * sxs +
+                                              (it.j * NGL + (NGL - NPOS)) * sys + it.k * NGL + (NGL - NPOS);
                             float acc = 0.0f;
-                            for (int x = ax0; x <= ax1; ++x) {
+#pragma unroll
+                            for (int a = 0; a < S; ++a) {
                                 float ay = 0.0f;
-                                for (int y = ay0; y <= ay1; ++y) {
-                                    const float* vr = V + (x * nn[1] + y) * nn[2];
+#pragma unroll
+                                for (int b = 0; b < S; ++b) {
+                                    const float* vr = vb + a * sxs + b * sys;
                                     float az = 0.0f;
-                                    for (int z = az0; z <= az1; ++z) az += su[z - fz] * vr[z];
-                                    ay += su[y - fy] * az;
+#pragma unroll
+                                    for (int c = 0; c < S; ++c) az = fmaf(su[c], vr[c], az);
+                                    ay = fmaf(su[b], az, ay);
                                 }
-                                acc += su[x - fx] * ay;
+                                acc = fmaf(su[a], ay, acc);
                             }
-                            val[o0 + ((int64_t)(gx - F0[0]) * FY + (gy - F0[1])) * FT + (gz - F0[2])] = acc;
+                            val[o0 + ((int64_t)(X0 + it.i - F0[0]) * FY + (Y0 + it.j - F0[1])) * FT +
+                                (Z0 + it.k - F0[2])] = acc;
                         }
                     }
                     __syncthreads();
@@ -365,7 +392,12 @@ __global__ __launch_bounds__(256) void k_effq(EffqParams P, int64_t n_dep,
             for (int o = 32; o > 0; o >>= 1) nsum += __shfl_down(nsum, o, kWave);
             if ((tid & 63) == 0) red[tid >> 6] = nsum;
             __syncthreads();
-            if (tid == 0) atomicAdd(charge_sum, red[0] + red[1] + red[2] + red[3]);
+            if (tid == 0) {
+                double tsum = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) tsum += red[w];
+                atomicAdd(charge_sum, tsum);
+            }
             __syncthreads();
         }
     }
@@ -405,9 +437,10 @@ void gl_rule(int n, double* xi, double* w) {
 template <int NGL>
 void launch_effq(const EffqParams& P, int64_t n_dep, const float* seg, const int32_t* fp,
                  const int64_t* off, float* val, int64_t val_cap, double* cs, hipStream_t st) {
-    constexpr int CAP = 16384;
+    constexpr int CAP = 16384;   // node charges of one tile (64 KiB of LDS)
+    constexpr int NT = 512;
     int64_t grid = n_dep < (1 << 20) ? n_dep : (1 << 20);
-    hipLaunchKernelGGL((k_effq<NGL, CAP>), dim3((unsigned)grid), dim3(256), 0, st, P, n_dep, seg,
+    hipLaunchKernelGGL((k_effq<NGL, CAP, NT>), dim3((unsigned)grid), dim3(NT), 0, st, P, n_dep, seg,
                        fp, off, val, val_cap, cs);
 }
 

@@ -102,6 +102,48 @@ struct Dft<4> {
     }
 };
 
+// 3- and 5-point DFTs (the odd factors of the prime-factor spatial transforms);
+// constants are the correctly rounded binary32 values of cos/sin of 2 pi k / R.
+namespace cst {
+constexpr float h3 = 0.86602540378443865f;   // sin(2 pi / 3)
+constexpr float c51 = 0.30901699437494742f;  // cos(2 pi / 5)
+constexpr float c52 = -0.80901699437494742f; // cos(4 pi / 5)
+constexpr float s51 = 0.95105651629515357f;  // sin(2 pi / 5)
+constexpr float s52 = 0.58778525229247313f;  // sin(4 pi / 5)
+}  // namespace cst
+
+template <>
+struct Dft<3> {
+    __device__ __forceinline__ static void run(float2* x) {
+        const float2 s = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+        const float2 m = make_float2(x[0].x - 0.5f * s.x, x[0].y - 0.5f * s.y);
+        x[0] = cadd(x[0], s);
+        x[1] = make_float2(m.x + cst::h3 * d.y, m.y - cst::h3 * d.x);
+        x[2] = make_float2(m.x - cst::h3 * d.y, m.y + cst::h3 * d.x);
+    }
+};
+
+template <>
+struct Dft<5> {
+    __device__ __forceinline__ static void run(float2* x) {
+        const float2 a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+        const float2 a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+        const float2 x0 = x[0];
+        // real-coefficient parts and the quadrature parts (multiplied by -i below)
+        const float2 r1 = make_float2(x0.x + cst::c51 * a1.x + cst::c52 * a2.x,
+                                      x0.y + cst::c51 * a1.y + cst::c52 * a2.y);
+        const float2 r2 = make_float2(x0.x + cst::c52 * a1.x + cst::c51 * a2.x,
+                                      x0.y + cst::c52 * a1.y + cst::c51 * a2.y);
+        const float2 q1 = make_float2(cst::s51 * b1.x + cst::s52 * b2.x, cst::s51 * b1.y + cst::s52 * b2.y);
+        const float2 q2 = make_float2(cst::s52 * b1.x - cst::s51 * b2.x, cst::s52 * b1.y - cst::s51 * b2.y);
+        x[0] = make_float2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+        x[1] = cadd(r1, cmul_mi(q1));
+        x[4] = csub(r1, cmul_mi(q1));
+        x[2] = cadd(r2, cmul_mi(q2));
+        x[3] = csub(r2, cmul_mi(q2));
+    }
+};
+
 // radix-2 split of an R-point DFT into two R/2-point DFTs (R = 8, 16)
 template <int R>
 struct Dft {
@@ -126,6 +168,54 @@ struct Dft {
         comb<0>(x, e, o);
     }
 };
+
+// c + a * b as four fused multiply-adds
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
+    c.x = fmaf(a.x, b.x, c.x);
+    c.x = fmaf(-a.y, b.y, c.x);
+    c.y = fmaf(a.x, b.y, c.y);
+    c.y = fmaf(a.y, b.x, c.y);
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Prime-factor (Good-Thomas) index maps of an FS-point DFT with FS = L * RS and
+// gcd(L, RS) = 1. Input n <-> (n1, n2) with n = (RS n1 + L n2) mod FS; output
+// k <-> (k1, k2) = (k mod L, k mod RS). Then
+//   X[k] = sum_n1 W_L^(n1 k1) sum_n2 W_RS^(n2 k2) x[n(n1, n2)]
+// with no twiddle factors between the L- and RS-point stages.
+// ---------------------------------------------------------------------------
+template <int L, int RS>
+struct Pfa {
+    static constexpr int FS = L * RS;
+    static constexpr int inv(int a, int m) {
+        for (int x = 0; x < m; ++x)
+            if ((a * x) % m == 1 % m) return x;
+        return -1;
+    }
+    static constexpr int RSi = inv(RS % L, L);            // RS^-1 mod L
+    static constexpr int Li = RS > 1 ? inv(L % RS, RS) : 0;  // L^-1 mod RS
+    static_assert(RSi >= 0 && Li >= 0, "L and RS must be coprime");
+    __host__ __device__ static constexpr int n1(int n) { return (n * RSi) % L; }
+    __host__ __device__ static constexpr int n2(int n) { return RS > 1 ? (n * Li) % RS : 0; }
+    __host__ __device__ static constexpr int n_of(int a, int b) { return (RS * a + L * b) % FS; }
+    __host__ __device__ static constexpr int k_of(int k1, int k2) {
+        return (RS * RSi * k1 + L * Li * k2) % FS;
+    }
+};
+
+// t[n1] = sum over inputs n < NIN with n1(n) = n1 of x[n] W_RS^(n2(n) k2), where
+// w[j] = W_RS^(j k2) (w[0] = 1); NIN <= 2 L, every n1 receives an input n < L.
+template <int L, int RS, int NIN>
+__device__ __forceinline__ void pfa_gather(const float2* x, const float2* w, float2* t) {
+    using P = Pfa<L, RS>;
+#pragma unroll
+    for (int n = 0; n < NIN; ++n) {
+        const int a = P::n1(n), b = P::n2(n);
+        if (n < L) t[a] = b == 0 ? x[n] : cmul(x[n], w[b]);
+        else t[a] = b == 0 ? cadd(t[a], x[n]) : cfma(x[n], w[b], t[a]);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Per-wavefront Stockham FFT of length N = 64 * M (M in {4, 8, 16, 32, 64}).
@@ -227,6 +317,9 @@ struct tred_conv_plan {
     int32_t kticks;
     int32_t fs;          // spatial FFT size (square)
     int32_t ls;          // length of the register sub-DFTs of the spatial transform
+    int32_t pfa;         // spatial stage by prime-factor maps (fs = ls * RS, coprime)
+    int32_t nin;         // inputs per axis of the prime-factor stage (ls or 2 ls)
+    int32_t spp_nb;      // bins per workgroup of the prime-factor stage
     int32_t ft;          // time FFT size
     int32_t ct;          // response ticks per piece
     int32_t nc;          // response pieces

@@ -334,6 +334,35 @@ class Pipeline:
                     wf=self.wf[:min(npx, self.pix.shape[0])].cpu().numpy())
 
 
+def plan_workspace_bytes(grid, blocking, kpix, kticks, fft=None, mpcp=True, batch=1) -> int:
+    """Device workspace of a convolution plan (host query, nothing allocated)."""
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    kp = (C.c_int32 * 2)(*kpix)
+    ff = (C.c_int32 * 3)(*(fft or (0, 0, 0)))
+    h = C.c_void_p()
+    ws = C.c_int64()
+    _check(lib().tred_conv_plan_create(C.byref(g), C.byref(b), kp, int(kticks), ff,
+                                       TRED_CONV_MPCP if mpcp else 0, int(batch), C.byref(h),
+                                       C.byref(ws)))
+    lib().tred_conv_plan_destroy(h)
+    return int(ws.value)
+
+
+def conv_batch(grid, blocking, kpix, kticks, fft, mpcp, n_bins, scratch_bytes) -> int:
+    """Bins per convolution pass whose scratch fits `scratch_bytes` (at most n_bins):
+    the plan's per-bin scratch is its workspace growth per bin at large batches (at
+    small batches the response set-up scratch, shared with the pass scratch, dominates)."""
+    w1 = plan_workspace_bytes(grid, blocking, kpix, kticks, fft, mpcp, 1 << 16)
+    w2 = plan_workspace_bytes(grid, blocking, kpix, kticks, fft, mpcp, 1 << 17)
+    per_bin = max(1, -(-(w2 - w1) // (1 << 16)))
+    return int(max(1, min(int(n_bins), int(scratch_bytes) // per_bin)))
+
+
+# Scratch budget of the convolution on one MI355X (288 GB of HBM): the module-scale
+# event (about 850 active bins, ~150 MB of spectra per bin) runs in one pass.
+DEFAULT_CONV_SCRATCH = 160e9
+
+
 def size_event(grid, phys, blocking, kpix, seg):
     """Capacities of one event: exact patch length and active-bin count (footprint
     step plus a counting pass of the binning, then one synchronisation), and the

@@ -259,8 +259,15 @@ def module_run(T):
     cfg = W.cfg_module()
     seg = W.gen_segments(cfg)
     resp = W.synthetic_response(cfg.kpix, cfg.grid.sub, cfg.kticks)
+    # the launch configuration bench.py times: bins per pass from the same scratch budget
+    import torch
+    _, bcap, _ = T.size_event(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix,
+                              torch.from_numpy(seg).cuda())
+    batch = T.conv_batch(cfg.grid, cfg.blocking, cfg.kpix, cfg.kticks, cfg.fft, True, bcap,
+                         T.DEFAULT_CONV_SCRATCH)
+    say(f"  {bcap} active bins, {batch} bins per convolution pass")
     r = gpu_path(T, cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, cfg.fft, seg, resp,
-                 mpcp=True, batch=64)
+                 mpcp=True, batch=batch)
     return cfg, seg, resp, r
 
 
