@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector: 256 CU x 128 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 
 
 class HipEvents:
@@ -121,6 +122,73 @@ def cpu_baseline(cfg, seg, resp, n_sample, seed=0):
                        f"(effective charge, binning, direct convolution, waveforms): {dt:.1f} s")
 
 
+def bench_direct(args, split):
+    """Block-direct convolution on BF16 matrix cores (hi/lo split or plain) beside the FP32
+    FFT convolution on the same bins: the whole 1,000-deposition event and a sample of
+    bins of the module-scale event. Prints one JSON line (not the benchmark's main line)."""
+    import torch
+    import workloads as W
+    from paper_2602_12052_amd import tred
+    stream = torch.cuda.current_stream().cuda_stream
+    ev = HipEvents(4)
+    forms = []
+    for name, cfg, nbins in (("plain-small-1k", W.cfg_plain_small(args.seed), None),
+                             ("module-1e5", W.cfg_module(args.seed), args.direct_bins)):
+        seg = W.gen_segments(cfg)
+        resp = W.synthetic_response(cfg.kpix, cfg.grid.sub, cfg.kticks)
+        sd = torch.from_numpy(seg).cuda()
+        dresp = torch.from_numpy(resp).cuda()
+        val_cap, bcap, pix_cap = tred.size_event(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, sd)
+        n = bcap if nbins is None else min(nbins, bcap)
+        pl = tred.Pipeline(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, dresp,
+                           seg.shape[0], val_cap, bcap, pix_cap, cfg.fft, True, n)
+        pl.run(sd, stop_after="bin")
+        nact = torch.tensor([n], dtype=torch.int32, device="cuda")
+        blocks = pl.blocks[:n]
+        dp = tred.DirectPlan(cfg.grid, cfg.blocking, cfg.kpix, cfg.kticks, split=split, batch=n)
+        dp.set_response(dresp)
+        out_d = torch.empty((n, pl.out_blocks.shape[1]), dtype=torch.float32, device="cuda")
+        out_f = torch.empty_like(out_d)
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                ev.record(0, stream)
+                fn()
+                ev.record(1, stream)
+                ts.append(ev.ms(0, 1))
+            return float(np.median(ts))
+
+        reps = max(1, args.steps)
+        t_d = timed(lambda: tred.tred_block_conv_direct(dp, nact, blocks, out_d, stream=stream), reps)
+        t_f = timed(lambda: tred.tred_block_conv(pl.plan, nact, blocks, out_f, stream), reps)
+        torch.cuda.synchronize()
+        d, f = out_d.double(), out_f.double()
+        err = float(torch.linalg.norm(d - f) / torch.linalg.norm(f))
+        Bx, By = cfg.blocking.blk_pix
+        S = cfg.grid.sub[0] * cfg.grid.sub[1]
+        useful = 2.0 * n * (Bx * By * S * cfg.blocking.blk_ticks) * (cfg.kpix[0] * cfg.kpix[1] * cfg.kticks)
+        prods = 3 if split else 1
+        forms.append({
+            "workload": name, "bins": n, "direct_ms": t_d, "direct_ms_per_bin": t_d / n,
+            "fft_fp32_ms": t_f, "fft_fp32_ms_per_bin": t_f / n,
+            "mfma_useful_tflop": useful * prods / 1e12,
+            "mfma_achieved_tflops": useful * prods / (t_d * 1e-3) / 1e12,
+            "mfma_frac_of_bf16_peak": useful * prods / (t_d * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+            "rel_l2_vs_fft_fp32": err,
+        })
+        print(f"# {name}: {forms[-1]}", file=sys.stderr, flush=True)
+        del pl, dp, out_d, out_f
+        torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": "block-direct convolution on BF16 MFMA (%s) beside the FP32 FFT path" %
+                  ("hi/lo split, 3 products" if split else "plain BF16"),
+        "unit": "ms", "dtype": "bf16x3" if split else "bf16", "data": "synthetic",
+        "peak_tflops": BF16_MFMA_PEAK_TFLOPS, "forms": forms}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +202,11 @@ def main():
                     help="bound on the convolution scratch (sets the bins per pass)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--form", default="fft", choices=["fft", "direct-split", "direct-bf16"],
+                    help="fft: the benchmark line; direct-*: block-direct convolution on BF16 "
+                         "matrix cores beside the FFT path (separate JSON line)")
+    ap.add_argument("--direct-bins", type=int, default=8,
+                    help="module-event bins timed by the direct forms")
     args = ap.parse_args()
     if args.scratch_gb is None:
         from paper_2602_12052_amd import tred as _t
@@ -153,6 +226,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}))
+        return
+
+    if args.form != "fft":
+        bench_direct(args, args.form == "direct-split")
         return
 
     import workloads as W
@@ -229,7 +306,7 @@ def main():
     sp_ms = float(conv_stages[:, 1].mean())
     achieved = fl["sp"] * sp_blocks / (sp_ms * 1e-3) / 1e12
     sha = src_sha(["paper_2602_12052_amd/csrc/conv.hip", "paper_2602_12052_amd/csrc/tred_internal.hpp"])
-    traffic = profile_traffic("k_sp", sha)
+    traffic = profile_traffic("k_spp", sha)
     vblk = Bx * cfg.grid.sub[0] * By * cfg.grid.sub[1] * Bt
     vout = box * boy * (Bt + cfg.kticks - 1)
     lwf = cfg.grid.nticks + cfg.kticks - 1
@@ -264,7 +341,7 @@ def main():
                      "conv_space_mac": float(conv_stages[:, 1].mean()),
                      "conv_time_inv": float(conv_stages[:, 2].mean())},
         "roofline": {
-            "kernel": "k_sp (spatial transforms + spectral multiply-accumulate)",
+            "kernel": "k_spp<40,8,16,2> (spatial transforms + spectral multiply-accumulate)",
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
             "flops_per_launch": fl["sp"] * sp_blocks, "avg_launch_ms": sp_ms,

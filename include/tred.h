@@ -218,6 +218,38 @@ tred_status tred_scatter_waveforms(const tred_conv_plan* plan, const int32_t* ke
 
 void tred_conv_plan_destroy(tred_conv_plan* plan);
 
+/* ------------------------------------------------------------------------- */
+/* Block-direct interlaced convolution on the matrix cores: the same operation and
+ * output as tred_block_conv (Sec. II-D eq. interlaced), evaluated per bin as the
+ * dense contraction out[p + k][t'] = sum_{j, tau} Q_j[p][t' - tau] R_j[k][tau]
+ * on BF16 matrix instructions with FP32 accumulation (no transforms).
+ * flags: TRED_DIRECT_SPLIT represents each operand x as hi + lo with hi = bf16(x),
+ * lo = bf16(x - hi) and accumulates hi*hi + hi*lo + lo*hi (about 16 significant
+ * bits per product); without it the operands are rounded to BF16 (8 bits).
+ * batch: bins per pass (1 <= batch <= 65535); bounds the operand scratch.
+ * workspace_bytes out: device bytes for set_response (BF16 response operands and
+ * the charge operands of one pass). Outputs are accumulated with atomic adds, so
+ * float sums are in an unspecified order; out_blocks rows of the active bins are
+ * overwritten. The response may be of any shape (no symmetry needed); kpix odd.
+ * Output rows are [cap][blk_pix[0]+kpix[0]-1][blk_pix[1]+kpix[1]-1][blk_ticks+kticks-1]
+ * as for tred_block_conv, so tred_scatter_waveforms (with a tred_conv_plan of the
+ * same geometry, which needs no response) forms the waveforms. */
+typedef struct tred_direct_plan tred_direct_plan;
+#define TRED_DIRECT_SPLIT 1u
+
+tred_status tred_direct_plan_create(const tred_grid* grid, const tred_blocking* blocking,
+                                    const int32_t kpix[2], int32_t kticks, uint32_t flags,
+                                    int32_t batch, tred_direct_plan** plan,
+                                    int64_t* workspace_bytes);
+/* Convert the response to BF16 operands in `workspace` (256-byte aligned; kept by
+ * the plan). Synchronises `stream`. */
+tred_status tred_direct_plan_set_response(tred_direct_plan* plan, const float* resp,
+                                          void* workspace, void* stream);
+tred_status tred_block_conv_direct(const tred_direct_plan* plan, const int32_t* n_active,
+                                   int32_t cap, const float* blocks, float* out_blocks,
+                                   void* stream);
+void tred_direct_plan_destroy(tred_direct_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

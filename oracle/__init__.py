@@ -7,9 +7,10 @@ suite, the smoke check and the benchmark's CPU-baseline leg may import it; the
 GPU library never does, and this package never imports the GPU library.
 
 The arithmetic lives in ``oracle.c`` (binary64, OpenMP over depositions or
-pixels); this module builds it with gcc and wraps it with ctypes. The one
-function written here in numpy, :func:`pix_set`, is the plain definition of the
-output pixel set.
+pixels); this module builds it with gcc and wraps it with ctypes. Written here in
+numpy are the plain definitions of the output pixel set (:func:`pix_set`), of the
+depositions reaching one bin (:func:`bin_members`) and of one bin's convolution
+output at isolated samples (:func:`block_output_points`).
 """
 from __future__ import annotations
 
@@ -293,6 +294,45 @@ def simulate(grid, physics, blocking, kpix, kticks, resp, seg):
     pix = pix_set(grid, blocking, kpix, keys)
     wf = waveforms(grid, kpix, kticks, resp, fp, off, val, pix)
     return dict(fp=fp, off=off, is_point=ip, val=val, node_sums=ns, keys=keys, pix=pix, wf=wf)
+
+
+def bin_members(grid, blocking, fp, key) -> np.ndarray:
+    """Indices of the depositions whose footprint has a cell in bin `key` (Sec. III-B:
+    a bin collects every patch cell inside its box)."""
+    fp = np.asarray(fp).reshape(-1, 6)
+    bf = (blocking.blk_pix[0] * grid.sub[0], blocking.blk_pix[1] * grid.sub[1], blocking.blk_ticks)
+    keep = np.ones(fp.shape[0], bool)
+    for a in range(3):
+        lo, hi = key[a] * bf[a], key[a] * bf[a] + bf[a] - 1
+        keep &= (fp[:, a] <= fp[:, 3 + a]) & (fp[:, a] <= hi) & (fp[:, 3 + a] >= lo)
+    return np.nonzero(keep)[0]
+
+
+def block_output_points(grid, blocking, kpix, kticks, resp, bvals, pts) -> np.ndarray:
+    """One bin's contribution to the induced current (Sec. II-D, eq. interlaced, summed
+    over the bin's cells only) at samples pts [m, 3] = (qx, qy, t') in the bin's output
+    frame: pixel (bx Bx - (Kx-1)/2 + qx, by By - (Ky-1)/2 + qy), tick bt Bt + t'.
+    bvals [Bx sx][By sy][Bt] is the bin's effective charge (binary64). With charge at
+    fine cell (px sx + jx, py sy + jy, t): out += Q * R[qx - px][qy - py][jx][jy][t' - t]."""
+    sx, sy = grid.sub
+    Bx, By = blocking.blk_pix
+    Bt = blocking.blk_ticks
+    Kx, Ky = kpix
+    R = np.asarray(resp, np.float64).reshape(Kx, Ky, sx, sy, kticks)
+    Q = np.asarray(bvals, np.float64).reshape(Bx, sx, By, sy, Bt)
+    out = np.zeros(len(pts))
+    for m, (qx, qy, tq) in enumerate(np.asarray(pts).reshape(-1, 3)):
+        t_lo, t_hi = max(0, tq - kticks + 1), min(Bt - 1, tq)
+        if t_lo > t_hi:
+            continue
+        acc = 0.0
+        for px in range(max(0, qx - Kx + 1), min(Bx - 1, qx) + 1):
+            for py in range(max(0, qy - Ky + 1), min(By - 1, qy) + 1):
+                q = Q[px, :, py, :, t_lo:t_hi + 1]                       # [sx, sy, nt]
+                r = R[qx - px, qy - py][:, :, tq - t_hi:tq - t_lo + 1][:, :, ::-1]
+                acc += float(np.sum(q * r))
+        out[m] = acc
+    return out
 
 
 def select_near(fp, sub, kpix, kticks, pts, margin_pix: int = 0) -> np.ndarray:

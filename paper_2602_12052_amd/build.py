@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtred.so")
-SOURCES = ["api.cpp", "effq.hip", "bin.hip", "conv.hip", "scatter.hip"]
+SOURCES = ["api.cpp", "effq.hip", "bin.hip", "conv.hip", "scatter.hip", "direct.hip"]
 ARCH = "gfx950"
 
 

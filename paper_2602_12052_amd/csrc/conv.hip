@@ -24,6 +24,10 @@
 #ifndef TRED_SPP_NB8
 #define TRED_SPP_NB8 2
 #endif
+// wave-level ordering inside the inverse time FFTs (1) or workgroup barriers (0)
+#ifndef TRED_TI_WAVESYNC
+#define TRED_TI_WAVESYNC 1
+#endif
 
 namespace {
 
@@ -197,7 +201,8 @@ __global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* _
                 if (m < mb) v[m].y = r1[lane + kWave * m];
         }
     }
-    wave_fft<FT>(v, lds + wv * kFftLds<FT>, tw, lane);
+    wave_fft<FT, true>(v, lds + wv * kFftLds<FT>, tw, lane);
+    __syncthreads();   // the staging tile overlaps the other waves' FFT scratch
     float2* stage = (float2*)lds;
 #pragma unroll
     for (int m = 0; m < M; ++m) stage[(lane + kWave * m) * kTile + wv] = v[m];
@@ -804,8 +809,10 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
 // it in every earlier piece (ct is a multiple of 64), so the overlap is added in
 // program order by one thread.
 // ---------------------------------------------------------------------------
+// Four waves per SIMD (two 8-wave workgroups per CU; the compiler's choice of 145
+// registers at ft = 1024 leaves one) for a spill of a few registers.
 template <int FT>
-__global__ __launch_bounds__(512) void k_ti(ConvArgs A, int b0, const int32_t* __restrict__ n_active,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 ? 4 : 1))) void k_ti(ConvArgs A, int b0, const int32_t* __restrict__ n_active,
                                             const float2* __restrict__ U,
                                             const float2* __restrict__ tw, float* __restrict__ out) {
     extern __shared__ float lds[];
@@ -828,7 +835,8 @@ __global__ __launch_bounds__(512) void k_ti(ConvArgs A, int b0, const int32_t* _
 #pragma unroll
         for (int m = 0; m < M; ++m) v[m] = cconj(stage[(lane + kWave * m) * kTile + wv]);
         __syncthreads();
-        wave_fft<FT>(v, lds + wv * kFftLds<FT>, tw, lane);
+        wave_fft<FT, TRED_TI_WAVESYNC>(v, lds + wv * kFftLds<FT>, tw, lane);
+        __syncthreads();   // the next piece's tile overlaps the other waves' FFT scratch
         if (valid) {
 #pragma unroll
             for (int m = 0; m < M; ++m) {

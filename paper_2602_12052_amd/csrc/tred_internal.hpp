@@ -222,7 +222,8 @@ __device__ __forceinline__ void pfa_gather(const float2* x, const float2* w, flo
 // On entry lane l holds x[l + 64 m] in v[m]; on exit X[l + 64 m] (forward DFT,
 // natural order). `buf` is the wave's private LDS scratch of kFftLds<N> floats;
 // `tw` is a table of exp(-2 pi i k / N), k < N (global or LDS).
-// Radix sequence: N = R1 * R2 * ... with every radix <= 16.
+// Radix sequence: N = R1 * R2 * ... with every radix <= 16. The scratch is private
+// to the wave (no workgroup barrier inside).
 // Stage (radix R, Ns = product of earlier radices): butterfly j reads
 // in[j + r N/R], multiplies by exp(-2 pi i r (j mod Ns) / (Ns R)), takes an
 // R-point DFT and writes out[(j / Ns) Ns R + j mod Ns + r Ns].
@@ -235,12 +236,28 @@ template <> struct FftPlan<1024> { static constexpr int R[4] = {16, 16, 4, 1}; s
 template <> struct FftPlan<2048> { static constexpr int R[4] = {16, 16, 8, 1}; static constexpr int S = 3; };
 template <> struct FftPlan<4096> { static constexpr int R[4] = {16, 16, 16, 1}; static constexpr int S = 3; };
 
+// Ordering of LDS accesses within one wavefront: the wave's LDS operations execute
+// in issue order, so it suffices to keep the compiler from moving accesses across
+// this point (the buffers of wave_fft are private to the wave).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // padded LDS index: one pad word per 16 (keeps stride-16 accesses conflict free)
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 template <int N>
 constexpr int kFftLds = 2 * (N + N / 16);
 
-template <int N, int R, int NS, bool FIRST>
+// WS: the scratch is private to the wave and only wave-level ordering is needed;
+// otherwise the stages are separated by workgroup barriers.
+template <bool WS>
+__device__ __forceinline__ void fft_sync() {
+    if constexpr (WS) wave_lds_sync();
+    else __syncthreads();
+}
+
+template <int N, int R, int NS, bool FIRST, bool WS>
 __device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* tw, int lane) {
     constexpr int M = N / kWave;
     constexpr int NB = N / R;            // butterflies in this stage
@@ -264,7 +281,7 @@ __device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* t
             }
         }
     }
-    __syncthreads();
+    fft_sync<WS>();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         int j = lane + kWave * i;
@@ -285,17 +302,17 @@ __device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* t
             im[idx] = x[r].y;
         }
     }
-    __syncthreads();
+    fft_sync<WS>();
 }
 
-template <int N>
+template <int N, bool WS>
 __device__ __forceinline__ void wave_fft(float2* v, float* buf, const float2* tw, int lane) {
     using P = FftPlan<N>;
     constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
-    fft_stage<N, R0, 1, true>(v, buf, tw, lane);
-    fft_stage<N, R1, R0, false>(v, buf, tw, lane);
-    if constexpr (P::S >= 3) fft_stage<N, R2, R0 * R1, false>(v, buf, tw, lane);
-    if constexpr (P::S >= 4) fft_stage<N, R3, R0 * R1 * R2, false>(v, buf, tw, lane);
+    fft_stage<N, R0, 1, true, WS>(v, buf, tw, lane);
+    fft_stage<N, R1, R0, false, WS>(v, buf, tw, lane);
+    if constexpr (P::S >= 3) fft_stage<N, R2, R0 * R1, false, WS>(v, buf, tw, lane);
+    if constexpr (P::S >= 4) fft_stage<N, R3, R0 * R1 * R2, false, WS>(v, buf, tw, lane);
     constexpr int M = N / kWave;
     const float* re = buf;
     const float* im = buf + (N + N / 16);
@@ -304,7 +321,7 @@ __device__ __forceinline__ void wave_fft(float2* v, float* buf, const float2* tw
         int idx = lpad(lane + kWave * m);
         v[m] = make_float2(re[idx], im[idx]);
     }
-    __syncthreads();
+    fft_sync<WS>();
 }
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("TRED_LIBRARY") or os.path.join(_HERE, "libtred.so")
 
 TRED_OK, TRED_EINVAL, TRED_ECAPACITY, TRED_EDEVICE, TRED_EUNSUPPORTED = range(5)
 TRED_CONV_MPCP = 1
+TRED_DIRECT_SPLIT = 1
 
 
 class TredError(RuntimeError):
@@ -67,6 +68,8 @@ EXPORTS = [
     "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
     "tred_scatter_workspace", "tred_scatter_waveforms", "tred_conv_plan_destroy",
+    "tred_direct_plan_create", "tred_direct_plan_set_response", "tred_block_conv_direct",
+    "tred_direct_plan_destroy",
 ]
 
 _lib = None
@@ -103,10 +106,17 @@ def lib():
     L.tred_scatter_waveforms.argtypes = [P, P, P, I32, P, P, P, P, I32, P, P]
     L.tred_conv_plan_destroy.argtypes = [P]
     L.tred_conv_plan_destroy.restype = None
+    L.tred_direct_plan_create.argtypes = [P, P, P, I32, U32, I32, C.POINTER(C.c_void_p),
+                                          C.POINTER(C.c_int64)]
+    L.tred_direct_plan_set_response.argtypes = [P, P, P, P]
+    L.tred_block_conv_direct.argtypes = [P, P, I32, P, P, P]
+    L.tred_direct_plan_destroy.argtypes = [P]
+    L.tred_direct_plan_destroy.restype = None
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
                  "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
-                 "tred_scatter_waveforms"):
+                 "tred_scatter_waveforms", "tred_direct_plan_create",
+                 "tred_direct_plan_set_response", "tred_block_conv_direct"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -250,6 +260,53 @@ def tred_block_conv(plan: ConvPlan, n_active, blocks, out_blocks, stream=None):
         raise ValueError("out_blocks has fewer rows than blocks")
     _check(lib().tred_block_conv(plan.handle, _ptr(n_active), cap, _ptr(blocks), _ptr(out_blocks),
                                  _stream(stream)))
+
+
+class DirectPlan:
+    """Owner of a tred_direct_plan (block-direct convolution on BF16 matrix cores)
+    and its device workspace."""
+
+    def __init__(self, grid, blocking, kpix, kticks, split=True, batch=64):
+        import torch
+        self.grid, self.blocking = grid_struct(grid), blocking_struct(blocking)
+        kp = (C.c_int32 * 2)(*kpix)
+        h = C.c_void_p()
+        ws = C.c_int64()
+        _check(lib().tred_direct_plan_create(C.byref(self.grid), C.byref(self.blocking), kp,
+                                             int(kticks), TRED_DIRECT_SPLIT if split else 0,
+                                             int(batch), C.byref(h), C.byref(ws)))
+        self.handle = h
+        self.kpix, self.kticks, self.split = tuple(kpix), int(kticks), bool(split)
+        self.workspace = torch.empty(int(ws.value) + 256, dtype=torch.uint8, device="cuda")
+
+    def _ws_ptr(self):
+        p = self.workspace.data_ptr()
+        return (p + 255) // 256 * 256
+
+    def set_response(self, resp, stream=None):
+        import torch
+        _dt(resp, torch.float32, "resp")
+        _check(lib().tred_direct_plan_set_response(self.handle, _ptr(resp), self._ws_ptr(),
+                                                   _stream(stream)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and self.handle.value:
+                lib().tred_direct_plan_destroy(self.handle)
+                self.handle = C.c_void_p()
+        except Exception:
+            pass
+
+
+def tred_block_conv_direct(plan: DirectPlan, n_active, blocks, out_blocks, cap=None, stream=None):
+    """cap: bins to convolve (default: all rows of blocks)."""
+    import torch
+    _dt(out_blocks, torch.float32, "out_blocks")
+    cap = blocks.shape[0] if cap is None else int(cap)
+    if out_blocks.shape[0] < cap or blocks.shape[0] < cap:
+        raise ValueError("blocks/out_blocks have fewer rows than cap")
+    _check(lib().tred_block_conv_direct(plan.handle, _ptr(n_active), cap, _ptr(blocks),
+                                        _ptr(out_blocks), _stream(stream)))
 
 
 def tred_scatter_workspace(plan: ConvPlan) -> int:

@@ -141,3 +141,41 @@ def test_block_conv_requires_response(T):
     assert T.lib().tred_block_conv(h, na, 4, na, na, None) == T.TRED_EINVAL
     assert b"set_response" in T.lib().tred_last_error()
     T.lib().tred_conv_plan_destroy(h)
+
+
+def _dplan(T, cfg, kpix=None, kticks=None, flags=1, batch=8):
+    g, b = T.grid_struct(cfg.grid), T.blocking_struct(cfg.blocking)
+    kp = (C.c_int32 * 2)(*(kpix or cfg.kpix))
+    h, ws = C.c_void_p(), C.c_int64()
+    st = T.lib().tred_direct_plan_create(C.byref(g), C.byref(b), kp, kticks or cfg.kticks, flags,
+                                         batch, C.byref(h), C.byref(ws))
+    return st, h, ws.value
+
+
+def test_direct_plan_workspace(T):
+    """BF16 operands: response [kticks][32-padded offsets][16-padded impacts] hi and lo,
+    plus the charge operands of one pass with 32-tick zero margins."""
+    cfg = _cfg()
+    st, h, ws = _dplan(T, cfg, batch=3)
+    assert st == 0
+    r = 200 * 32 * 112 * 2
+    q = 3 * 16 * (128 + 64) * 112 * 2
+    pad = lambda v: (v + 255) // 256 * 256
+    assert ws == 2 * pad(r) + 2 * pad(q)
+    T.lib().tred_direct_plan_destroy(h)
+
+
+@pytest.mark.parametrize("kw", [dict(kpix=(4, 5)), dict(flags=2), dict(batch=0),
+                                dict(batch=70000), dict(kticks=-1)])
+def test_direct_plan_rejects(T, kw):
+    st, h, ws = _dplan(T, _cfg(), **kw)
+    assert st == T.TRED_EINVAL, T.lib().tred_last_error()
+    assert not h.value
+
+
+def test_direct_conv_requires_response(T):
+    st, h, ws = _dplan(T, _cfg())
+    na = C.c_void_p(0x1000)
+    assert T.lib().tred_block_conv_direct(h, na, 4, na, na, None) == T.TRED_EINVAL
+    assert b"set_response" in T.lib().tred_last_error()
+    T.lib().tred_direct_plan_destroy(h)

@@ -522,6 +522,53 @@ def test_waveform_points_match_full(orc):
     assert np.max(np.abs(got - wf[pts[:, 0], pts[:, 1]])) < 1e-12 * np.abs(wf).max()
 
 
+def test_block_outputs_overlap_add_to_global_convolution(orc):
+    """Blocking + overlap-add reaches the global direct convolution exactly (Sec.
+    III-B): each bin's output at every sample of its output frame, placed at the bin's
+    origin and summed over bins (cropped to the region), equals the waveforms."""
+    g, ph, seg, fp, off, val = _small_event(orc, n=10, nticks=64)
+    K, kt = (3, 5), 24
+    R = W.random_symmetric_response(K, g.sub, kt, seed=4)
+    blk = W.Blocking((2, 4), 32)
+    keys = orc.block_keys(g, blk, fp)
+    NP = g.npix
+    L = g.nticks + kt - 1
+    total = np.zeros((NP[0], NP[1], L))
+    box, boy, bot = 2 + K[0] - 1, 4 + K[1] - 1, 32 + kt - 1
+    pts = np.array([(qx, qy, t) for qx in range(box) for qy in range(boy) for t in range(bot)])
+    for key in keys:
+        bv = orc.block_values(g, blk, fp, off, val, key)
+        out = orc.block_output_points(g, blk, K, kt, R, bv, pts).reshape(box, boy, bot)
+        x0, y0, t0 = key[0] * 2 - 1, key[1] * 4 - 2, key[2] * 32
+        for qx in range(box):
+            for qy in range(boy):
+                px, py = x0 + qx, y0 + qy
+                if 0 <= px < NP[0] and 0 <= py < NP[1]:
+                    n = min(bot, L - t0)
+                    total[px, py, t0:t0 + n] += out[qx, qy, :n]
+    allpix = np.arange(NP[0] * NP[1], dtype=np.int32)
+    wf = orc.waveforms(g, K, kt, R, fp, off, val, allpix).reshape(NP[0], NP[1], -1)
+    assert np.max(np.abs(total - wf)) < 1e-11 * np.abs(wf).max()
+
+
+def test_bin_members_brute_force(orc):
+    """The depositions reaching a bin are those with a footprint cell inside it."""
+    g, ph, seg, fp, off, val = _small_event(orc, n=15, nticks=64)
+    blk = W.Blocking((2, 4), 32)
+    bf = (2 * g.sub[0], 4 * g.sub[1], 32)
+    for key in orc.block_keys(g, blk, fp):
+        got = set(orc.bin_members(g, blk, fp, key).tolist())
+        exp = set()
+        for d in range(fp.shape[0]):
+            f = fp[d]
+            cells = [range(f[a], f[3 + a] + 1) for a in range(3)]
+            if any(c // bf[0] == key[0] for c in cells[0]) and \
+                    any(c // bf[1] == key[1] for c in cells[1]) and \
+                    any(c // bf[2] == key[2] for c in cells[2]):
+                exp.add(d)
+        assert got == exp
+
+
 # ---------------------------------------------------------------------------
 # Accuracy study of the paper (Sec. IV-B): GL-2 vs grid sampling, against GL-4
 # ---------------------------------------------------------------------------
