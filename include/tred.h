@@ -219,6 +219,32 @@ tred_status tred_scatter_waveforms(const tred_conv_plan* plan, const int32_t* ke
 void tred_conv_plan_destroy(tred_conv_plan* plan);
 
 /* ------------------------------------------------------------------------- */
+/* Batches of events (one binned tensor for many events). The depositions of n_ev
+ * events are concatenated: event e owns depositions [ev_off[e], ev_off[e+1]) with
+ * ev_off a DEVICE int64 array of n_ev + 1 non-decreasing offsets (ev_off[0] = 0,
+ * ev_off[n_ev] = n_dep). tred_effq_windows / tred_effq run unchanged on the
+ * concatenation (they are per deposition). The active (event, bin) pairs of all
+ * events form one list of bins, so one tred_block_conv pass convolves the bins of
+ * every event together (Sec. III-B, batching over the outer dimensions).
+ * keys [cap][4] out: (event, bx, by, bt), ascending lexicographically.
+ * pix  [pix_cap] out: ids event * npix[0] * npix[1] + px * npix[1] + py, ascending.
+ * Per event, bins, pixels and waveforms are those of tred_block_bin and
+ * tred_scatter_waveforms run on that event alone. Workspaces scale with n_ev. */
+int64_t tred_block_bin_events_workspace(const tred_grid* grid, const tred_blocking* blocking,
+                                        int32_t n_ev);
+tred_status tred_block_bin_events(const tred_grid* grid, const tred_blocking* blocking,
+                                  int32_t n_ev, const int64_t* ev_off, int64_t n_dep,
+                                  const int32_t* fp, const int64_t* off, const float* val,
+                                  int64_t val_cap, int32_t* keys, int32_t* n_active, float* blocks,
+                                  int32_t cap, void* work, void* stream);
+int64_t tred_scatter_events_workspace(const tred_conv_plan* plan, int32_t n_ev);
+tred_status tred_scatter_waveforms_events(const tred_conv_plan* plan, int32_t n_ev,
+                                          const int32_t* keys, const int32_t* n_active,
+                                          int32_t cap, const float* out_blocks, int32_t* pix,
+                                          int32_t* n_pix, float* wf, int32_t pix_cap, void* work,
+                                          void* stream);
+
+/* ------------------------------------------------------------------------- */
 /* Block-direct interlaced convolution on the matrix cores: the same operation and
  * output as tred_block_conv (Sec. II-D eq. interlaced), evaluated per bin as the
  * dense contraction out[p + k][t'] = sum_{j, tau} Q_j[p][t' - tau] R_j[k][tau]

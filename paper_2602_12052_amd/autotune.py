@@ -1,0 +1,101 @@
+"""Autotuner for the bin shape and FFT sizes of the convolution.
+
+The paper (Sec. III-B and its bin-size study) chooses the bin shape by measurement:
+small bins waste less volume on empty cells but convolve more overlapping output
+halos, and the FFT length trades transform work against the number of response
+pieces. This tuner times the whole path (effective charge, binning, convolution,
+overlap-add) on a sample event for each candidate that fits a memory budget and
+returns the fastest. All arithmetic runs in the library; this module only creates
+plans, allocates buffers and times calls.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+from . import tred
+
+# (blk_pix, blk_ticks, fft) candidates; fft = (fs, fs, ft)
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int, Tuple[int, int, int]], ...] = (
+    (16, 512, (40, 40, 1024)),
+    (16, 512, (40, 40, 2048)),
+    (16, 256, (40, 40, 1024)),
+    (16, 256, (40, 40, 2048)),
+    (8, 512, (40, 40, 1024)),
+    (8, 256, (40, 40, 1024)),
+)
+
+
+@dataclass
+class Trial:
+    blk_pix: int
+    blk_ticks: int
+    fft: Tuple[int, int, int]
+    ms: Optional[float] = None          # median time of the whole path on the sample
+    bins: Optional[int] = None
+    bytes: Optional[int] = None         # device bytes of blocks, outputs and scratch
+    note: str = ""
+
+
+@dataclass
+class TuneResult:
+    best: Trial
+    trials: List[Trial] = field(default_factory=list)
+
+    def blocking(self, W):
+        return W.Blocking((self.best.blk_pix, self.best.blk_pix), self.best.blk_ticks)
+
+
+def _bytes_per_bin(grid, blocking, kpix, kticks, fft, mpcp):
+    g, b = tred.grid_struct(grid), tred.blocking_struct(blocking)
+    vblk = b.blk_pix[0] * g.sub[0] * b.blk_pix[1] * g.sub[1] * b.blk_ticks
+    vout = (b.blk_pix[0] + kpix[0] - 1) * (b.blk_pix[1] + kpix[1] - 1) * (b.blk_ticks + kticks - 1)
+    w1 = tred.plan_workspace_bytes(grid, blocking, kpix, kticks, fft, mpcp, 1 << 16)
+    w2 = tred.plan_workspace_bytes(grid, blocking, kpix, kticks, fft, mpcp, 1 << 17)
+    return 4 * (vblk + vout), (w2 - w1) // (1 << 16)
+
+
+def tune(grid, phys, kpix, kticks, resp, seg, mpcp: bool = True,
+         candidates: Sequence = DEFAULT_CANDIDATES, budget_bytes: float = 200e9,
+         reps: int = 2, make_blocking=None, log=None) -> TuneResult:
+    """Time each candidate on the sample event `seg` (device tensor) and return the
+    fastest. make_blocking(blk_pix, blk_ticks) builds a blocking object."""
+    import torch
+    trials = []
+    for bp, bt, fft in candidates:
+        tr = Trial(bp, bt, tuple(fft))
+        trials.append(tr)
+        blk = make_blocking(bp, bt)
+        try:
+            val_cap, bcap, pix_cap = tred.size_event(grid, phys, blk, kpix, seg)
+            fixed, scratch = _bytes_per_bin(grid, blk, kpix, kticks, fft, mpcp)
+            nb = tred.conv_batch(grid, blk, kpix, kticks, fft, mpcp, bcap,
+                                 max(scratch, budget_bytes - fixed * bcap))
+            tr.bins = bcap
+            tr.bytes = fixed * bcap + scratch * nb
+            if fixed * bcap + scratch > budget_bytes:
+                tr.note = "over the memory budget"
+                continue
+            pl = tred.Pipeline(grid, phys, blk, kpix, kticks, resp, seg.shape[0], val_cap, bcap,
+                               pix_cap, fft, mpcp, nb)
+            pl.run(seg)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                pl.run(seg)
+                torch.cuda.synchronize()
+                ts.append(1e3 * (time.perf_counter() - t0))
+            tr.ms = sorted(ts)[len(ts) // 2]
+            del pl
+            torch.cuda.empty_cache()
+        except tred.TredError as e:
+            tr.note = f"unsupported: {e}"
+        if log:
+            log(f"autotune: blk {bp}x{bp}x{bt} fft {fft}: "
+                + (f"{tr.ms:.1f} ms, {tr.bins} bins" if tr.ms is not None else tr.note))
+    ok = [t for t in trials if t.ms is not None]
+    if not ok:
+        raise RuntimeError("no autotune candidate ran")
+    return TuneResult(min(ok, key=lambda t: t.ms), trials)

@@ -1,5 +1,7 @@
 // Block-sparse binned tensor (Sec. III-B): active bins, their keys and the dense
-// charge of each active bin, reduced over overlapping deposition patches.
+// charge of each active bin, reduced over overlapping deposition patches. A batch
+// of events shares one binned tensor: the event index leads the bin key, so the
+// (event, bin) pairs of all events form one list of independent blocks.
 #include "tred_internal.hpp"
 #include "validate.hpp"
 
@@ -9,7 +11,22 @@ struct BinGeom {
     int32_t bf[3];   // bin extent in fine cells
     int32_t nb[3];   // bins per axis
     int64_t vblk;    // cells per bin
+    int32_t nev;     // events in the batch
+    int32_t kst;     // key stride: 3 (bx, by, bt) or 4 (event, bx, by, bt)
+    int64_t nbins;   // bins per event
 };
+
+// event of deposition d: ev_off[e] <= d < ev_off[e + 1] (ev_off NULL: one event)
+__device__ __forceinline__ int event_of(int64_t d, const int64_t* __restrict__ ev_off, int nev) {
+    if (ev_off == nullptr) return 0;
+    int lo = 0, hi = nev - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ev_off[mid] <= d) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -19,11 +36,13 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 
 // every bin touched by a footprint box gets flag 1
 __global__ __launch_bounds__(256) void k_mark(BinGeom G, int64_t n, const int32_t* __restrict__ fp,
+                                              const int64_t* __restrict__ ev_off,
                                               int32_t* __restrict__ flag) {
     int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= n) return;
     const int32_t* f = fp + 6 * d;
     if (f[3] < f[0] || f[4] < f[1] || f[5] < f[2]) return;
+    flag += (int64_t)event_of(d, ev_off, G.nev) * G.nbins;
     for (int bx = f[0] / G.bf[0]; bx <= f[3] / G.bf[0]; ++bx)
         for (int by = f[1] / G.bf[1]; by <= f[4] / G.bf[1]; ++by)
             for (int bt = f[2] / G.bf[2]; bt <= f[5] / G.bf[2]; ++bt)
@@ -46,7 +65,7 @@ __global__ __launch_bounds__(1024) void k_compact(BinGeom G, int32_t* __restrict
                                                   int32_t* __restrict__ n_active, int32_t cap) {
     __shared__ int wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t tot = (int64_t)G.nb[0] * G.nb[1] * G.nb[2];
+    const int64_t tot = (int64_t)G.nev * G.nbins;
     int carry = 0;
     for (int64_t base = 0; base < tot; base += 1024) {
         const int64_t i = base + tid;
@@ -63,9 +82,12 @@ __global__ __launch_bounds__(1024) void k_compact(BinGeom G, int32_t* __restrict
         const int slot = carry + incl - f + (wave > 0 ? wsum[wave - 1] : 0);
         if (i < tot) {
             if (f && slot < cap) {
-                keys[3 * slot + 0] = (int32_t)(i / ((int64_t)G.nb[1] * G.nb[2]));
-                keys[3 * slot + 1] = (int32_t)((i / G.nb[2]) % G.nb[1]);
-                keys[3 * slot + 2] = (int32_t)(i % G.nb[2]);
+                const int64_t e = i / G.nbins, b = i % G.nbins;
+                int32_t* k = keys + (int64_t)G.kst * slot;
+                if (G.kst == 4) *k++ = (int32_t)e;
+                k[0] = (int32_t)(b / ((int64_t)G.nb[1] * G.nb[2]));
+                k[1] = (int32_t)((b / G.nb[2]) % G.nb[1]);
+                k[2] = (int32_t)(b % G.nb[2]);
             }
             flag[i] = (f && slot < cap) ? slot : -1;
         }
@@ -100,11 +122,13 @@ __global__ __launch_bounds__(256) void k_zero_tail(float* __restrict__ blocks,
 __global__ __launch_bounds__(256) void k_accum(BinGeom G, int64_t n, const int32_t* __restrict__ fp,
                                                const int64_t* __restrict__ off,
                                                const float* __restrict__ val, int64_t val_cap,
-                                               const int32_t* __restrict__ slot,
+                                               const int64_t* __restrict__ ev_off,
+                                               const int32_t* __restrict__ slot_all,
                                                float* __restrict__ blocks) {
     for (int64_t d = blockIdx.x; d < n; d += gridDim.x) {
         const int32_t* f = fp + 6 * d;
         if (f[3] < f[0] || f[4] < f[1] || f[5] < f[2]) continue;
+        const int32_t* slot = slot_all + (int64_t)event_of(d, ev_off, G.nev) * G.nbins;
         const int ny = f[4] - f[1] + 1, nt = f[5] - f[2] + 1;
         if (off[d + 1] > val_cap) continue;
         const int64_t cnt = off[d + 1] - off[d];
@@ -127,14 +151,56 @@ __global__ __launch_bounds__(256) void k_accum(BinGeom G, int64_t n, const int32
     }
 }
 
-BinGeom geom(const tred_grid* g, const tred_blocking* b) {
+BinGeom geom(const tred_grid* g, const tred_blocking* b, int nev, int kst) {
     BinGeom G;
     G.bf[0] = b->blk_pix[0] * g->sub[0];
     G.bf[1] = b->blk_pix[1] * g->sub[1];
     G.bf[2] = b->blk_ticks;
     for (int a = 0; a < 3; ++a) G.nb[a] = nblk_axis(g, b, a);
     G.vblk = (int64_t)G.bf[0] * G.bf[1] * G.bf[2];
+    G.nev = nev;
+    G.kst = kst;
+    G.nbins = (int64_t)G.nb[0] * G.nb[1] * G.nb[2];
     return G;
+}
+
+tred_status block_bin(const tred_grid* grid, const tred_blocking* blocking, int32_t n_ev,
+                      const int64_t* ev_off, int64_t n_dep, const int32_t* fp, const int64_t* off,
+                      const float* val, int64_t val_cap, int32_t* keys, int32_t* n_active,
+                      float* blocks, int32_t cap, void* work, void* stream) {
+    TRED_TRY(validate_grid(grid));
+    TRED_TRY(validate_blocking(blocking));
+    TRED_REQUIRE(n_dep >= 0, "n_dep must be >= 0");
+    TRED_REQUIRE(cap >= 0, "cap must be >= 0");
+    TRED_REQUIRE(n_active && work, "n_active/work is NULL");
+    TRED_REQUIRE(cap == 0 || (keys && blocks), "keys/blocks is NULL");
+    TRED_REQUIRE(n_dep == 0 || (fp && off && val), "fp/off/val is NULL");
+    TRED_REQUIRE(tred_block_count(grid, blocking) > 0, "too many bins");
+    TRED_REQUIRE((int64_t)n_ev * tred_block_count(grid, blocking) < INT32_MAX,
+                 "too many (event, bin) pairs");
+    TRED_REQUIRE(((uintptr_t)blocks & 15) == 0, "blocks must be 16-byte aligned");
+    const BinGeom G = geom(grid, blocking, n_ev, ev_off ? 4 : 3);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t* flag = (int32_t*)work;
+    const int64_t tot = (int64_t)G.nev * G.nbins;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 4096)),
+                       dim3(256), 0, st, flag, tot, 0);
+    if (n_dep > 0)
+        hipLaunchKernelGGL(k_mark, dim3((unsigned)((n_dep + 255) / 256)), dim3(256), 0, st, G,
+                           n_dep, fp, ev_off, flag);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, G, flag, keys, n_active, cap);
+    TRED_TRY(tred_check_launch("tred_block_bin compact"));
+    if (cap > 0) {
+        hipLaunchKernelGGL(k_zero_blocks, dim3(2048), dim3(256), 0, st, (float4*)blocks, n_active,
+                           cap, G.vblk);
+        hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(4), 0, st, blocks, n_active, cap, G.vblk);
+        if (n_dep > 0) {
+            unsigned nb = (unsigned)std::min<int64_t>(n_dep, 1 << 20);
+            hipLaunchKernelGGL(k_accum, dim3(nb), dim3(256), 0, st, G, n_dep, fp, off, val, val_cap,
+                               ev_off, flag, blocks);
+        }
+    }
+    return tred_check_launch("tred_block_bin");
 }
 
 }  // namespace
@@ -156,35 +222,24 @@ extern "C" tred_status tred_block_bin(const tred_grid* grid, const tred_blocking
                                       const float* val, int64_t val_cap, int32_t* keys,
                                       int32_t* n_active,
                                       float* blocks, int32_t cap, void* work, void* stream) {
-    TRED_TRY(validate_grid(grid));
-    TRED_TRY(validate_blocking(blocking));
-    TRED_REQUIRE(n_dep >= 0, "n_dep must be >= 0");
-    TRED_REQUIRE(cap >= 0, "cap must be >= 0");
-    TRED_REQUIRE(n_active && work, "n_active/work is NULL");
-    TRED_REQUIRE(cap == 0 || (keys && blocks), "keys/blocks is NULL");
-    TRED_REQUIRE(n_dep == 0 || (fp && off && val), "fp/off/val is NULL");
-    TRED_REQUIRE(tred_block_count(grid, blocking) > 0, "too many bins");
-    TRED_REQUIRE(((uintptr_t)blocks & 15) == 0, "blocks must be 16-byte aligned");
-    const BinGeom G = geom(grid, blocking);
-    hipStream_t st = (hipStream_t)stream;
-    int32_t* flag = (int32_t*)work;
-    const int64_t tot = (int64_t)G.nb[0] * G.nb[1] * G.nb[2];
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 4096)),
-                       dim3(256), 0, st, flag, tot, 0);
-    if (n_dep > 0)
-        hipLaunchKernelGGL(k_mark, dim3((unsigned)((n_dep + 255) / 256)), dim3(256), 0, st, G,
-                           n_dep, fp, flag);
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, G, flag, keys, n_active, cap);
-    TRED_TRY(tred_check_launch("tred_block_bin compact"));
-    if (cap > 0) {
-        hipLaunchKernelGGL(k_zero_blocks, dim3(2048), dim3(256), 0, st, (float4*)blocks, n_active,
-                           cap, G.vblk);
-        hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(4), 0, st, blocks, n_active, cap, G.vblk);
-        if (n_dep > 0) {
-            unsigned nb = (unsigned)std::min<int64_t>(n_dep, 1 << 20);
-            hipLaunchKernelGGL(k_accum, dim3(nb), dim3(256), 0, st, G, n_dep, fp, off, val, val_cap,
-                               flag, blocks);
-        }
-    }
-    return tred_check_launch("tred_block_bin");
+    return block_bin(grid, blocking, 1, nullptr, n_dep, fp, off, val, val_cap, keys, n_active,
+                     blocks, cap, work, stream);
+}
+
+extern "C" int64_t tred_block_bin_events_workspace(const tred_grid* grid,
+                                                   const tred_blocking* blocking, int32_t n_ev) {
+    int32_t n = tred_block_count(grid, blocking);
+    return (n < 0 || n_ev <= 0) ? -1 : (int64_t)n * n_ev * 4;
+}
+
+extern "C" tred_status tred_block_bin_events(const tred_grid* grid, const tred_blocking* blocking,
+                                             int32_t n_ev, const int64_t* ev_off, int64_t n_dep,
+                                             const int32_t* fp, const int64_t* off,
+                                             const float* val, int64_t val_cap, int32_t* keys,
+                                             int32_t* n_active, float* blocks, int32_t cap,
+                                             void* work, void* stream) {
+    TRED_REQUIRE(n_ev > 0, "n_ev must be > 0");
+    TRED_REQUIRE(ev_off != nullptr, "ev_off is NULL");
+    return block_bin(grid, blocking, n_ev, ev_off, n_dep, fp, off, val, val_cap, keys, n_active,
+                     blocks, cap, work, stream);
 }

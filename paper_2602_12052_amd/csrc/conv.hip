@@ -15,7 +15,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 #include "tred_internal.hpp"
 #include "validate.hpp"
@@ -920,12 +922,20 @@ ConvArgs make_args(const tred_conv_plan* P) {
     return A;
 }
 
+// Permit dynamic LDS above the 64 KiB default (gfx950 has 160 KiB per CU). The
+// attribute is set once per kernel and size, so that launches recorded into a graph
+// are not interleaved with attribute calls.
 template <typename K>
 void allow_lds(K kernel, size_t bytes) {
-    // permit dynamic LDS above the 64 KiB default (gfx950 has 160 KiB per CU)
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)bytes);
+    if (bytes <= 65536) return;
+    static std::mutex mu;
+    static std::unordered_map<const void*, size_t> done;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& have = done[(const void*)kernel];
+    if (bytes <= have) return;
+    if (hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) == hipSuccess)
+        have = bytes;
 }
 
 template <int FT>

@@ -16,6 +16,7 @@ struct ScatArgs {
     int32_t lwf;        // waveform length nticks + kticks - 1
     int32_t cap, pix_cap;
     int64_t vout;
+    int32_t nev, kst;   // events in the batch; key stride (3, or 4 with the event first)
 };
 
 __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v) {
@@ -30,15 +31,19 @@ __global__ __launch_bounds__(256) void k_mark_pix(ScatArgs S, const int32_t* __r
                                                   int32_t* __restrict__ pmap,
                                                   int32_t* __restrict__ bmap) {
     const int na = min(*n_active, S.cap);
+    const int64_t nbins = (int64_t)S.nb[0] * S.nb[1] * S.nb[2];
+    const int64_t npix = (int64_t)S.npx * S.npy;
     for (int i = blockIdx.x; i < na; i += gridDim.x) {
-        const int bx = keys[3 * i], by = keys[3 * i + 1], bt = keys[3 * i + 2];
-        if (threadIdx.x == 0) bmap[((int64_t)bx * S.nb[1] + by) * S.nb[2] + bt] = i;
+        const int32_t* k = keys + (int64_t)S.kst * i;
+        const int e = S.kst == 4 ? *k++ : 0;
+        const int bx = k[0], by = k[1], bt = k[2];
+        if (threadIdx.x == 0) bmap[e * nbins + ((int64_t)bx * S.nb[1] + by) * S.nb[2] + bt] = i;
         const int x0 = max(0, bx * S.Bx - S.hx), x1 = min(S.npx - 1, bx * S.Bx + S.Bx - 1 + S.hx);
         const int y0 = max(0, by * S.By - S.hy), y1 = min(S.npy - 1, by * S.By + S.By - 1 + S.hy);
         const int ny = y1 - y0 + 1;
         const int cnt = (x1 - x0 + 1) * ny;
-        for (int k = threadIdx.x; k < cnt; k += blockDim.x)
-            pmap[(int64_t)(x0 + k / ny) * S.npy + (y0 + k % ny)] = 1;
+        for (int c = threadIdx.x; c < cnt; c += blockDim.x)
+            pmap[e * npix + (int64_t)(x0 + c / ny) * S.npy + (y0 + c % ny)] = 1;
     }
 }
 
@@ -57,7 +62,7 @@ __global__ __launch_bounds__(1024) void k_compact_pix(ScatArgs S, int32_t* __res
                                                       int32_t* __restrict__ n_pix) {
     __shared__ int wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t tot = (int64_t)S.npx * S.npy;
+    const int64_t tot = (int64_t)S.nev * S.npx * S.npy;
     int carry = 0;
     for (int64_t base = 0; base < tot; base += 1024) {
         const int64_t i = base + tid;
@@ -90,8 +95,11 @@ __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __res
                                                 float* __restrict__ wf) {
     const int slot = blockIdx.x;
     if (slot >= min(*n_pix, S.pix_cap)) return;
-    const int p = pix[slot];
+    const int64_t npix = (int64_t)S.npx * S.npy;
+    const int e = (int)(pix[slot] / npix);
+    const int p = (int)(pix[slot] % npix);
     const int px = p / S.npy, py = p % S.npy;
+    bmap += e * (int64_t)S.nb[0] * S.nb[1] * S.nb[2];
     const int T0 = blockIdx.y * 256;
     const int T = T0 + threadIdx.x;
     // bins whose output footprint contains this pixel: b*B - h <= p <= b*B + B - 1 + h
@@ -134,35 +142,36 @@ ScatArgs make_sargs(const tred_conv_plan* P) {
     S.bot = P->bo[2];
     S.lwf = P->grid.nticks + P->kticks - 1;
     S.vout = (int64_t)S.box * S.boy * S.bot;
+    S.nev = 1;
+    S.kst = 3;
     return S;
 }
 
-}  // namespace
-
-extern "C" int64_t tred_scatter_workspace(const tred_conv_plan* P) {
-    if (!P) return -1;
+int64_t scatter_workspace(const tred_conv_plan* P, int32_t nev) {
     const int64_t nbt = (int64_t)nblk_axis(&P->grid, &P->blk, 0) * nblk_axis(&P->grid, &P->blk, 1) *
                         nblk_axis(&P->grid, &P->blk, 2);
-    return ((int64_t)P->grid.npix[0] * P->grid.npix[1] + nbt) * 4;
+    return ((int64_t)P->grid.npix[0] * P->grid.npix[1] + nbt) * 4 * nev;
 }
 
-extern "C" tred_status tred_scatter_waveforms(const tred_conv_plan* P, const int32_t* keys,
-                                              const int32_t* n_active, int32_t cap,
-                                              const float* out_blocks, int32_t* pix, int32_t* n_pix,
-                                              float* wf, int32_t pix_cap, void* work,
-                                              void* stream) {
+tred_status scatter(const tred_conv_plan* P, int32_t nev, int32_t kst, const int32_t* keys,
+                    const int32_t* n_active, int32_t cap, const float* out_blocks, int32_t* pix,
+                    int32_t* n_pix, float* wf, int32_t pix_cap, void* work, void* stream) {
     TRED_REQUIRE(P && n_active && n_pix && work, "plan/n_active/n_pix/work is NULL");
     TRED_REQUIRE(cap >= 0 && pix_cap >= 0, "capacities must be >= 0");
     TRED_REQUIRE(cap == 0 || (keys && out_blocks), "keys/out_blocks is NULL");
     TRED_REQUIRE(pix_cap == 0 || (pix && wf), "pix/wf is NULL");
+    TRED_REQUIRE((int64_t)nev * P->grid.npix[0] * P->grid.npix[1] < INT32_MAX,
+                 "too many (event, pixel) pairs");
     hipStream_t st = (hipStream_t)stream;
     ScatArgs S = make_sargs(P);
     S.cap = cap;
     S.pix_cap = pix_cap;
+    S.nev = nev;
+    S.kst = kst;
     int32_t* pmap = (int32_t*)work;
-    const int64_t npix_tot = (int64_t)S.npx * S.npy;
+    const int64_t npix_tot = (int64_t)nev * S.npx * S.npy;
     int32_t* bmap = pmap + npix_tot;
-    const int64_t nbt = (int64_t)S.nb[0] * S.nb[1] * S.nb[2];
+    const int64_t nbt = (int64_t)nev * S.nb[0] * S.nb[1] * S.nb[2];
     hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((npix_tot + 255) / 256, 4096)),
                        dim3(256), 0, st, pmap, npix_tot, 0);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((nbt + 255) / 256, 4096)), dim3(256),
@@ -176,4 +185,34 @@ extern "C" tred_status tred_scatter_waveforms(const tred_conv_plan* P, const int
         hipLaunchKernelGGL(k_gather, dim3(pix_cap, (S.lwf + 255) / 256), dim3(256), 0, st, S, pix,
                            n_pix, bmap, out_blocks, wf);
     return tred_check_launch("tred_scatter_waveforms");
+}
+
+}  // namespace
+
+extern "C" int64_t tred_scatter_workspace(const tred_conv_plan* P) {
+    if (!P) return -1;
+    return scatter_workspace(P, 1);
+}
+
+extern "C" tred_status tred_scatter_waveforms(const tred_conv_plan* P, const int32_t* keys,
+                                              const int32_t* n_active, int32_t cap,
+                                              const float* out_blocks, int32_t* pix, int32_t* n_pix,
+                                              float* wf, int32_t pix_cap, void* work,
+                                              void* stream) {
+    return scatter(P, 1, 3, keys, n_active, cap, out_blocks, pix, n_pix, wf, pix_cap, work, stream);
+}
+
+extern "C" int64_t tred_scatter_events_workspace(const tred_conv_plan* P, int32_t n_ev) {
+    if (!P || n_ev <= 0) return -1;
+    return scatter_workspace(P, n_ev);
+}
+
+extern "C" tred_status tred_scatter_waveforms_events(const tred_conv_plan* P, int32_t n_ev,
+                                                     const int32_t* keys, const int32_t* n_active,
+                                                     int32_t cap, const float* out_blocks,
+                                                     int32_t* pix, int32_t* n_pix, float* wf,
+                                                     int32_t pix_cap, void* work, void* stream) {
+    TRED_REQUIRE(n_ev > 0, "n_ev must be > 0");
+    return scatter(P, n_ev, 4, keys, n_active, cap, out_blocks, pix, n_pix, wf, pix_cap, work,
+                   stream);
 }

@@ -69,7 +69,8 @@ EXPORTS = [
     "tred_block_conv",
     "tred_scatter_workspace", "tred_scatter_waveforms", "tred_conv_plan_destroy",
     "tred_direct_plan_create", "tred_direct_plan_set_response", "tred_block_conv_direct",
-    "tred_direct_plan_destroy",
+    "tred_direct_plan_destroy", "tred_block_bin_events_workspace", "tred_block_bin_events",
+    "tred_scatter_events_workspace", "tred_scatter_waveforms_events",
 ]
 
 _lib = None
@@ -112,11 +113,18 @@ def lib():
     L.tred_block_conv_direct.argtypes = [P, P, I32, P, P, P]
     L.tred_direct_plan_destroy.argtypes = [P]
     L.tred_direct_plan_destroy.restype = None
+    L.tred_block_bin_events_workspace.argtypes = [P, P, I32]
+    L.tred_block_bin_events_workspace.restype = I64
+    L.tred_block_bin_events.argtypes = [P, P, I32, P, I64, P, P, P, I64, P, P, P, I32, P, P]
+    L.tred_scatter_events_workspace.argtypes = [P, I32]
+    L.tred_scatter_events_workspace.restype = I64
+    L.tred_scatter_waveforms_events.argtypes = [P, I32, P, P, I32, P, P, P, P, I32, P, P]
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
                  "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
                  "tred_scatter_waveforms", "tred_direct_plan_create",
-                 "tred_direct_plan_set_response", "tred_block_conv_direct"):
+                 "tred_direct_plan_set_response", "tred_block_conv_direct",
+                 "tred_block_bin_events", "tred_scatter_waveforms_events"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -196,6 +204,30 @@ def tred_block_bin(grid, blocking, fp, off, val, keys, n_active, blocks, work, s
     _check(lib().tred_block_bin(C.byref(g), C.byref(b), n, _ptr(fp), _ptr(off), _ptr(val),
                                 val.numel(), _ptr(keys), _ptr(n_active), _ptr(blocks), cap,
                                 _ptr(work), _stream(stream)))
+
+
+def tred_block_bin_events_workspace(grid, blocking, n_ev) -> int:
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    return int(lib().tred_block_bin_events_workspace(C.byref(g), C.byref(b), int(n_ev)))
+
+
+def tred_block_bin_events(grid, blocking, ev_off, fp, off, val, keys, n_active, blocks, work,
+                          stream=None):
+    """ev_off: int64 device tensor [n_ev + 1]; keys [cap][4] (event, bx, by, bt)."""
+    import torch
+    _dt(ev_off, torch.int64, "ev_off"), _dt(keys, torch.int32, "keys")
+    _dt(n_active, torch.int32, "n_active"), _dt(blocks, torch.float32, "blocks")
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    n = fp.shape[0]
+    cap = 0 if keys is None else keys.shape[0]
+    if keys is not None and keys.shape[1] != 4:
+        raise ValueError("keys must be [cap][4]")
+    if blocks is not None and blocks.shape[0] < cap:
+        raise ValueError("blocks has fewer rows than keys")
+    _check(lib().tred_block_bin_events(C.byref(g), C.byref(b), ev_off.numel() - 1, _ptr(ev_off), n,
+                                       _ptr(fp), _ptr(off), _ptr(val), val.numel(), _ptr(keys),
+                                       _ptr(n_active), _ptr(blocks), cap, _ptr(work),
+                                       _stream(stream)))
 
 
 class ConvPlan:
@@ -309,6 +341,20 @@ def tred_block_conv_direct(plan: DirectPlan, n_active, blocks, out_blocks, cap=N
                                         _ptr(out_blocks), _stream(stream)))
 
 
+def tred_scatter_events_workspace(plan: ConvPlan, n_ev) -> int:
+    return int(lib().tred_scatter_events_workspace(plan.handle, int(n_ev)))
+
+
+def tred_scatter_waveforms_events(plan: ConvPlan, n_ev, keys, n_active, out_blocks, pix, n_pix,
+                                  wf, work, stream=None):
+    import torch
+    _dt(pix, torch.int32, "pix"), _dt(n_pix, torch.int32, "n_pix"), _dt(wf, torch.float32, "wf")
+    cap = keys.shape[0]
+    _check(lib().tred_scatter_waveforms_events(plan.handle, int(n_ev), _ptr(keys), _ptr(n_active),
+                                               cap, _ptr(out_blocks), _ptr(pix), _ptr(n_pix),
+                                               _ptr(wf), pix.shape[0], _ptr(work), _stream(stream)))
+
+
 def tred_scatter_workspace(plan: ConvPlan) -> int:
     return int(lib().tred_scatter_workspace(plan.handle))
 
@@ -389,6 +435,99 @@ class Pipeline:
                     keys=self.keys[:min(na, self.keys.shape[0])].cpu().numpy(), n_pix=npx,
                     pix=self.pix[:min(npx, self.pix.shape[0])].cpu().numpy(),
                     wf=self.wf[:min(npx, self.pix.shape[0])].cpu().numpy())
+
+
+class BatchPipeline:
+    """Buffers and plan for batches of events sharing one grid and response. A batch
+    is a concatenation of depositions with device offsets ev_off (event e owns rows
+    ev_off[e] .. ev_off[e+1]); its (event, bin) pairs form one binned tensor
+    convolved in passes of `batch` bins, and waveforms are per (event, pixel).
+    Capacities bound any batch given to run(), so one buffer set serves a stream of
+    batches; run() enqueues every call with no host synchronisation (a caller may
+    capture it in a HIP graph per batch shape)."""
+
+    def __init__(self, grid, phys, blocking, kpix, kticks, resp, n_ev_max, n_dep_max, val_cap,
+                 block_cap, pix_cap, fft=None, mpcp=True, batch=64, plan=None):
+        import torch
+        dev = "cuda"
+        self.grid, self.phys, self.blocking = grid_struct(grid), physics_struct(phys), \
+            blocking_struct(blocking)
+        self.n_ev_max, self.n_dep_max = int(n_ev_max), int(n_dep_max)
+        if plan is None:
+            plan = ConvPlan(grid, blocking, kpix, kticks, fft, mpcp, batch)
+            plan.set_response(resp)
+        self.plan = plan
+        g, b = self.grid, self.blocking
+        self.fp = torch.empty((self.n_dep_max, 6), dtype=torch.int32, device=dev)
+        self.off = torch.empty(self.n_dep_max + 1, dtype=torch.int64, device=dev)
+        self.val = torch.empty(int(val_cap), dtype=torch.float32, device=dev)
+        self.charge_sum = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.keys = torch.empty((int(block_cap), 4), dtype=torch.int32, device=dev)
+        self.n_active = torch.zeros(1, dtype=torch.int32, device=dev)
+        vblk = b.blk_pix[0] * g.sub[0] * b.blk_pix[1] * g.sub[1] * b.blk_ticks
+        self.blocks = torch.empty((int(block_cap), vblk), dtype=torch.float32, device=dev)
+        o = self.plan.out_shape
+        self.out_blocks = torch.empty((int(block_cap), o[0] * o[1] * o[2]), dtype=torch.float32,
+                                      device=dev)
+        self.bin_work = torch.empty(max(4, tred_block_bin_events_workspace(g, b, self.n_ev_max)),
+                                    dtype=torch.uint8, device=dev)
+        self.pix = torch.empty(int(pix_cap), dtype=torch.int32, device=dev)
+        self.n_pix = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.lwf = g.nticks + int(kticks) - 1
+        self.wf = torch.empty((int(pix_cap), self.lwf), dtype=torch.float32, device=dev)
+        self.scat_work = torch.empty(
+            max(4, tred_scatter_events_workspace(self.plan, self.n_ev_max)), dtype=torch.uint8,
+            device=dev)
+
+    def run(self, seg, ev_off, stream=None):
+        """seg: float32 [n, 7] device (n <= n_dep_max); ev_off: int64 device [n_ev + 1]."""
+        n, n_ev = seg.shape[0], ev_off.numel() - 1
+        if n > self.n_dep_max or n_ev > self.n_ev_max:
+            raise ValueError("batch exceeds the pipeline's capacities")
+        fp, off = self.fp[:n], self.off[:n + 1]
+        tred_effq_windows(self.grid, self.phys, seg, fp, off, stream)
+        self.charge_sum.zero_()
+        tred_effq(self.grid, self.phys, seg, fp, off, self.val, self.charge_sum, stream)
+        tred_block_bin_events(self.grid, self.blocking, ev_off, fp, off, self.val, self.keys,
+                              self.n_active, self.blocks, self.bin_work, stream)
+        tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
+        tred_scatter_waveforms_events(self.plan, n_ev, self.keys, self.n_active, self.out_blocks,
+                                      self.pix, self.n_pix, self.wf, self.scat_work, stream)
+
+    def results(self, n_dep=None):
+        """Host copies of the outputs of the last run (synchronises)."""
+        import torch
+        torch.cuda.synchronize()
+        n = self.n_dep_max if n_dep is None else int(n_dep)
+        na = int(self.n_active.item())
+        npx = int(self.n_pix.item())
+        return dict(fp=self.fp[:n].cpu().numpy(), off=self.off[:n + 1].cpu().numpy(),
+                    n_active=na, keys=self.keys[:min(na, self.keys.shape[0])].cpu().numpy(),
+                    n_pix=npx, pix=self.pix[:min(npx, self.pix.shape[0])].cpu().numpy(),
+                    wf=self.wf[:min(npx, self.pix.shape[0])].cpu().numpy(),
+                    charge_sum=float(self.charge_sum.item()))
+
+
+def size_batch(grid, phys, blocking, kpix, seg, ev_off):
+    """Capacities of a batch (as size_event, with the event dimension)."""
+    import torch
+    n = seg.shape[0]
+    fp = torch.empty((n, 6), dtype=torch.int32, device="cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    tred_effq_windows(grid, phys, seg, fp, off)
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    eo = torch.from_numpy(np.asarray(ev_off, np.int64)).cuda()
+    na = torch.zeros(1, dtype=torch.int32, device="cuda")
+    work = torch.empty(max(4, tred_block_bin_events_workspace(g, b, eo.numel() - 1)),
+                       dtype=torch.uint8, device="cuda")
+    dummy = torch.empty(1, dtype=torch.float32, device="cuda")
+    tred_block_bin_events(g, b, eo, fp, off, dummy, None, na, None, work)
+    torch.cuda.synchronize()
+    val_cap = int(off[-1].item())
+    block_cap = int(na.item())
+    per = (b.blk_pix[0] + kpix[0] - 1) * (b.blk_pix[1] + kpix[1] - 1)
+    pix_cap = min((eo.numel() - 1) * int(g.npix[0]) * int(g.npix[1]), block_cap * per)
+    return max(val_cap, 1), max(block_cap, 1), max(pix_cap, 1)
 
 
 def plan_workspace_bytes(grid, blocking, kpix, kticks, fft=None, mpcp=True, batch=1) -> int:

@@ -225,6 +225,24 @@ def gen_module_event(n_dep: int, xy_extent: Tuple[float, float], z_max: float = 
     return seg.astype(np.float32)
 
 
+def gen_event_batch(n_ev: int = 64, n_range=(1_000, 200_000), npix: int = 256,
+                    nticks: int = 6250, seed: int = 1):
+    """A batch of module-scale events of uneven size: deposition counts log-uniform in
+    n_range, each generated like the module event with a per-event mix of tracks
+    (5-60) and blobs (2-30). Returns a list of float32 [n_e, 7] arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ext = (npix * PITCH, npix * PITCH)
+    zmax = nticks * TICK * V_DRIFT
+    out = []
+    for e in range(n_ev):
+        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        nt = int(rng.integers(5, 61))
+        nb = int(rng.integers(2, 31))
+        out.append(gen_module_event(n, ext, zmax, n_tracks=nt, n_blobs=nb,
+                                    seed=int(rng.integers(1, 2**31))))
+    return out
+
+
 def gen_segments(cfg: Config, seed: Optional[int] = None) -> np.ndarray:
     seed = cfg.seed if seed is None else seed
     g = cfg.grid
