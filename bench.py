@@ -299,6 +299,8 @@ def main():
                     help="bound on the convolution scratch (sets the bins per pass)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--workload", default="module", choices=["module", "plain-small"],
+                    help="module: the benchmark event; plain-small: the 1,000-segment event")
     ap.add_argument("--events", type=int, default=64, help="events of the batched form")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="device memory of a chunk")
     ap.add_argument("--pass-gb", type=float, default=60.0, help="convolution scratch per pass")
@@ -338,7 +340,7 @@ def main():
     import workloads as W
     from paper_2602_12052_amd import tred
 
-    cfg = W.cfg_module(args.seed)
+    cfg = W.cfg_module(args.seed) if args.workload == "module" else W.cfg_plain_small(args.seed)
     seg = W.gen_segments(cfg)
     resp = W.synthetic_response(cfg.kpix, cfg.grid.sub, cfg.kticks)
     dev_seg = torch.from_numpy(seg).cuda()
@@ -397,6 +399,7 @@ def main():
     wall = time.perf_counter() - t0
 
     n_dep = seg.shape[0]
+    n_bins_total = tred.tred_block_count(cfg.grid, cfg.blocking)
     n_act = int(pl.n_active.item())
     n_pix = int(pl.n_pix.item())
     ms_per_step = 1e3 * wall / args.steps
@@ -409,7 +412,7 @@ def main():
     sp_ms = float(conv_stages[:, 1].mean())
     achieved = fl["sp"] * sp_blocks / (sp_ms * 1e-3) / 1e12
     sha = src_sha(["paper_2602_12052_amd/csrc/conv.hip", "paper_2602_12052_amd/csrc/tred_internal.hpp"])
-    traffic = profile_traffic("k_spp", sha)
+    traffic = profile_traffic("k_spp", sha) if args.workload == "module" else None
     vblk = Bx * cfg.grid.sub[0] * By * cfg.grid.sub[1] * Bt
     vout = box * boy * (Bt + cfg.kticks - 1)
     lwf = cfg.grid.nticks + cfg.kticks - 1
@@ -429,11 +432,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "module-scale event: 1e5 line depositions (40 tracks at 0.5 mm steps + "
-                        "20 shower blobs), 256x256 pixels x 6250 ticks, 10x10 impacts/pixel, "
-                        "response 21x21 px x 2048 ticks, bins 16x16 px x 512 ticks",
-            "n_dep": n_dep, "active_bins": n_act, "bins_total": 16 * 16 * 13,
-            "active_fraction": n_act / (16 * 16 * 13), "pixels": n_pix,
+            "workload": ("module-scale event: 1e5 line depositions (40 tracks at 0.5 mm steps + "
+                         "20 shower blobs), 256x256 pixels x 6250 ticks, 10x10 impacts/pixel, "
+                         "response 21x21 px x 2048 ticks, bins 16x16 px x 512 ticks"
+                         if args.workload == "module" else
+                         "1,000 line segments in 32x32 pixels x 6250 ticks, 10x10 impacts/pixel, "
+                         "response 5x5 px x 200 ticks, bins 4x4 px x 128 ticks"),
+            "n_dep": n_dep, "active_bins": n_act, "bins_total": n_bins_total,
+            "active_fraction": n_act / n_bins_total, "pixels": n_pix,
             "fft": list(cfg.fft), "response_pieces": nc,
             "packing": "mirror-pair" if mpcp else "complex-of-real", "bins_per_conv_pass": batch,
         },
@@ -444,7 +450,8 @@ def main():
                      "conv_space_mac": float(conv_stages[:, 1].mean()),
                      "conv_time_inv": float(conv_stages[:, 2].mean())},
         "roofline": {
-            "kernel": "k_spp<40,8,16,2> (spatial transforms + spectral multiply-accumulate)",
+            "kernel": ("k_spp<40,8,16,2>" if args.workload == "module" else "k_spp<8,8,8,1>") +
+                      " (spatial transforms + spectral multiply-accumulate)",
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
             "flops_per_launch": fl["sp"] * sp_blocks, "avg_launch_ms": sp_ms,

@@ -3,7 +3,7 @@
 // frequency domain, one inverse per block; mirror-pair complex packing, eq. multch).
 //
 // Per block and impact channel j the transform is separable:
-//   k_tf : time FFT (length ft) of every (channel, pixel) row   -> T[b][j][p/8][f][p%8]
+//   k_tf : time FFT (length ft) of every (channel, pixel) row   -> T[b][j][p/16][f][p%16]
 //   k_sp : per time frequency f, 2-D spatial FFT of each channel (block pixels zero
 //          padded to fs x fs), multiply-accumulate with the precomputed response
 //          spectra of every response piece, inverse spatial FFT   -> U[b][c][q/8][f][q%8]
@@ -25,6 +25,10 @@
 // bins per workgroup of the prime-factor spatial stage with 8-point sub-DFTs
 #ifndef TRED_SPP_NB8
 #define TRED_SPP_NB8 2
+#endif
+// XCD-aware workgroup order in the spatial stage (1) or the dispatch order (0)
+#ifndef TRED_XCD_REMAP
+#define TRED_XCD_REMAP 1
 #endif
 // wave-level ordering inside the inverse time FFTs (1) or workgroup barriers (0)
 #ifndef TRED_TI_WAVESYNC
@@ -205,14 +209,16 @@ __global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* _
     }
     wave_fft<FT, true>(v, lds + wv * kFftLds<FT>, tw, lane);
     __syncthreads();   // the staging tile overlaps the other waves' FFT scratch
-    float2* stage = (float2*)lds;
+    float2* stage = (float2*)lds;   // [f][kTileP]: odd row stride keeps the wave's writes conflict free
 #pragma unroll
-    for (int m = 0; m < M; ++m) stage[(lane + kWave * m) * kTile + wv] = v[m];
+    for (int m = 0; m < M; ++m) stage[(lane + kWave * m) * kTileP + wv] = v[m];
     __syncthreads();
-    const int64_t base = (((int64_t)bl * A.nch + ch) * (A.ppad / kTile) + blockIdx.x) * FT * kTile;
-    float4* d4 = (float4*)(T + base);
-    const float4* s4 = (const float4*)stage;
-    for (int i = threadIdx.x; i < FT * kTile / 2; i += blockDim.x) d4[i] = s4[i];
+    // T tiles hold kTileT = 2 kTile pixels per frequency (one 128-byte line); this
+    // workgroup's 8 rows are one half of tile blockIdx.x / 2
+    const int pt = blockIdx.x >> 1, half = blockIdx.x & 1;
+    float2* d2 = T + (((int64_t)bl * A.nch + ch) * (A.ppad / kTileT) + pt) * FT * kTileT + half * kTile;
+    for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x)
+        d2[(i / kTile) * kTileT + (i % kTile)] = stage[(i / kTile) * kTileP + (i % kTile)];
 }
 
 // ---------------------------------------------------------------------------
@@ -287,7 +293,7 @@ void k_sp(ConvArgs A, int b0, int nbp,
     const int fl = active ? tid / TPF : 0, item = tid % TPF;
     const int kx = item / RS, ry = item % RS;
     const int By = A.By, Bx = A.Bx, CHX = A.chx, ppad = A.ppad, box = A.box, boy = A.boy;
-    const int ptiles = ppad / kTile;
+    const int ptiles = ppad / kTileT;
     const SpLds Ls = sp_lds(FS, L, NF, CHX, By, ppad, box, boy);
     const int P1 = Ls.P1, GL = Ls.GL, YB = Ls.YB;
     float2* twl = sm;                        // exp(-2 pi i k / fs)
@@ -302,9 +308,9 @@ void k_sp(ConvArgs A, int b0, int nbp,
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int m = 0; m < L; ++m) acc[c][m] = make_float2(0.f, 0.f);
-    const int nld = CHX * ptiles * NF * kTile;
+    const int nld = CHX * ptiles * NF * kTileT;
     const int nx = CHX * NF * By * RS;
-    const int64_t tstride = (int64_t)ptiles * A.ft * kTile;   // one channel of T
+    const int64_t tstride = (int64_t)ptiles * A.ft * kTileT;   // one channel of T
     const float2* Tb = T + (int64_t)bl * A.nch * tstride;
     // response spectra of (channel, frequency): nc * L values per thread at fixed offsets
     const int64_t rstride = (int64_t)A.nc * L * TPF;
@@ -313,16 +319,16 @@ void k_sp(ConvArgs A, int b0, int nbp,
     for (int j0 = 0; j0 < A.nch; j0 += CHX) {
         // stage the time spectra of CHX channels at frequencies f0 .. f0+NF-1
         for (int i = tid; i < nld; i += NT) {
-            const int pi = i % kTile;
-            int r = i / kTile;
+            const int pi = i % kTileT;
+            int r = i / kTileT;
             const int fl2 = r % NF;
             r /= NF;
             const int pt = r % ptiles;
             const int cx = r / ptiles;
             const int ch = j0 + cx;
             float2 z = make_float2(0.f, 0.f);
-            if (ch < A.nch) z = Tb[ch * tstride + (pt * A.ft + f0 + fl2) * kTile + pi];
-            zbuf[(cx * NF + fl2) * ppad + pt * kTile + pi] = z;
+            if (ch < A.nch) z = Tb[ch * tstride + (pt * A.ft + f0 + fl2) * kTileT + pi];
+            zbuf[(cx * NF + fl2) * ppad + pt * kTileT + pi] = z;
         }
         __syncthreads();
         // x pass: for each (channel, frequency, py, rx): L-point DFT over the folded px
@@ -558,13 +564,20 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
     static_assert(NIN % 2 == 0 && NIN <= 2 * L, "input padding");
     extern __shared__ float4 sm4[];
     float2* sm = (float2*)sm4;
-    // bins vary fastest across the grid (response spectra shared through L2)
+    // Bins vary fastest in the logical order (response spectra shared through L2).
+    // Workgroup ids are dealt round-robin to the XCDs; the logical index is remapped so
+    // that each XCD walks a contiguous range of frequencies and the response-spectrum
+    // slab of a frequency is fetched into one XCD's L2 only.
+    const unsigned nbg = gridDim.x, total = gridDim.x * gridDim.y;
+    const unsigned wid = blockIdx.y * nbg + blockIdx.x;
+    unsigned lid = wid;
+    if (TRED_XCD_REMAP && total % kXcd == 0) lid = (wid % kXcd) * (total / kXcd) + wid / kXcd;
     const int na = min(*n_active, A.cap);
     const int nloc = min(nbp, na - b0);
-    const int bl0 = blockIdx.x * NB;
+    const int bl0 = (int)(lid % nbg) * NB;
     if (bl0 >= nloc) return;
     const int nbv = min(NB, nloc - bl0);
-    const int f0 = blockIdx.y * NF;
+    const int f0 = (int)(lid / nbg) * NF;
     const int tid = threadIdx.x;
     const bool active = tid < NF * TPF;
     const int fl = active ? tid / TPF : 0, item = tid % TPF;
@@ -579,8 +592,8 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
     float2* abuf = regA + Ls.zsz;           // [NB][NF][FS kx][P1 py]
     for (int i = tid; i < FS; i += NT) twl[i] = tws[i];
 
-    const int ptiles = A.ppad / kTile;
-    const int64_t tstride = (int64_t)ptiles * A.ft * kTile;   // one channel of T
+    const int ptiles = A.ppad / kTileT;
+    const int64_t tstride = (int64_t)ptiles * A.ft * kTileT;   // one channel of T
     const float2* Tb = T + (int64_t)bl0 * A.nch * tstride;
     float2 zpre[ZPT];
     auto load_T = [&](int ch) {
@@ -598,7 +611,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
                 if (b < nbv && px < Bx && py < By) {
                     const int p = px * By + py;
                     zpre[k] = Tb[((int64_t)b * A.nch + ch) * tstride +
-                                 ((int64_t)(p / kTile) * A.ft + f0 + fl2) * kTile + p % kTile];
+                                 ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT + p % kTileT];
                 }
             }
         }
@@ -813,7 +826,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
 // ---------------------------------------------------------------------------
 // Four waves per SIMD (two 8-wave workgroups per CU; the compiler's choice of 145
 // registers at ft = 1024 leaves one) for a spill of a few registers.
-template <int FT>
+template <int FT, bool CARRY>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 ? 4 : 1))) void k_ti(ConvArgs A, int b0, const int32_t* __restrict__ n_active,
                                             const float2* __restrict__ U,
                                             const float2* __restrict__ tw, float* __restrict__ out) {
@@ -827,27 +840,51 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     const bool valid = q < A.box * A.boy;
     const int qtiles = A.qpad / kTile;
     float* orow = out + (int64_t)b * A.vout + (int64_t)(valid ? q : 0) * A.bot;
+    // CARRY (pieces of half the transform length, ct = Bt = FT / 2): the second half of
+    // piece c overlaps only the first half of piece c + 1, so it is carried in
+    // registers and every output tick is written once; otherwise overlaps are added
+    // in memory
+    constexpr int MH = M / 2;
+    float carry[MH];
+#pragma unroll
+    for (int m = 0; m < MH; ++m) carry[m] = 0.0f;
     for (int c = 0; c < A.nc; ++c) {
-        const float4* s4 = (const float4*)(U + ((((int64_t)bl * A.nc + c) * qtiles + qt) * FT) * kTile);
-        float4* d4 = (float4*)lds;
-        for (int i = threadIdx.x; i < FT * kTile / 2; i += blockDim.x) d4[i] = s4[i];
+        const float2* s2 = U + ((((int64_t)bl * A.nc + c) * qtiles + qt) * FT) * kTile;
+        float2* stage = (float2*)lds;   // [f][kTileP]
+        for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x)
+            stage[(i / kTile) * kTileP + (i % kTile)] = s2[i];
         __syncthreads();
-        const float2* stage = (const float2*)lds;
         float2 v[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) v[m] = cconj(stage[(lane + kWave * m) * kTile + wv]);
+        for (int m = 0; m < M; ++m) v[m] = cconj(stage[(lane + kWave * m) * kTileP + wv]);
         __syncthreads();
         wave_fft<FT, TRED_TI_WAVESYNC>(v, lds + wv * kFftLds<FT>, tw, lane);
         __syncthreads();   // the next piece's tile overlaps the other waves' FFT scratch
         if (valid) {
+            if constexpr (CARRY) {
+                const bool last = c == A.nc - 1;
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const int t = lane + kWave * m;
-                const int a = c * A.ct + t;
-                if (a < A.bot) {
-                    const float r = v[m].x;  // Re conj(.) = Re(.)
-                    if (c > 0 && t < A.Bt) orow[a] += r;
-                    else orow[a] = r;
+                for (int m = 0; m < M; ++m) {
+                    const int a = c * A.ct + lane + kWave * m;
+                    const float r = v[m].x;   // Re conj(.) = Re(.)
+                    if (m < MH) {
+                        if (a < A.bot) orow[a] = r + carry[m];
+                    } else if (last) {
+                        if (a < A.bot) orow[a] = r;
+                    } else {
+                        carry[m - MH] = r;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int t = lane + kWave * m;
+                    const int a = c * A.ct + t;
+                    if (a < A.bot) {
+                        const float r = v[m].x;
+                        if (c > 0 && t < A.Bt) orow[a] += r;
+                        else orow[a] = r;
+                    }
                 }
             }
         }
@@ -895,7 +932,7 @@ ConvArgs make_args(const tred_conv_plan* P) {
     A.ct = P->ct;
     A.ft = P->ft;
     A.fs = P->fs;
-    A.ppad = (A.Bx * A.By + kTile - 1) / kTile * kTile;
+    A.ppad = (A.Bx * A.By + kTileT - 1) / kTileT * kTileT;
     A.qpad = P->qpad;
     A.box = P->bo[0];
     A.boy = P->bo[1];
@@ -941,7 +978,7 @@ void allow_lds(K kernel, size_t bytes) {
 template <int FT>
 tred_status launch_time_fwd(const ConvArgs& A, int b0, int nb, const int32_t* na, const float* blocks,
                             const float2* tw, float2* T, hipStream_t st) {
-    const size_t lds = (size_t)8 * kFftLds<FT> * sizeof(float);
+    const size_t lds = std::max((size_t)8 * kFftLds<FT> * sizeof(float), (size_t)FT * kTileP * sizeof(float2));
     allow_lds(k_tf<FT>, lds);
     hipLaunchKernelGGL((k_tf<FT>), dim3(A.ppad / kTile, A.nch, nb), dim3(512), lds, st, A, b0, na,
                        blocks, tw, T);
@@ -951,10 +988,16 @@ tred_status launch_time_fwd(const ConvArgs& A, int b0, int nb, const int32_t* na
 template <int FT>
 tred_status launch_time_inv(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* U,
                             const float2* tw, float* out, hipStream_t st) {
-    const size_t lds = (size_t)8 * kFftLds<FT> * sizeof(float);
-    allow_lds(k_ti<FT>, lds);
-    hipLaunchKernelGGL((k_ti<FT>), dim3(A.qpad / kTile, nb), dim3(512), lds, st, A, b0, na, U, tw,
-                       out);
+    const size_t lds = std::max((size_t)8 * kFftLds<FT> * sizeof(float), (size_t)FT * kTileP * sizeof(float2));
+    if (A.ct == A.Bt && 2 * A.ct == FT) {
+        allow_lds(k_ti<FT, true>, lds);
+        hipLaunchKernelGGL((k_ti<FT, true>), dim3(A.qpad / kTile, nb), dim3(512), lds, st, A, b0, na,
+                           U, tw, out);
+    } else {
+        allow_lds(k_ti<FT, false>, lds);
+        hipLaunchKernelGGL((k_ti<FT, false>), dim3(A.qpad / kTile, nb), dim3(512), lds, st, A, b0, na,
+                           U, tw, out);
+    }
     return tred_check_launch("tred_block_conv time inverse");
 }
 
@@ -964,7 +1007,7 @@ tred_status launch_space(const ConvArgs& A0, int b0, int nb, const int32_t* na, 
     using S = SpShape<FS, L>;
     constexpr int MAXIT = 2;   // per-thread staging / x-pass items the kernel unrolls
     ConvArgs A = A0;
-    const int per_ch_ld = (A.ppad / kTile) * S::NF * kTile;
+    const int per_ch_ld = A.ppad * S::NF;
     const int per_ch_x = S::NF * A.By * S::RS;
     A.chx = std::min(std::max(1, FS / A.By),
                      std::min(MAXIT * S::NT / per_ch_ld, MAXIT * S::NT / per_ch_x));
@@ -1086,7 +1129,7 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     const int S = grid->sub[0] * grid->sub[1];
     P->nch = P->mpcp ? (S + 1) / 2 : S;
     P->qpad = (P->bo[0] * P->bo[1] + kTile - 1) / kTile * kTile;
-    const int64_t ppad = (Bx * By + kTile - 1) / kTile * kTile;
+    const int64_t ppad = (Bx * By + kTileT - 1) / kTileT * kTileT;
     // workspace layout
     int64_t o = 0;
     P->off_tw_t = o;

@@ -145,11 +145,14 @@ struct EffqParams {
     float u[16];   // per-axis spread weights over the node stencil of one grid point
 };
 
-// erf(b) - erf(a), through erfc when both arguments share a sign (no cancellation
-// of the tails)
+// erf(b) - erf(a) for a < b, through erfc when both arguments share a sign (no
+// cancellation of the tails): erfc(a) - erfc(b) for a >= 0, erfc(-b) - erfc(-a) for
+// b <= 0 (one code path for both, so a wave runs at most two of them)
 __device__ __forceinline__ float erf_diff(float b, float a) {
-    if (a >= 0.0f && b >= 0.0f) return erfcf(a) - erfcf(b);
-    if (a <= 0.0f && b <= 0.0f) return erfcf(-b) - erfcf(-a);
+    if (a >= 0.0f || b <= 0.0f) {
+        const bool pos = a >= 0.0f;
+        return erfcf(pos ? a : -b) - erfcf(pos ? b : -a);
+    }
     return erff(b) - erff(a);
 }
 

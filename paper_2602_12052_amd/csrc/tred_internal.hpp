@@ -19,6 +19,7 @@ tred_status tred_check_launch(const char* what);
     } while (0)
 
 constexpr int kWave = 64;
+constexpr unsigned kXcd = 8;   // XCDs of an MI355X; workgroup ids are dealt to them round-robin
 
 // ---------------------------------------------------------------------------
 // complex arithmetic on float2
@@ -355,3 +356,5 @@ struct tred_conv_plan {
 };
 
 constexpr int kTile = 8;   // pixels per interleaved tile of the spectral scratch
+constexpr int kTileP = kTile + 1;   // LDS row stride of a staged tile (odd: no bank conflicts)
+constexpr int kTileT = 2 * kTile;   // pixels per frequency in a tile of the time spectra T (128 B)
