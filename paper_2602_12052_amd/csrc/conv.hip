@@ -183,7 +183,21 @@ __global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* _
     if (b >= min(*n_active, A.cap)) return;
     const int ch = blockIdx.y;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int p = blockIdx.x * kTile + wv;
+    // T tiles hold kTileT = 2 kTile pixels per frequency (one 128-byte line); a
+    // workgroup transforms the 8 rows of one half of a tile. Workgroup ids are dealt
+    // to the XCDs round-robin, so the two halves of a tile go to workgroups kXcd ids
+    // apart (same XCD, same L2) when there are whole groups of kXcd tiles.
+    const int ntile = A.ppad / kTileT;
+    int pt, half;
+    if (ntile % (int)kXcd == 0) {
+        const int g = blockIdx.x / (2 * kXcd), r = blockIdx.x % (2 * kXcd);
+        pt = g * kXcd + r % kXcd;
+        half = r / kXcd;
+    } else {
+        pt = blockIdx.x >> 1;
+        half = blockIdx.x & 1;
+    }
+    const int p = pt * kTileT + half * kTile + wv;
     const int jx = ch / A.sy, jy = ch % A.sy;
     const int jb = A.S - 1 - ch;
     const bool pair = A.mpcp && jb != ch;
@@ -213,9 +227,6 @@ __global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* _
 #pragma unroll
     for (int m = 0; m < M; ++m) stage[(lane + kWave * m) * kTileP + wv] = v[m];
     __syncthreads();
-    // T tiles hold kTileT = 2 kTile pixels per frequency (one 128-byte line); this
-    // workgroup's 8 rows are one half of tile blockIdx.x / 2
-    const int pt = blockIdx.x >> 1, half = blockIdx.x & 1;
     float2* d2 = T + (((int64_t)bl * A.nch + ch) * (A.ppad / kTileT) + pt) * FT * kTileT + half * kTile;
     for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x)
         d2[(i / kTile) * kTileT + (i % kTile)] = stage[(i / kTile) * kTileP + (i % kTile)];
@@ -554,7 +565,7 @@ __host__ __device__ inline SppLds spp_lds(int box, int boy) {
 }
 
 template <int FS, int L, int NIN, int NB>
-__global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
+__global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdgpu_waves_per_eu(2))) void k_spp(
     ConvArgs A, int b0, int nbp, const int32_t* __restrict__ n_active,
     const float2* __restrict__ T, const float2* __restrict__ rhat,
     const float2* __restrict__ tws, float2* __restrict__ U) {
@@ -579,8 +590,12 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
     const int nbv = min(NB, nloc - bl0);
     const int f0 = (int)(lid / nbg) * NF;
     const int tid = threadIdx.x;
+    // threads past the NF * TPF work items repeat the last item's work in the channel
+    // loop (keeps that loop free of branches, so loads can be waited for precisely);
+    // only active threads write results
     const bool active = tid < NF * TPF;
-    const int fl = active ? tid / TPF : 0, item = tid % TPF;
+    const int tw_ = active ? tid : NF * TPF - 1;
+    const int fl = tw_ / TPF, item = tw_ % TPF;
     const int kx = item / RS, k2 = item % RS;
     const int Bx = A.Bx, By = A.By, box = A.box, boy = A.boy;
     const SppLds Ls = spp_lds<FS, L, NIN, NB, NF>(box, boy);
@@ -595,32 +610,38 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
     const int ptiles = A.ppad / kTileT;
     const int64_t tstride = (int64_t)ptiles * A.ft * kTileT;   // one channel of T
     const float2* Tb = T + (int64_t)bl0 * A.nch * tstride;
+    // Staged time spectra of one channel: element i of zbuf (py fastest, then px, fl,
+    // bin) comes from T at a fixed per-thread offset plus the channel stride. The
+    // loads are unconditional (elements outside the bin read a valid element of bin 0
+    // and are masked when stored), so that no wait for them is forced before the
+    // arithmetic that follows.
+    int64_t zoff[ZPT];
+    bool zval[ZPT];
+#pragma unroll
+    for (int k = 0; k < ZPT; ++k) {
+        const int i = tid + k * NT;
+        const int py = i % NIN;
+        int r = i / NIN;
+        const int px = r % NIN;
+        r /= NIN;
+        const int fl2 = r % NF;
+        const int b = r / NF;
+        zval[k] = i < NZ && b < nbv && px < Bx && py < By;
+        const int p = px * By + py;
+        zoff[k] = zval[k] ? ((int64_t)b * A.nch) * tstride +
+                                ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT + p % kTileT
+                          : (int64_t)f0 * kTileT;
+    }
     float2 zpre[ZPT];
     auto load_T = [&](int ch) {
 #pragma unroll
-        for (int k = 0; k < ZPT; ++k) {
-            const int i = tid + k * NT;
-            zpre[k] = make_float2(0.f, 0.f);
-            if (i < NZ) {
-                const int py = i % NIN;
-                int r = i / NIN;
-                const int px = r % NIN;
-                r /= NIN;
-                const int fl2 = r % NF;
-                const int b = r / NF;
-                if (b < nbv && px < Bx && py < By) {
-                    const int p = px * By + py;
-                    zpre[k] = Tb[((int64_t)b * A.nch + ch) * tstride +
-                                 ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT + p % kTileT];
-                }
-            }
-        }
+        for (int k = 0; k < ZPT; ++k) zpre[k] = Tb[zoff[k] + (int64_t)ch * tstride];
     };
     auto store_T = [&]() {
 #pragma unroll
         for (int k = 0; k < ZPT; ++k) {
             const int i = tid + k * NT;
-            if (i < NZ) zbuf[i] = zpre[k];
+            if (i < NZ) zbuf[i] = zval[k] ? zpre[k] : make_float2(0.f, 0.f);
         }
     };
 
@@ -667,8 +688,21 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
             for (int m = 0; m < L; ++m) ar[P::k_of(m, kk) * P1] = t[m];
         }
         __syncthreads();
-        if (ch + 1 < A.nch) load_T(ch + 1);
-        // y pass and multiply-accumulate with the response spectra of every piece
+        // y pass and multiply-accumulate with the response spectra of every piece. The
+        // spectra of piece 0 are requested before the y pass and those of piece c + 1
+        // before the multiply-adds of piece c (two register buffers), so L2 latency is
+        // covered by arithmetic; the next channel's time spectra are requested after
+        // piece 0's, so waits for the spectra never wait for them. Everything is
+        // unconditional: pieces past nc load piece nc - 1 again and accumulate into
+        // slots that are never read, the last channel prefetches itself again.
+        const float2* rh = rhat + ((int64_t)ch * A.ft + f0 + fl) * rstride + item;
+        const int clast = A.nc - 1;
+        float2 w[2][L];
+#pragma unroll
+        for (int m = 0; m < L; ++m) w[0][m] = rh[m * TPF];
+        __builtin_amdgcn_sched_barrier(0);   // vector loads complete in issue order
+        load_T(min(ch + 1, A.nch - 1));
+        __builtin_amdgcn_sched_barrier(0);
         if (active) {
             float2 s[NB][L];
 #pragma unroll
@@ -684,21 +718,23 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) void k_spp(
                 pfa_gather<L, RS, NIN>(x, wy, s[b]);
                 Dft<L>::run(s[b]);
             }
-            const float2* rh = rhat + ((int64_t)ch * A.ft + f0 + fl) * rstride + item;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                if (c < A.nc) {
-                    float2 w[L];
+                if (c < 3) {
+                    const int cn = min(c + 1, clast);
 #pragma unroll
-                    for (int m = 0; m < L; ++m) w[m] = rh[(c * L + m) * TPF];
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-#pragma unroll
-                        for (int m = 0; m < L; ++m) acc[b][c][m] = cfma(s[b][m], w[m], acc[b][c][m]);
+                    for (int m = 0; m < L; ++m) w[(c + 1) & 1][m] = rh[(cn * L + m) * TPF];
                 }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int m = 0; m < L; ++m)
+                        acc[b][c][m] = cfma(s[b][m], w[c & 1][m], acc[b][c][m]);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
-        if (ch + 1 < A.nch) store_T();
+        store_T();
         __syncthreads();
     }
 

@@ -190,7 +190,9 @@ struct Idx3 {
 // cells outside the quadrature window) are evaluated once into LDS, so that the
 // spread stencil of every output cell (the S = NGL + 2 (NGL / 2) nodes per axis of
 // cells g-1, g, g+1 that reach g) lies inside the tile and the 3-D gather is fully
-// unrolled with constant offsets.
+// unrolled. Along t (the axis consecutive lanes walk) the nodes are stored in planes
+// of equal local index, V[..][l][cell], so the lanes' stencil reads are unit-stride
+// (no LDS bank conflicts); along x and y they are interleaved, V[cell * NGL + l].
 template <int NGL, int CAP, int NT>
 __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                                              const float* __restrict__ seg,
@@ -301,6 +303,7 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                     const int Z1 = min(Z0 + T[2] - 1, F1[2]);
                     const int t0c[3] = {X0, Y0, Z0}, t1c[3] = {X1, Y1, Z1};
                     int nn[3], own0[3], own1[3];
+                    const int nct = t1c[2] - t0c[2] + 3;          // padded cells along t
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         nn[a] = (t1c[a] - t0c[a] + 3) * NGL;   // cells t0c-1 .. t1c+1
@@ -316,7 +319,10 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                         for (int i = tid; i < total; i += NT, it.next()) {
                             const int cx = X0 - 1 + it.i / NGL, lx = it.i % NGL;
                             const int cy = Y0 - 1 + it.j / NGL, ly = it.j % NGL;
-                            const int ct = Z0 - 1 + it.k / NGL, lt = it.k % NGL;
+                            int lt;
+                            if constexpr (NGL == 2) lt = it.k >= nct ? 1 : 0;
+                            else lt = it.k / nct;
+                            const int ct = Z0 - 1 + (it.k - lt * nct);
                             const bool inside = cx >= C0[0] && cx <= C1[0] && cy >= C0[1] &&
                                                 cy <= C1[1] && ct >= C0[2] && ct <= C1[2];
                             float vq = 0.0f;
@@ -364,12 +370,22 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                         const int nx = X1 - X0 + 1, ny = Y1 - Y0 + 1, nz = Z1 - Z0 + 1;
                         const int count = nx * ny * nz;
                         const int sxs = nn[1] * nn[2], sys = nn[2];
+                        // t stencil: nodes NGL-NPOS.. of cell g-1, all of g, ..NPOS-1 of g+1,
+                        // at plane l, cell offset -1 / 0 / +1 from g
+                        int offt[S];
+#pragma unroll
+                        for (int c = 0; c < S; ++c) {
+                            const int l = c < NPOS ? NGL - NPOS + c : (c < NPOS + NGL ? c - NPOS : c - NPOS - NGL);
+                            const int dc = c < NPOS ? -1 : (c < NPOS + NGL ? 0 : 1);
+                            offt[c] = l * nct + dc;
+                        }
                         Idx3 it;
                         it.init(tid, NT, ny, nz);
                         for (int k = tid; k < count; k += NT, it.next()) {
-                            // first stencil node of cell g: node NGL - NPOS of cell g - 1
+                            // first x/y stencil node of cell g: node NGL - NPOS of cell g - 1;
+                            // along t cell g sits at padded index it.k + 1
                             const float* vb = V + (it.i * NGL + (NGL - NPOS)) * sxs +
-                                              (it.j * NGL + (NGL - NPOS)) * sys + it.k * NGL + (NGL - NPOS);
+                                              (it.j * NGL + (NGL - NPOS)) * sys + it.k + 1;
                             float acc = 0.0f;
 #pragma unroll
                             for (int a = 0; a < S; ++a) {
@@ -379,7 +395,7 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                                     const float* vr = vb + a * sxs + b * sys;
                                     float az = 0.0f;
 #pragma unroll
-                                    for (int c = 0; c < S; ++c) az = fmaf(su[c], vr[c], az);
+                                    for (int c = 0; c < S; ++c) az = fmaf(su[c], vr[offt[c]], az);
                                     ay = fmaf(su[b], az, ay);
                                 }
                                 acc = fmaf(su[a], ay, acc);
