@@ -316,7 +316,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path is "
-              f"single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+              f"single-GPU; sharding over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch

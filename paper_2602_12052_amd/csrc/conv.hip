@@ -189,7 +189,10 @@ __global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* _
     // apart (same XCD, same L2) when there are whole groups of kXcd tiles.
     const int ntile = A.ppad / kTileT;
     int pt, half;
-    if (ntile % (int)kXcd == 0) {
+    if (kTileT == kTile) {
+        pt = blockIdx.x;
+        half = 0;
+    } else if (ntile % (int)kXcd == 0) {
         const int g = blockIdx.x / (2 * kXcd), r = blockIdx.x % (2 * kXcd);
         pt = g * kXcd + r % kXcd;
         half = r / kXcd;

@@ -357,4 +357,8 @@ struct tred_conv_plan {
 
 constexpr int kTile = 8;   // pixels per interleaved tile of the spectral scratch
 constexpr int kTileP = kTile + 1;   // LDS row stride of a staged tile (odd: no bank conflicts)
-constexpr int kTileT = 2 * kTile;   // pixels per frequency in a tile of the time spectra T (128 B)
+// pixels per frequency in a tile of the time spectra T: 16 (one 128-byte line) or 8
+#ifndef TRED_TTILE
+#define TRED_TTILE 16
+#endif
+constexpr int kTileT = TRED_TTILE;
