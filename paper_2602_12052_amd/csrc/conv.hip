@@ -43,6 +43,7 @@ struct ConvArgs {
     int32_t ppad, qpad, box, boy, bot;
     int32_t mpcp, chx, cap;
     int32_t e1, e2;      // row order of the response spectra: ky = (e1 m + e2 ry) mod fs
+    int32_t rpair;       // response spectra stored as row pairs [m / 2][item][m % 2]
     int64_t vblk, vout;
 };
 
@@ -142,6 +143,9 @@ __global__ void k_rhat_x(ConvArgs A, int Kx, int Ky, const double2* __restrict__
 // item = kxf * RS + ry, kyf = (e1 m + e2 ry) mod fs: the order in which the spatial
 // kernels hold spectra (k_sp: kyf = ry + RS m; k_spp: the prime-factor output map),
 // so that the nc * L values a thread needs at one frequency lie at fixed offsets.
+// With rpair the rows m of one (ch, f, c) are stored in pairs, [m / 2][item][m % 2],
+// so that a thread reads two rows with one 16-byte load and a wave's loads are
+// contiguous.
 __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2* __restrict__ twd,
                          const double2* __restrict__ PB, float2* __restrict__ rhat) {
     const int RS = A.fs / L;
@@ -150,12 +154,19 @@ __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2*
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = i;
-        const int item = (int)(r % TPF); r /= TPF;
-        const int m = (int)(r % L); r /= L;
+        int item, m;
+        if (A.rpair) {
+            const int e = (int)(r % 2); r /= 2;
+            item = (int)(r % TPF); r /= TPF;
+            m = 2 * (int)(r % (L / 2)) + e; r /= L / 2;
+        } else {
+            item = (int)(r % TPF); r /= TPF;
+            m = (int)(r % L); r /= L;
+        }
+        const int kxf = item / RS, ry = item % RS;
         const int c = (int)(r % A.nc); r /= A.nc;
         const int f = (int)(r % A.ft); r /= A.ft;
         const int64_t cc = r * A.nc + c;  // ch * nc + c
-        const int kxf = item / RS, ry = item % RS;
         const int kyf = (A.e1 * m + A.e2 * ry) % A.fs;
         double re = 0.0, im = 0.0;
         for (int ky = 0; ky < Ky; ++ky) {
@@ -618,7 +629,9 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     // loads are unconditional (elements outside the bin read a valid element of bin 0
     // and are masked when stored), so that no wait for them is forced before the
     // arithmetic that follows.
-    int64_t zoff[ZPT];
+    // (byte offsets from channel ch of bin bl0; the host keeps NB channels' worth of
+    // bins below 2^31 bytes)
+    uint32_t zoff[ZPT];
     bool zval[ZPT];
 #pragma unroll
     for (int k = 0; k < ZPT; ++k) {
@@ -631,14 +644,17 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         const int b = r / NF;
         zval[k] = i < NZ && b < nbv && px < Bx && py < By;
         const int p = px * By + py;
-        zoff[k] = zval[k] ? ((int64_t)b * A.nch) * tstride +
-                                ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT + p % kTileT
-                          : (int64_t)f0 * kTileT;
+        zoff[k] = (uint32_t)(8 * (zval[k] ? ((int64_t)b * A.nch) * tstride +
+                                                ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT +
+                                                p % kTileT
+                                          : (int64_t)f0 * kTileT));
     }
     float2 zpre[ZPT];
     auto load_T = [&](int ch) {
+        const auto tr = buf_rsrc(Tb + (int64_t)ch * tstride,
+                                 (uint32_t)(((int64_t)nbv * A.nch - ch) * tstride * 8));
 #pragma unroll
-        for (int k = 0; k < ZPT; ++k) zpre[k] = Tb[zoff[k] + (int64_t)ch * tstride];
+        for (int k = 0; k < ZPT; ++k) zpre[k] = buf_f2(tr, zoff[k], 0u);
     };
     auto store_T = [&]() {
 #pragma unroll
@@ -662,7 +678,11 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     for (int j = 0; j < RS; ++j) wy[j] = twl[((j * k2) % RS) * L];
     store_T();
     __syncthreads();
-    const int64_t rstride = (int64_t)A.nc * L * TPF;
+    const int64_t rstride = (int64_t)A.nc * L * TPF;   // nc * fs * fs values per (ch, f)
+    // response spectra of (ch, f0 .. f0 + NF - 1) as row pairs [c][m / 2][item][m % 2]
+    const uint32_t rbytes = (uint32_t)(NF * rstride * 8);
+    const uint32_t rvoff = (uint32_t)(fl * rstride * 8 + item * 16);
+    static_assert(L % 2 == 0, "row pairs");
 
     for (int ch = 0; ch < A.nch; ++ch) {
         // x pass: for each (bin, frequency, py, k2x) an L-point DFT over the gathered px
@@ -698,11 +718,18 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         // piece 0's, so waits for the spectra never wait for them. Everything is
         // unconditional: pieces past nc load piece nc - 1 again and accumulate into
         // slots that are never read, the last channel prefetches itself again.
-        const float2* rh = rhat + ((int64_t)ch * A.ft + f0 + fl) * rstride + item;
+        const auto rr = buf_rsrc(rhat + ((int64_t)ch * A.ft + f0) * rstride, rbytes);
+        auto load_w = [&](float2* wv, int c) {
+#pragma unroll
+            for (int mp = 0; mp < L / 2; ++mp) {
+                const float4 v = buf_f4(rr, rvoff, (uint32_t)((c * L + 2 * mp) * TPF * 8));
+                wv[2 * mp] = make_float2(v.x, v.y);
+                wv[2 * mp + 1] = make_float2(v.z, v.w);
+            }
+        };
         const int clast = A.nc - 1;
         float2 w[2][L];
-#pragma unroll
-        for (int m = 0; m < L; ++m) w[0][m] = rh[m * TPF];
+        load_w(w[0], 0);
         __builtin_amdgcn_sched_barrier(0);   // vector loads complete in issue order
         load_T(min(ch + 1, A.nch - 1));
         __builtin_amdgcn_sched_barrier(0);
@@ -723,11 +750,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                if (c < 3) {
-                    const int cn = min(c + 1, clast);
-#pragma unroll
-                    for (int m = 0; m < L; ++m) w[(c + 1) & 1][m] = rh[(cn * L + m) * TPF];
-                }
+                if (c < 3) load_w(w[(c + 1) & 1], min(c + 1, clast));
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
@@ -989,9 +1012,11 @@ ConvArgs make_args(const tred_conv_plan* P) {
             if ((L * x) % RS == 1 % RS) { li = x; break; }
         A.e1 = (RS * rsi) % P->fs;
         A.e2 = RS > 1 ? (L * li) % P->fs : 0;
+        A.rpair = 1;   // k_spp reads rows in pairs (L is 8 or 16)
     } else {
         A.e1 = RS;
         A.e2 = 1;
+        A.rpair = 0;
     }
     A.vblk = (int64_t)A.Bx * A.sx * A.NYf * A.Bt;
     A.vout = (int64_t)A.box * A.boy * A.bot;
@@ -1067,6 +1092,10 @@ tred_status launch_spp(const ConvArgs& A, int b0, int nb, const int32_t* na, con
     const SppLds Ls = spp_lds<FS, L, NIN, NB, S::NF>(A.box, A.boy);
     const size_t lds = (size_t)Ls.total * sizeof(float2);
     if (lds > 160 * 1024) return tred_fail(TRED_EUNSUPPORTED, "spatial stage needs %zu B of LDS", lds);
+    const int64_t tbytes = (int64_t)NB * A.nch * (A.ppad / kTileT) * A.ft * kTileT * 8;
+    if (tbytes > INT32_MAX)
+        return tred_fail(TRED_EUNSUPPORTED, "spatial stage: %lld B of time spectra per workgroup",
+                         (long long)tbytes);
     allow_lds(k_spp<FS, L, NIN, NB>, lds);
     hipLaunchKernelGGL((k_spp<FS, L, NIN, NB>), dim3((nb + NB - 1) / NB, A.ft / S::NF), dim3(S::NT),
                        lds, st, A, b0, nb, na, T, rhat, tws, U);

@@ -87,7 +87,12 @@ __global__ __launch_bounds__(1024) void k_compact_pix(ScatArgs S, int32_t* __res
     if (tid == 0) *n_pix = carry;
 }
 
-// one workgroup per (pixel slot, 256-tick tile)
+// One workgroup per pixel slot. Its threads walk the waveform in spans of 1024 ticks,
+// four ticks per thread, so the pixel's bin lookups are made once per span and each
+// thread keeps several block-output loads in flight. Per sample the covering bins are
+// summed in (bx, by, bt) order.
+constexpr int kGatherSpan = 1024;
+
 __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __restrict__ pix,
                                                 const int32_t* __restrict__ n_pix,
                                                 const int32_t* __restrict__ bmap,
@@ -100,30 +105,43 @@ __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __res
     const int p = (int)(pix[slot] % npix);
     const int px = p / S.npy, py = p % S.npy;
     bmap += e * (int64_t)S.nb[0] * S.nb[1] * S.nb[2];
-    const int T0 = blockIdx.y * 256;
-    const int T = T0 + threadIdx.x;
     // bins whose output footprint contains this pixel: b*B - h <= p <= b*B + B - 1 + h
     const int bx0 = max(0, (px - S.hx - S.Bx + 1 + S.Bx * 4096) / S.Bx - 4096);
     const int bx1 = min(S.nb[0] - 1, (px + S.hx) / S.Bx);
     const int by0 = max(0, (py - S.hy - S.By + 1 + S.By * 4096) / S.By - 4096);
     const int by1 = min(S.nb[1] - 1, (py + S.hy) / S.By);
-    // bins whose ticks [bt Bt, bt Bt + bot) meet the tile [T0, T0 + 256)
-    const int bt0 = max(0, (T0 - S.bot + 1 + S.Bt * 4096) / S.Bt - 4096);
-    const int bt1 = min(S.nb[2] - 1, (T0 + 255) / S.Bt);
-    float acc = 0.0f;
-    for (int bx = bx0; bx <= bx1; ++bx)
-        for (int by = by0; by <= by1; ++by) {
-            const int qx = px - bx * S.Bx + S.hx, qy = py - by * S.By + S.hy;
-            if (qx < 0 || qx >= S.box || qy < 0 || qy >= S.boy) continue;
-            for (int bt = bt0; bt <= bt1; ++bt) {
-                const int b = bmap[((int64_t)bx * S.nb[1] + by) * S.nb[2] + bt];
-                if (b < 0) continue;
-                const int t = T - bt * S.Bt;
-                if (t >= 0 && t < S.bot)
-                    acc += outb[(int64_t)b * S.vout + ((int64_t)qx * S.boy + qy) * S.bot + t];
+    constexpr int NJ = kGatherSpan / 256;
+    float* wrow = wf + (int64_t)slot * S.lwf;
+    for (int T0 = 0; T0 < S.lwf; T0 += kGatherSpan) {
+        // bins whose ticks [bt Bt, bt Bt + bot) meet [T0, T0 + span)
+        const int bt0 = max(0, (T0 - S.bot + 1 + S.Bt * 4096) / S.Bt - 4096);
+        const int bt1 = min(S.nb[2] - 1, (T0 + kGatherSpan - 1) / S.Bt);
+        float acc[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = 0.0f;
+        for (int bx = bx0; bx <= bx1; ++bx)
+            for (int by = by0; by <= by1; ++by) {
+                const int qx = px - bx * S.Bx + S.hx, qy = py - by * S.By + S.hy;
+                if (qx < 0 || qx >= S.box || qy < 0 || qy >= S.boy) continue;
+                const int32_t* bcol = bmap + ((int64_t)bx * S.nb[1] + by) * S.nb[2];
+                for (int bt = bt0; bt <= bt1; ++bt) {
+                    const int b = bcol[bt];
+                    if (b < 0) continue;
+                    const float* row = outb + (int64_t)b * S.vout + ((int64_t)qx * S.boy + qy) * S.bot;
+                    const int tb = T0 + (int)threadIdx.x - bt * S.Bt;   // tick within the row
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        const int t = tb + 256 * j;
+                        if (t >= 0 && t < S.bot) acc[j] += row[t];
+                    }
+                }
             }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int T = T0 + (int)threadIdx.x + 256 * j;
+            if (T < S.lwf) wrow[T] = acc[j];
         }
-    if (T < S.lwf) wf[(int64_t)slot * S.lwf + T] = acc;
+    }
 }
 
 ScatArgs make_sargs(const tred_conv_plan* P) {
@@ -182,8 +200,8 @@ tred_status scatter(const tred_conv_plan* P, int32_t nev, int32_t kst, const int
     hipLaunchKernelGGL(k_compact_pix, dim3(1), dim3(1024), 0, st, S, pmap, pix, n_pix);
     TRED_TRY(tred_check_launch("tred_scatter_waveforms compact"));
     if (pix_cap > 0)
-        hipLaunchKernelGGL(k_gather, dim3(pix_cap, (S.lwf + 255) / 256), dim3(256), 0, st, S, pix,
-                           n_pix, bmap, out_blocks, wf);
+        hipLaunchKernelGGL(k_gather, dim3(pix_cap), dim3(256), 0, st, S, pix, n_pix, bmap,
+                           out_blocks, wf);
     return tred_check_launch("tred_scatter_waveforms");
 }
 

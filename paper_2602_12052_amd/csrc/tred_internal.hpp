@@ -171,6 +171,21 @@ struct Dft {
 };
 
 // c + a * b as four fused multiply-adds
+// Raw buffer loads: a 128-bit resource (base, size in bytes) held in scalar registers,
+// a 32-bit per-lane byte offset and a wave-uniform byte offset. Offsets at or past
+// the size read zero. Address arithmetic stays 32-bit, and a uniform part of the
+// offset costs no vector instruction.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+__device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
     c.x = fmaf(a.x, b.x, c.x);
     c.x = fmaf(-a.y, b.y, c.x);
