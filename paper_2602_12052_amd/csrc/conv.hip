@@ -181,69 +181,127 @@ __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2*
 
 // ---------------------------------------------------------------------------
 // k_tf: time FFT of the (channel, pixel) rows of a block; one wavefront per row,
-// 8 rows (one tile of the spectral scratch) per workgroup.
+// 8 rows (one half of a T tile) per group. Workgroups are persistent: workgroup w
+// takes groups w, w + G, w + 2G, ... (G = gridDim.x), and requests the next group's
+// rows before the FFT of the current one, so HBM reads overlap the arithmetic.
 // Under mirror-pair packing the row is Q_j[p] + i Q_{j'}[B-1-p] with j' = sub-1-j.
 // ---------------------------------------------------------------------------
+struct TfGroup {
+    int bl, ch, pt, half;
+};
+
+// LDS of k_tf in floats: the 8 waves' FFT scratch or the staging tile (rows of kTile
+// values, no padding), then the twiddles; two workgroups fit in a CU at FT = 1024
 template <int FT>
-__global__ __launch_bounds__(512) void k_tf(ConvArgs A, int b0, const int32_t* __restrict__ n_active,
+__host__ __device__ constexpr int tf_lds_floats() {
+    return 8 * kFftLds<FT> > 2 * FT * kTile ? 8 * kFftLds<FT> : 2 * FT * kTile;
+}
+
+// column of pixel c in staging row f: an XOR swizzle by f / 4 spreads a wave's writes
+// of one column over all banks (rows are 64 bytes, four rows span the 64 banks)
+__device__ __forceinline__ int tf_col(int f, int c) { return c ^ ((f >> 2) & (kTile - 1)); }
+
+// Group q -> (bin, channel, tile, half). T tiles hold kTileT = 2 kTile pixels per
+// frequency (one 128-byte line) and a group transforms the 8 rows of one half.
+// Workgroup ids are dealt to the XCDs round-robin; with G a multiple of 2 kXcd the
+// two halves of a tile go to groups kXcd apart, i.e. to one XCD (one L2).
+__device__ __forceinline__ TfGroup tf_group(const ConvArgs& A, int q) {
+    const int nbx = A.ppad / kTile;
+    TfGroup g;
+    const int x = q % nbx;
+    g.ch = (q / nbx) % A.nch;
+    g.bl = q / (nbx * A.nch);
+    const int ntile = A.ppad / kTileT;
+    if (kTileT == kTile) {
+        g.pt = x;
+        g.half = 0;
+    } else if (ntile % (int)kXcd == 0) {
+        const int gg = x / (2 * kXcd), r = x % (2 * kXcd);
+        g.pt = gg * kXcd + r % kXcd;
+        g.half = r / kXcd;
+    } else {
+        g.pt = x >> 1;
+        g.half = x & 1;
+    }
+    return g;
+}
+
+// HALF: the block holds at most FT / 2 ticks, so only the first half of each row is
+// loaded (the rest is zero padding).
+template <int FT, bool HALF>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 ? 4 : 1))) void k_tf(ConvArgs A, int b0, int nbp, const int32_t* __restrict__ n_active,
                                             const float* __restrict__ blocks,
                                             const float2* __restrict__ tw, float2* __restrict__ T) {
     extern __shared__ float lds[];
-    constexpr int M = FT / kWave;
-    const int bl = blockIdx.z, b = b0 + bl;
-    if (b >= min(*n_active, A.cap)) return;
-    const int ch = blockIdx.y;
+    constexpr int M = FT / kWave, MB = HALF ? M / 2 : M;
+    const int nbin = min(nbp, min(*n_active, A.cap) - b0);
+    if (nbin <= 0) return;
+    const int total = (A.ppad / kTile) * A.nch * nbin;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // T tiles hold kTileT = 2 kTile pixels per frequency (one 128-byte line); a
-    // workgroup transforms the 8 rows of one half of a tile. Workgroup ids are dealt
-    // to the XCDs round-robin, so the two halves of a tile go to workgroups kXcd ids
-    // apart (same XCD, same L2) when there are whole groups of kXcd tiles.
-    const int ntile = A.ppad / kTileT;
-    int pt, half;
-    if (kTileT == kTile) {
-        pt = blockIdx.x;
-        half = 0;
-    } else if (ntile % (int)kXcd == 0) {
-        const int g = blockIdx.x / (2 * kXcd), r = blockIdx.x % (2 * kXcd);
-        pt = g * kXcd + r % kXcd;
-        half = r / kXcd;
-    } else {
-        pt = blockIdx.x >> 1;
-        half = blockIdx.x & 1;
-    }
-    const int p = pt * kTileT + half * kTile + wv;
-    const int jx = ch / A.sy, jy = ch % A.sy;
-    const int jb = A.S - 1 - ch;
-    const bool pair = A.mpcp && jb != ch;
     const int mb = A.Bt / kWave;
-    float2 v[M];
+    // rows of group q into (ra, rb): Q_j and, under mirror-pair packing, Q_j'; 32-bit
+    // offsets within the bin (the host keeps a bin below 2^31 bytes)
+    float ra[MB], rb[MB];
+    auto load = [&](int q) {
+        const TfGroup g = tf_group(A, q);
+        const int p = g.pt * kTileT + g.half * kTile + wv;
+        const int jx = g.ch / A.sy, jy = g.ch % A.sy;
+        const int jb = A.S - 1 - g.ch;
+        const bool pair = A.mpcp && jb != g.ch;
+        const bool live = p < A.Bx * A.By;
+        const auto br = buf_rsrc(blocks + (int64_t)(b0 + g.bl) * A.vblk, (uint32_t)(A.vblk * 4));
+        const int px = live ? p / A.By : 0, py = live ? p % A.By : 0;
+        const uint32_t o0 = 4u * (uint32_t)(((px * A.sx + jx) * A.NYf + (py * A.sy + jy)) * A.Bt + lane);
+        const int jbx = jb / A.sy, jby = jb % A.sy;
+        const uint32_t o1 = 4u * (uint32_t)((((A.Bx - 1 - px) * A.sx + jbx) * A.NYf +
+                                             ((A.By - 1 - py) * A.sy + jby)) * A.Bt + lane);
 #pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = make_float2(0.f, 0.f);
-    if (p < A.Bx * A.By) {
-        const float* blk = blocks + (int64_t)b * A.vblk;
-        const int px = p / A.By, py = p % A.By;
-        const float* r0 = blk + ((int64_t)(px * A.sx + jx) * A.NYf + (py * A.sy + jy)) * A.Bt;
-#pragma unroll
-        for (int m = 0; m < M; ++m)
-            if (m < mb) v[m].x = r0[lane + kWave * m];
-        if (pair) {
-            const int jbx = jb / A.sy, jby = jb % A.sy;
-            const float* r1 = blk + ((int64_t)((A.Bx - 1 - px) * A.sx + jbx) * A.NYf +
-                                     ((A.By - 1 - py) * A.sy + jby)) * A.Bt;
-#pragma unroll
-            for (int m = 0; m < M; ++m)
-                if (m < mb) v[m].y = r1[lane + kWave * m];
+        for (int m = 0; m < MB; ++m) {
+            ra[m] = (live && m < mb) ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                           br, o0, (uint32_t)(m * kWave * 4), 0))
+                                     : 0.0f;
+            rb[m] = (live && pair && m < mb) ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                   br, o1, (uint32_t)(m * kWave * 4), 0))
+                                             : 0.0f;
         }
-    }
-    wave_fft<FT, true>(v, lds + wv * kFftLds<FT>, tw, lane);
-    __syncthreads();   // the staging tile overlaps the other waves' FFT scratch
-    float2* stage = (float2*)lds;   // [f][kTileP]: odd row stride keeps the wave's writes conflict free
-#pragma unroll
-    for (int m = 0; m < M; ++m) stage[(lane + kWave * m) * kTileP + wv] = v[m];
+    };
+    // twiddle table in LDS after the FFT scratch / staging region
+    float2* twl = (float2*)(lds + tf_lds_floats<FT>());
+    for (int i = threadIdx.x; i < FT; i += blockDim.x) twl[i] = tw[i];
+    int q = blockIdx.x;
+    if (q < total) load(q);
     __syncthreads();
-    float2* d2 = T + (((int64_t)bl * A.nch + ch) * (A.ppad / kTileT) + pt) * FT * kTileT + half * kTile;
-    for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x)
-        d2[(i / kTile) * kTileT + (i % kTile)] = stage[(i / kTile) * kTileP + (i % kTile)];
+    for (; q < total; q += gridDim.x) {
+        const TfGroup g = tf_group(A, q);
+        float2 v[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = m < MB ? make_float2(ra[m], rb[m]) : make_float2(0.f, 0.f);
+        if (q + (int)gridDim.x < total) load(q + gridDim.x);   // in flight during the FFT
+        wave_fft<FT, true, true>(v, lds + wv * kFftLds<FT>, twl, lane);
+        __syncthreads();   // the staging tile overlaps the other waves' FFT scratch
+        float2* stage = (float2*)lds;   // [f][kTile], columns swizzled
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int f = lane + kWave * m;
+            stage[f * kTile + tf_col(f, wv)] = v[m];
+        }
+        __syncthreads();
+        const auto tr = buf_rsrc(T + (((int64_t)g.bl * A.nch + g.ch) * (A.ppad / kTileT) + g.pt) * FT * kTileT,
+                                 (uint32_t)(FT * kTileT * sizeof(float2)));
+        // thread t stores pixel c = t % kTile of rows f = t / kTile + (512 / kTile) k; the
+        // swizzle term of those rows does not depend on k (512 / kTile / 4 is a multiple
+        // of kTile), so the LDS and T offsets are a per-thread base plus constants
+        static_assert(FT * kTile % 512 == 0 && (512 / kTile / 4) % kTile == 0, "store loop");
+        {
+            const int f0 = (int)threadIdx.x / kTile, c = (int)threadIdx.x % kTile;
+            const float2* src = stage + f0 * kTile + tf_col(f0, c);
+            const uint32_t voff = (uint32_t)((f0 * kTileT + g.half * kTile + c) * 8);
+#pragma unroll
+            for (int k = 0; k < FT * kTile / 512; ++k)
+                buf_st_f2(src[512 * k], tr, voff, (uint32_t)(k * (512 / kTile) * kTileT * 8));
+        }
+        __syncthreads();   // the next FFT's scratch overlaps the staging tile
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -910,17 +968,40 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     float carry[MH];
 #pragma unroll
     for (int m = 0; m < MH; ++m) carry[m] = 0.0f;
+    // twiddle table in LDS after the FFT scratch / staging region
+    float2* twl = (float2*)(lds + tf_lds_floats<FT>());
+    for (int i = threadIdx.x; i < FT; i += blockDim.x) twl[i] = tw[i];
     for (int c = 0; c < A.nc; ++c) {
         const float2* s2 = U + ((((int64_t)bl * A.nc + c) * qtiles + qt) * FT) * kTile;
-        float2* stage = (float2*)lds;   // [f][kTileP]
-        for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x)
-            stage[(i / kTile) * kTileP + (i % kTile)] = s2[i];
+        float2* stage = (float2*)lds;   // [f][kTile], columns swizzled (tf_col)
+        // the tile is requested in groups of four 16-byte loads (two pixels of one
+        // frequency each) that are in flight together before their LDS writes
+        constexpr int NLD = FT * kTile / 2 / 512, G = NLD < 4 ? NLD : 4;
+        static_assert(FT * kTile % 1024 == 0 && kTile % 2 == 0 && NLD % G == 0, "tile loads");
+        const auto ur = buf_rsrc(s2, (uint32_t)(FT * kTile * sizeof(float2)));
+#pragma unroll
+        for (int k0 = 0; k0 < NLD; k0 += G) {
+            float4 ld[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+                ld[k] = buf_f4(ur, threadIdx.x * 16u, (uint32_t)((k0 + k) * 512 * 16));
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int i = 2 * ((int)threadIdx.x + 512 * (k0 + k));
+                const int f = i / kTile, c = i % kTile;
+                stage[f * kTile + tf_col(f, c)] = make_float2(ld[k].x, ld[k].y);
+                stage[f * kTile + tf_col(f, c + 1)] = make_float2(ld[k].z, ld[k].w);
+            }
+        }
         __syncthreads();
         float2 v[M];
 #pragma unroll
-        for (int m = 0; m < M; ++m) v[m] = cconj(stage[(lane + kWave * m) * kTileP + wv]);
+        for (int m = 0; m < M; ++m) {
+            const int f = lane + kWave * m;
+            v[m] = cconj(stage[f * kTile + tf_col(f, wv)]);
+        }
         __syncthreads();
-        wave_fft<FT, TRED_TI_WAVESYNC>(v, lds + wv * kFftLds<FT>, tw, lane);
+        wave_fft<FT, TRED_TI_WAVESYNC, true>(v, lds + wv * kFftLds<FT>, twl, lane);
         __syncthreads();   // the next piece's tile overlaps the other waves' FFT scratch
         if (valid) {
             if constexpr (CARRY) {
@@ -1042,17 +1123,30 @@ void allow_lds(K kernel, size_t bytes) {
 template <int FT>
 tred_status launch_time_fwd(const ConvArgs& A, int b0, int nb, const int32_t* na, const float* blocks,
                             const float2* tw, float2* T, hipStream_t st) {
-    const size_t lds = std::max((size_t)8 * kFftLds<FT> * sizeof(float), (size_t)FT * kTileP * sizeof(float2));
-    allow_lds(k_tf<FT>, lds);
-    hipLaunchKernelGGL((k_tf<FT>), dim3(A.ppad / kTile, A.nch, nb), dim3(512), lds, st, A, b0, na,
-                       blocks, tw, T);
+    const size_t lds = (size_t)tf_lds_floats<FT>() * sizeof(float) + (size_t)FT * sizeof(float2);
+    if (A.vblk * 4 > INT32_MAX)
+        return tred_fail(TRED_EUNSUPPORTED, "time forward: %lld B per bin", (long long)(A.vblk * 4));
+    // persistent workgroups: a multiple of 2 kXcd (tile halves on one XCD), a few per CU
+    const int64_t groups = (int64_t)(A.ppad / kTile) * A.nch * nb;
+    const int64_t cap = 4096;
+    const int64_t G = std::min(cap, (groups + 2 * kXcd - 1) / (2 * kXcd) * (2 * kXcd));
+    if (G <= 0) return TRED_OK;
+    if (2 * A.Bt <= FT) {
+        allow_lds(k_tf<FT, true>, lds);
+        hipLaunchKernelGGL((k_tf<FT, true>), dim3((unsigned)G), dim3(512), lds, st, A, b0, nb, na,
+                           blocks, tw, T);
+    } else {
+        allow_lds(k_tf<FT, false>, lds);
+        hipLaunchKernelGGL((k_tf<FT, false>), dim3((unsigned)G), dim3(512), lds, st, A, b0, nb, na,
+                           blocks, tw, T);
+    }
     return tred_check_launch("tred_block_conv time forward");
 }
 
 template <int FT>
 tred_status launch_time_inv(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* U,
                             const float2* tw, float* out, hipStream_t st) {
-    const size_t lds = std::max((size_t)8 * kFftLds<FT> * sizeof(float), (size_t)FT * kTileP * sizeof(float2));
+    const size_t lds = (size_t)tf_lds_floats<FT>() * sizeof(float) + (size_t)FT * sizeof(float2);
     if (A.ct == A.Bt && 2 * A.ct == FT) {
         allow_lds(k_ti<FT, true>, lds);
         hipLaunchKernelGGL((k_ti<FT, true>), dim3(A.qpad / kTile, nb), dim3(512), lds, st, A, b0, na,

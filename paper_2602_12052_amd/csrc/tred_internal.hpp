@@ -185,6 +185,11 @@ __device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t voff
 __device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
+__device__ __forceinline__ void buf_st_f2(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff) {
+    using u2 = __attribute__((ext_vector_type(2))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+}
 
 __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
     c.x = fmaf(a.x, b.x, c.x);
@@ -237,7 +242,7 @@ __device__ __forceinline__ void pfa_gather(const float2* x, const float2* w, flo
 // Per-wavefront Stockham FFT of length N = 64 * M (M in {4, 8, 16, 32, 64}).
 // On entry lane l holds x[l + 64 m] in v[m]; on exit X[l + 64 m] (forward DFT,
 // natural order). `buf` is the wave's private LDS scratch of kFftLds<N> floats;
-// `tw` is a table of exp(-2 pi i k / N), k < N (global or LDS).
+// `tw` is a table of exp(-2 pi i k / N), k < N, in device memory or (TWL) in LDS.
 // Radix sequence: N = R1 * R2 * ... with every radix <= 16. The scratch is private
 // to the wave (no workgroup barrier inside).
 // Stage (radix R, Ns = product of earlier radices): butterfly j reads
@@ -273,7 +278,11 @@ __device__ __forceinline__ void fft_sync() {
     else __syncthreads();
 }
 
-template <int N, int R, int NS, bool FIRST, bool WS>
+// TWL: the twiddle table is in LDS and read where it is used (LDS loads leave the
+// vector-memory counter alone, so loads in flight from before the FFT are not waited
+// for); otherwise it is in device memory, read through a buffer resource (32-bit
+// offsets), and a stage requests all its twiddles before its first butterfly.
+template <int N, int R, int NS, bool FIRST, bool WS, bool TWL>
 __device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* tw, int lane) {
     constexpr int M = N / kWave;
     constexpr int NB = N / R;            // butterflies in this stage
@@ -281,6 +290,18 @@ __device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* t
     static_assert(PER >= 1 && PER * R == M, "radix does not match the lane data");
     float* re = buf;
     float* im = buf + (N + N / 16);
+    constexpr int NW = (NS > 1 && !TWL) ? R : 1;
+    float2 w[PER][NW];
+    if constexpr (NS > 1 && !TWL) {
+        const auto twr = buf_rsrc(tw, (uint32_t)(N * sizeof(float2)));
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int jm = (lane + kWave * i) % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r)
+                w[i][r] = buf_f2(twr, (uint32_t)(r * jm * (N / (NS * R))) * 8u, 0u);
+        }
+    }
     float2 u[M];
     if constexpr (FIRST) {
         // inputs in[j + r N/R] with j = lane + 64 i: register i + r * PER
@@ -305,9 +326,10 @@ __device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* t
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = FIRST ? u[i + r * PER] : u[i * R + r];
         if constexpr (NS > 1) {
-            int jm = j % NS;
+            const int jm = j % NS;
 #pragma unroll
-            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * jm * (N / (NS * R))]);
+            for (int r = 1; r < R; ++r)
+                x[r] = cmul(x[r], TWL ? tw[r * jm * (N / (NS * R))] : w[i][NW > 1 ? r : 0]);
         }
         Dft<R>::run(x);
         int base = (j / NS) * NS * R + (j % NS);
@@ -321,14 +343,14 @@ __device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* t
     fft_sync<WS>();
 }
 
-template <int N, bool WS>
+template <int N, bool WS, bool TWL = false>
 __device__ __forceinline__ void wave_fft(float2* v, float* buf, const float2* tw, int lane) {
     using P = FftPlan<N>;
     constexpr int R0 = P::R[0], R1 = P::R[1], R2 = P::R[2], R3 = P::R[3];
-    fft_stage<N, R0, 1, true, WS>(v, buf, tw, lane);
-    fft_stage<N, R1, R0, false, WS>(v, buf, tw, lane);
-    if constexpr (P::S >= 3) fft_stage<N, R2, R0 * R1, false, WS>(v, buf, tw, lane);
-    if constexpr (P::S >= 4) fft_stage<N, R3, R0 * R1 * R2, false, WS>(v, buf, tw, lane);
+    fft_stage<N, R0, 1, true, WS, TWL>(v, buf, tw, lane);
+    fft_stage<N, R1, R0, false, WS, TWL>(v, buf, tw, lane);
+    if constexpr (P::S >= 3) fft_stage<N, R2, R0 * R1, false, WS, TWL>(v, buf, tw, lane);
+    if constexpr (P::S >= 4) fft_stage<N, R3, R0 * R1 * R2, false, WS, TWL>(v, buf, tw, lane);
     constexpr int M = N / kWave;
     const float* re = buf;
     const float* im = buf + (N + N / 16);
