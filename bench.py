@@ -189,6 +189,92 @@ def bench_direct(args, split):
         "peak_tflops": BF16_MFMA_PEAK_TFLOPS, "forms": forms}), flush=True)
 
 
+def bench_adjoint(args):
+    """Differentiation workload: 2e4 depositions in a 128x128-pixel region with the
+    module-scale response. A step is the forward path (five calls), the gradient of
+    the L2 loss against target waveforms made with diff_T +10 %, diff_L -10 % and
+    lifetime +20 % (aligned on the simulated pixel list), and the four transposed
+    calls back to dL/d(depositions) and dL/d(diff_T, diff_L, lifetime). One JSON line."""
+    import copy
+    import torch
+    import workloads as W
+    from paper_2602_12052_amd import tred
+    stream = torch.cuda.current_stream().cuda_stream
+    cfg = W.cfg_diff(args.seed)
+    seg = W.gen_segments(cfg)
+    resp = W.synthetic_response(cfg.kpix, cfg.grid.sub, cfg.kticks)
+    sd = torch.from_numpy(seg).cuda()
+    dresp = torch.from_numpy(resp).cuda()
+    g, ph, blk = cfg.grid, cfg.physics, cfg.blocking
+    pt = copy.copy(ph)
+    pt.diff_T, pt.diff_L, pt.lifetime = ph.diff_T * 1.1, ph.diff_L * 0.9, ph.lifetime * 1.2
+    caps = [max(a, b) for a, b in zip(tred.size_event(g, ph, blk, cfg.kpix, sd),
+                                      tred.size_event(g, pt, blk, cfg.kpix, sd))]
+    pl = tred.Pipeline(g, ph, blk, cfg.kpix, cfg.kticks, dresp, seg.shape[0], caps[0], caps[1],
+                       caps[2], cfg.fft, True, caps[1])
+    tgt = tred.Pipeline(g, pt, blk, cfg.kpix, cfg.kticks, dresp, seg.shape[0], caps[0], caps[1],
+                        caps[2], cfg.fft, True, caps[1])
+    tgt.run(sd)
+    torch.cuda.synchronize()
+    nt = int(tgt.n_pix.item())
+    tpix, twf = tgt.pix[:nt].clone(), tgt.wf[:nt].clone()
+    del tgt
+    torch.cuda.empty_cache()
+    d_wf = torch.zeros_like(pl.wf)
+    ev = HipEvents(3)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def step():
+        ev.record(0, stream)
+        pl.run(sd)
+        ev.record(1, stream)
+        n = pl.n_pix                          # device scalar; rows past it stay zero
+        rows = torch.arange(pl.pix.shape[0], device="cuda")
+        live = rows < n
+        j = torch.searchsorted(tpix, pl.pix).clamp_(max=max(nt - 1, 0))
+        hit = live & (tpix[j] == pl.pix) if nt > 0 else torch.zeros_like(live)
+        target = torch.where(hit[:, None], twf[j], torch.zeros((), device="cuda"))
+        torch.sub(pl.wf, target, out=d_wf)
+        d_wf.mul_(live[:, None])
+        loss.copy_(0.5 * (d_wf.double() ** 2).sum())
+        pl.backward(sd, d_wf)
+        ev.record(2, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ts, tf, tb = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        ts.append(1e3 * (time.perf_counter() - s0))
+        tf.append(ev.ms(0, 1))
+        tb.append(ev.ms(1, 2))
+    wall = time.perf_counter() - t0
+    ms = 1e3 * wall / args.steps
+    d_seg = pl.d_seg.double()
+    print(json.dumps({
+        "metric": "depositions/s, forward path + gradient (L2 loss on the waveforms)",
+        "value": seg.shape[0] / (ms * 1e-3), "unit": "depositions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "differentiation: 2e4 depositions (tracks + blobs) in 128x128 pixels "
+                               "x 6250 ticks, response 21x21 px x 2048 ticks, bins 16x16 px x 512 "
+                               "ticks; target waveforms with diff_T +10 %, diff_L -10 %, lifetime "
+                               "+20 %", "n_dep": int(seg.shape[0]),
+                   "active_bins": int(pl.n_active.item()), "pixels": int(pl.n_pix.item())},
+        "step_ms": {"p50": float(np.percentile(ts, 50)), "p99": float(np.percentile(ts, 99))},
+        "stage_ms": {"forward": float(np.median(tf)), "loss+gradient": float(np.median(tb))},
+        "loss": float(loss.item()),
+        "grad": {"d_diff_T": float(pl.d_phys[0]), "d_diff_L": float(pl.d_phys[1]),
+                 "d_lifetime": float(pl.d_phys[2]),
+                 "rms_d_endpoints": float(torch.sqrt((d_seg[:, :6] ** 2).mean())),
+                 "rms_d_charge": float(torch.sqrt((d_seg[:, 6] ** 2).mean()))},
+    }), flush=True)
+
+
 def bench_batched(args):
     """Batched events: n_ev module-scale events of log-uniform size in [1e3, 2e5]. The
     autotuner picks the bin shape and FFT sizes on the median event; events are grouped
@@ -304,9 +390,11 @@ def main():
     ap.add_argument("--events", type=int, default=64, help="events of the batched form")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="device memory of a chunk")
     ap.add_argument("--pass-gb", type=float, default=60.0, help="convolution scratch per pass")
-    ap.add_argument("--form", default="fft", choices=["fft", "direct-split", "direct-bf16", "batched"],
+    ap.add_argument("--form", default="fft",
+                    choices=["fft", "direct-split", "direct-bf16", "batched", "adjoint"],
                     help="fft: the benchmark line; direct-*: block-direct convolution on BF16 "
-                         "matrix cores beside the FFT path (separate JSON line)")
+                         "matrix cores beside the FFT path; batched: 64 events; adjoint: "
+                         "forward + gradient on the differentiation workload (separate lines)")
     ap.add_argument("--direct-bins", type=int, default=8,
                     help="module-event bins timed by the direct forms")
     args = ap.parse_args()
@@ -332,6 +420,9 @@ def main():
 
     if args.form == "batched":
         bench_batched(args)
+        return
+    if args.form == "adjoint":
+        bench_adjoint(args)
         return
     if args.form != "fft":
         bench_direct(args, args.form == "direct-split")

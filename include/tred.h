@@ -276,6 +276,49 @@ tred_status tred_block_conv_direct(const tred_direct_plan* plan, const int32_t* 
                                    void* stream);
 void tred_direct_plan_destroy(tred_direct_plan* plan);
 
+/* ------------------------------------------------------------------------- */
+/* Gradients (Sec. V-A: the simulation is differentiable, e.g. to fit the electron
+ * lifetime). Each call is the transpose of the forward call of the same name for
+ * the same inputs, plan, keys, pixel list and capacities: given dL/d(its outputs)
+ * it returns dL/d(its inputs). Chained backwards they give dL/d(depositions) and
+ * dL/d(transport parameters) for a loss L on the waveforms; the effective charge is
+ * recomputed, not stored.
+ *
+ * tred_scatter_waveforms_adjoint: d_wf [pix_cap][nticks + kticks - 1] in,
+ *   d_out_blocks [cap][..] out (every sample of the active bins written: the
+ *   gradient of its pixel's waveform at its tick, zero for pixels outside the region,
+ *   pixels without a slot below pix_cap and ticks past the waveform end). */
+tred_status tred_scatter_waveforms_adjoint(const tred_conv_plan* plan, const int32_t* keys,
+                                           const int32_t* n_active, int32_t cap,
+                                           const int32_t* pix, const int32_t* n_pix,
+                                           int32_t pix_cap, const float* d_wf,
+                                           float* d_out_blocks, void* stream);
+/* tred_block_conv_adjoint: d_out_blocks in, d_blocks [cap][..] out (every cell of the
+ *   active bins written). The correlation with the response by the same transforms:
+ *   conj(FFT(R_j)) in the channel fan-out. Supported for spatial sizes 8, 16, 24, 40
+ *   and 48 (TRED_EUNSUPPORTED otherwise); uses the plan's scratch like tred_block_conv. */
+tred_status tred_block_conv_adjoint(const tred_conv_plan* plan, const int32_t* n_active,
+                                    int32_t cap, const float* d_out_blocks, float* d_blocks,
+                                    void* stream);
+/* tred_block_bin_adjoint: d_blocks in, d_val [val_cap] out (each patch cell gets the
+ *   gradient of its bin cell; zero for cells of bins beyond cap and for patches that
+ *   end past val_cap). work: tred_block_bin_workspace() bytes (overwritten). */
+tred_status tred_block_bin_adjoint(const tred_grid* grid, const tred_blocking* blocking,
+                                   int64_t n_dep, const int32_t* fp, const int64_t* off,
+                                   int64_t val_cap, const int32_t* keys, const int32_t* n_active,
+                                   const float* d_blocks, int32_t cap, float* d_val, void* work,
+                                   void* stream);
+/* tred_effq_adjoint: d_val in; d_seg [n_dep][7] out: dL/d(x0, y0, z0, x1, y1, z1, Q) of
+ *   every deposition (zero for depositions that miss the region or whose patch ends
+ *   past val_cap); d_phys (may be NULL) [3] binary64, ACCUMULATED: dL/d(diff_T, diff_L,
+ *   lifetime). The quadrature windows and the point/line decision are held fixed
+ *   (they are piecewise constant in the inputs); widths at their floor sigma_min do
+ *   not depend on t_mid or the diffusion constants. The node sums are binary64. */
+tred_status tred_effq_adjoint(const tred_grid* grid, const tred_physics* phys, int64_t n_dep,
+                              const float* seg, const int32_t* fp, const int64_t* off,
+                              const float* d_val, int64_t val_cap, float* d_seg, double* d_phys,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

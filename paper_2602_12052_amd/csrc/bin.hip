@@ -151,6 +151,50 @@ __global__ __launch_bounds__(256) void k_accum(BinGeom G, int64_t n, const int32
     }
 }
 
+// Transpose of the binning: the slot of every active bin from the keys, then every
+// patch cell takes the gradient of its bin's cell (zero where the bin is not held).
+__global__ __launch_bounds__(256) void k_slots(BinGeom G, const int32_t* __restrict__ keys,
+                                               const int32_t* __restrict__ n_active, int32_t cap,
+                                               int32_t* __restrict__ slot) {
+    const int na = min(*n_active, cap);
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < na; s += gridDim.x * blockDim.x) {
+        const int32_t* k = keys + (int64_t)G.kst * s;
+        const int e = G.kst == 4 ? k[0] : 0;
+        const int32_t* b = k + (G.kst == 4 ? 1 : 0);
+        slot[(int64_t)e * G.nbins + ((int64_t)b[0] * G.nb[1] + b[1]) * G.nb[2] + b[2]] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_accum_adj(BinGeom G, int64_t n, const int32_t* __restrict__ fp,
+                                                   const int64_t* __restrict__ off, int64_t val_cap,
+                                                   const int64_t* __restrict__ ev_off,
+                                                   const int32_t* __restrict__ slot_all,
+                                                   const float* __restrict__ dblocks,
+                                                   float* __restrict__ dval) {
+    for (int64_t d = blockIdx.x; d < n; d += gridDim.x) {
+        const int32_t* f = fp + 6 * d;
+        if (f[3] < f[0] || f[4] < f[1] || f[5] < f[2]) continue;
+        const int32_t* slot = slot_all + (int64_t)event_of(d, ev_off, G.nev) * G.nbins;
+        const int ny = f[4] - f[1] + 1, nt = f[5] - f[2] + 1;
+        const int64_t o0 = off[d], o1 = min(off[d + 1], val_cap);
+        const bool kept = off[d + 1] <= val_cap;
+        for (int64_t k = threadIdx.x; k < o1 - o0; k += blockDim.x) {
+            const int it = (int)(k % nt);
+            const int64_t r = k / nt;
+            const int iy = (int)(r % ny), ix = (int)(r / ny);
+            const int gx = f[0] + ix, gy = f[1] + iy, gt = f[2] + it;
+            const int bx = gx / G.bf[0], by = gy / G.bf[1], bt = gt / G.bf[2];
+            const int s = slot[((int64_t)bx * G.nb[1] + by) * G.nb[2] + bt];
+            float g = 0.0f;
+            if (kept && s >= 0)
+                g = dblocks[(int64_t)s * G.vblk +
+                            ((int64_t)(gx - bx * G.bf[0]) * G.bf[1] + (gy - by * G.bf[1])) * G.bf[2] +
+                            (gt - bt * G.bf[2])];
+            dval[o0 + k] = g;
+        }
+    }
+}
+
 BinGeom geom(const tred_grid* g, const tred_blocking* b, int nev, int kst) {
     BinGeom G;
     G.bf[0] = b->blk_pix[0] * g->sub[0];
@@ -224,6 +268,35 @@ extern "C" tred_status tred_block_bin(const tred_grid* grid, const tred_blocking
                                       float* blocks, int32_t cap, void* work, void* stream) {
     return block_bin(grid, blocking, 1, nullptr, n_dep, fp, off, val, val_cap, keys, n_active,
                      blocks, cap, work, stream);
+}
+
+extern "C" tred_status tred_block_bin_adjoint(const tred_grid* grid, const tred_blocking* blocking,
+                                              int64_t n_dep, const int32_t* fp, const int64_t* off,
+                                              int64_t val_cap, const int32_t* keys,
+                                              const int32_t* n_active, const float* d_blocks,
+                                              int32_t cap, float* d_val, void* work, void* stream) {
+    TRED_TRY(validate_grid(grid));
+    TRED_TRY(validate_blocking(blocking));
+    TRED_REQUIRE(n_dep >= 0 && cap >= 0 && val_cap >= 0, "sizes must be >= 0");
+    TRED_REQUIRE(n_active && work, "n_active/work is NULL");
+    TRED_REQUIRE(cap == 0 || (keys && d_blocks), "keys/d_blocks is NULL");
+    TRED_REQUIRE(n_dep == 0 || (fp && off), "fp/off is NULL");
+    TRED_REQUIRE(val_cap == 0 || d_val, "d_val is NULL");
+    TRED_REQUIRE(tred_block_count(grid, blocking) > 0, "too many bins");
+    const BinGeom G = geom(grid, blocking, 1, 3);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t* slot = (int32_t*)work;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((G.nbins + 255) / 256, 4096)),
+                       dim3(256), 0, st, slot, G.nbins, -1);
+    if (cap > 0)
+        hipLaunchKernelGGL(k_slots, dim3((unsigned)std::min(((int64_t)cap + 255) / 256, (int64_t)4096)),
+                           dim3(256), 0, st, G, keys, n_active, cap, slot);
+    if (n_dep > 0 && val_cap > 0) {
+        const unsigned nb = (unsigned)std::min<int64_t>(n_dep, 1 << 20);
+        hipLaunchKernelGGL(k_accum_adj, dim3(nb), dim3(256), 0, st, G, n_dep, fp, off, val_cap,
+                           (const int64_t*)nullptr, slot, d_blocks, d_val);
+    }
+    return tred_check_launch("tred_block_bin_adjoint");
 }
 
 extern "C" int64_t tred_block_bin_events_workspace(const tred_grid* grid,

@@ -30,6 +30,10 @@
 #ifndef TRED_XCD_REMAP
 #define TRED_XCD_REMAP 1
 #endif
+// persistent workgroups of the forward time FFTs (at most)
+#ifndef TRED_TF_GRID
+#define TRED_TF_GRID 4096
+#endif
 // wave-level ordering inside the inverse time FFTs (1) or workgroup barriers (0)
 #ifndef TRED_TI_WAVESYNC
 #define TRED_TI_WAVESYNC 1
@@ -1034,6 +1038,365 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     }
 }
 
+// ===========================================================================
+// Transpose of the convolution (gradients, Sec. V-A). For one bin the forward map is
+//   out = OLA_c Re F_t^H Unpack Crop F_xy^H ( sum_ch Rhat[ch][c] F_xy F_t Pack(Q_ch) )
+// with F the unnormalised DFT (the 1/N factors live in Rhat). Its transpose (real
+// inner products) runs the same stages backwards:
+//   dQ = Pack^T Crop_Bt F_t^H ( Crop_B F_xy^H sum_c conj(Rhat[ch][c]) F_xy Unpack^H F_t Seg_c(dout) )
+// k_ti_adj: F_t of each output-gradient piece segment -> dU (layout of U);
+// k_spp_adj: per frequency, Unpack^H and F_xy of the pieces, the conjugate multiply-
+//            accumulate into every channel, F_xy^H pruned to the bin -> dT (layout of T);
+// k_tf_adj:  F_t^H of every (channel, pixel) row cropped to Bt, Pack^T -> d blocks.
+// ===========================================================================
+
+// k_ti_adj: per (output-pixel tile, piece, bin); wave wv handles pixel qt * 8 + wv.
+template <int FT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 ? 4 : 1))) void k_ti_adj(
+    ConvArgs A, int b0, const int32_t* __restrict__ n_active, const float* __restrict__ dout,
+    const float2* __restrict__ tw, float2* __restrict__ dU) {
+    extern __shared__ float lds[];
+    constexpr int M = FT / kWave;
+    const int qt = blockIdx.x, c = blockIdx.y, bl = blockIdx.z, b = b0 + bl;
+    if (b >= min(*n_active, A.cap)) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = qt * kTile + wv;
+    const bool valid = q < A.box * A.boy;
+    float2* twl = (float2*)(lds + tf_lds_floats<FT>());
+    for (int i = threadIdx.x; i < FT; i += blockDim.x) twl[i] = tw[i];
+    const float* row = dout + (int64_t)b * A.vout + (int64_t)(valid ? q : 0) * A.bot;
+    float2 v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int a = c * A.ct + lane + kWave * m;   // output tick of piece sample t
+        v[m] = make_float2(valid && a < A.bot ? row[a] : 0.0f, 0.0f);
+    }
+    __syncthreads();
+    wave_fft<FT, true, true>(v, lds + wv * kFftLds<FT>, twl, lane);
+    __syncthreads();
+    float2* stage = (float2*)lds;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int f = lane + kWave * m;
+        stage[f * kTile + tf_col(f, wv)] = v[m];
+    }
+    __syncthreads();
+    const int qtiles = A.qpad / kTile;
+    float2* d2 = dU + ((((int64_t)bl * A.nc + c) * qtiles + qt) * FT) * kTile;
+    for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x) {
+        const int f = i / kTile, cc = i % kTile;
+        d2[i] = stage[f * kTile + tf_col(f, cc)];
+    }
+}
+
+// k_tf_adj: per (half T tile, channel, bin); wave wv handles pixel p of the half tile.
+template <int FT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 ? 4 : 1))) void k_tf_adj(
+    ConvArgs A, int b0, const int32_t* __restrict__ n_active, const float2* __restrict__ dT,
+    const float2* __restrict__ tw, float* __restrict__ dblocks) {
+    extern __shared__ float lds[];
+    constexpr int M = FT / kWave;
+    const int bl = blockIdx.z, b = b0 + bl;
+    if (b >= min(*n_active, A.cap)) return;
+    const int ch = blockIdx.y;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int pt = blockIdx.x / (kTileT / kTile), half = blockIdx.x % (kTileT / kTile);
+    float2* twl = (float2*)(lds + tf_lds_floats<FT>());
+    for (int i = threadIdx.x; i < FT; i += blockDim.x) twl[i] = tw[i];
+    // stage the half tile [f][kTile] of T-layout gradients
+    const float2* s2 = dT + (((int64_t)bl * A.nch + ch) * (A.ppad / kTileT) + pt) * FT * kTileT +
+                       half * kTile;
+    float2* stage = (float2*)lds;
+    for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x) {
+        const int f = i / kTile, cc = i % kTile;
+        stage[f * kTile + tf_col(f, cc)] = s2[(int64_t)f * kTileT + cc];
+    }
+    __syncthreads();
+    float2 v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int f = lane + kWave * m;
+        v[m] = cconj(stage[f * kTile + tf_col(f, wv)]);
+    }
+    __syncthreads();
+    wave_fft<FT, true, true>(v, lds + wv * kFftLds<FT>, twl, lane);   // F^H = conj F conj
+    const int p = pt * kTileT + half * kTile + wv;
+    if (p >= A.Bx * A.By) return;
+    const int jx = ch / A.sy, jy = ch % A.sy;
+    const int jb = A.S - 1 - ch;
+    const bool pair = A.mpcp && jb != ch;
+    const int px = p / A.By, py = p % A.By;
+    float* blk = dblocks + (int64_t)b * A.vblk;
+    float* r0 = blk + ((int64_t)(px * A.sx + jx) * A.NYf + (py * A.sy + jy)) * A.Bt;
+    const int jbx = jb / A.sy, jby = jb % A.sy;
+    float* r1 = blk + ((int64_t)((A.Bx - 1 - px) * A.sx + jbx) * A.NYf +
+                       ((A.By - 1 - py) * A.sy + jby)) * A.Bt;
+    const int mb = A.Bt / kWave;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if (m < mb) {
+            const float2 z = cconj(v[m]);
+            r0[lane + kWave * m] = z.x;
+            if (pair) r1[lane + kWave * m] = z.y;
+        }
+    }
+}
+
+// k_spp_adj: the transpose of k_spp for one group of NB bins at NF frequencies.
+// Phase A (per piece): dU of the output pixels -> Unpack^H (dY[q] = dU[q] + i dU[q'])
+// -> forward 2-D DFT with the box x boy inputs zero-padded to fs -> dacc[b][c][k1] in
+// registers of thread (kx, k2), the layout of the forward accumulators.
+// Phase B (per channel): s = sum_c conj(Rhat[ch][c]) dacc[c] -> inverse 2-D DFT with
+// outputs pruned to the bin's Bx x By pixels -> dT[ch] (layout of T).
+template <int FS, int L, int NIN, int NB>
+struct SppAdjLds {
+    int tw, YO, P2, YB, du, a2, gb, yb, g2, ob, A, B, total;
+};
+
+template <int FS, int L, int NIN, int NB, int NF>
+__host__ __device__ inline SppAdjLds<FS, L, NIN, NB> spp_adj_lds(int box, int boy, int Bx, int By) {
+    constexpr int RS = FS / L;
+    SppAdjLds<FS, L, NIN, NB> s;
+    s.tw = even_up(FS);
+    s.YO = (boy % 2 == 0) ? boy + 1 : boy;     // odd row stride of the output-gradient tile
+    s.P2 = even_up(FS) + 2;                    // even: 16-byte rows for the column reads
+    s.YB = (By % 2 == 0) ? By + 1 : By;
+    s.du = NB * NF * box * s.YO;
+    s.a2 = NB * NF * FS * s.P2;
+    s.gb = RS > 1 ? NB * NF * FS * L * RS : 0;
+    s.yb = NB * NF * FS * s.YB;
+    s.g2 = RS > 1 ? NB * NF * By * L * RS : 0;
+    s.ob = NB * NF * Bx * By;
+    s.A = even_up(s.du + s.a2);
+    int bb = s.gb > s.g2 + s.ob ? s.gb : s.g2 + s.ob;
+    s.B = even_up(bb + s.yb);
+    s.total = s.tw + (s.A > s.B ? s.A : s.B);
+    return s;
+}
+
+template <int FS, int L, int NIN, int NB>
+__global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdgpu_waves_per_eu(2))) void k_spp_adj(
+    ConvArgs A, int b0, int nbp, const int32_t* __restrict__ n_active,
+    const float2* __restrict__ dU, const float2* __restrict__ rhat,
+    const float2* __restrict__ tws, float2* __restrict__ dT) {
+    using S = SppShape<FS, L, NIN, NB>;
+    using P = Pfa<L, S::RS>;
+    constexpr int RS = S::RS, TPF = S::TPF, NF = S::NF, NT = S::NT;
+    extern __shared__ float4 sm4[];
+    float2* sm = (float2*)sm4;
+    const unsigned nbg = gridDim.x;
+    const int na = min(*n_active, A.cap);
+    const int nloc = min(nbp, na - b0);
+    const int bl0 = (int)(blockIdx.x % nbg) * NB;
+    if (bl0 >= nloc) return;
+    const int nbv = min(NB, nloc - bl0);
+    const int f0 = (int)blockIdx.y * NF;
+    const int tid = threadIdx.x;
+    const bool active = tid < NF * TPF;
+    const int tw_ = active ? tid : NF * TPF - 1;
+    const int fl = tw_ / TPF, item = tw_ % TPF;
+    const int kx = item / RS, k2 = item % RS;
+    const int Bx = A.Bx, By = A.By, box = A.box, boy = A.boy;
+    const auto Ls = spp_adj_lds<FS, L, NIN, NB, NF>(box, boy, Bx, By);
+    const int YO = Ls.YO, P2 = Ls.P2, YB = Ls.YB;
+    float2* twl = sm;
+    float2* reg = sm + Ls.tw;
+    float2* du = reg;                  // [NB][NF][box qx][YO qy]
+    float2* a2 = reg + Ls.du;          // [NB][NF][FS kx][P2 qy]
+    float2* gbuf = reg;                // [NB][NF][FS kx][L n1][RS k2]
+    float2* g2 = reg;                  // [NB][NF][By py][L n1][RS kk]
+    float2* ob = reg + Ls.g2;          // [NB][NF][Bx px][By py]
+    float2* yb = reg + (Ls.gb > Ls.g2 + Ls.ob ? Ls.gb : Ls.g2 + Ls.ob);   // [NB][NF][FS kx][YB py]
+    for (int i = tid; i < FS; i += NT) twl[i] = tws[i];
+    __syncthreads();
+    float2 wy[RS];
+#pragma unroll
+    for (int j = 0; j < RS; ++j) wy[j] = twl[((j * k2) % RS) * L];
+    const int qtiles = A.qpad / kTile;
+    const int nq = box * boy;
+
+    float2 dacc[NB][4][L];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (c < A.nc) {
+            // output-pixel gradients of piece c at the group's frequencies
+            for (int i = tid; i < NB * NF * nq; i += NT) {
+                const int q = i % nq;
+                const int r = i / nq;   // b * NF + fl2
+                const int fl2 = r % NF, b = r / NF;
+                float2 u = make_float2(0.f, 0.f);
+                if (b < nbv)
+                    u = dU[((((int64_t)(bl0 + b) * A.nc + c) * qtiles + q / kTile) * A.ft + f0 + fl2) *
+                               kTile + q % kTile];
+                du[(r * box + q / boy) * YO + q % boy] = u;
+            }
+            __syncthreads();
+            if (A.mpcp) {
+                // dY[q] = dU[q] + i dU[q'] for the mirror pair (q, q'), in place
+                const int npair = (nq + 1) / 2;
+                for (int i = tid; i < NB * NF * npair; i += NT) {
+                    const int q = i % npair, r = i / npair;
+                    const int qm = nq - 1 - q;
+                    float2* yy = du + r * box * YO;
+                    const int ia = (q / boy) * YO + q % boy, ib = (qm / boy) * YO + qm % boy;
+                    const float2 u = yy[ia], w = yy[ib];
+                    yy[ia] = make_float2(u.x - w.y, u.y + w.x);
+                    if (ib != ia) yy[ib] = make_float2(w.x - u.y, w.y + u.x);
+                }
+                __syncthreads();
+            }
+            // x stage: for each (b, qy, kk) an L-point DFT over the gathered qx < box
+            for (int i = tid; i < NB * NF * boy * RS; i += NT) {
+                const int kk = i % RS;
+                const int r = i / RS;
+                const int qy = r % boy, bf = r / boy;
+                float2 x[FS];
+#pragma unroll
+                for (int qx = 0; qx < FS; ++qx)
+                    x[qx] = qx < box ? du[(bf * box + qx) * YO + qy] : make_float2(0.f, 0.f);
+                float2 w[RS];
+#pragma unroll
+                for (int j = 0; j < RS; ++j) w[j] = twl[((j * kk) % RS) * L];
+                float2 t[L];
+                pfa_gather<L, RS, FS>(x, w, t);
+                Dft<L>::run(t);
+                float2* ar = a2 + bf * FS * P2 + qy;
+#pragma unroll
+                for (int m = 0; m < L; ++m) ar[P::k_of(m, kk) * P2] = t[m];
+            }
+            __syncthreads();
+            // y stage: thread (kx, k2) over the gathered qy < boy
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float2* ar = a2 + ((b * NF + fl) * FS + kx) * P2;
+                float2 x[FS];
+#pragma unroll
+                for (int qy = 0; qy < FS; ++qy) x[qy] = qy < boy ? ar[qy] : make_float2(0.f, 0.f);
+                pfa_gather<L, RS, FS>(x, wy, dacc[b][c]);
+                Dft<L>::run(dacc[b][c]);
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int m = 0; m < L; ++m) dacc[b][c][m] = make_float2(0.f, 0.f);
+        }
+    }
+
+    const int64_t rstride = (int64_t)A.nc * L * TPF;
+    const uint32_t rbytes = (uint32_t)(NF * rstride * 8);
+    const uint32_t rvoff = (uint32_t)(fl * rstride * 8 + item * 16);
+    const int ptiles = A.ppad / kTileT;
+    const int64_t tstride = (int64_t)ptiles * A.ft * kTileT;   // one channel of T
+    for (int ch = 0; ch < A.nch; ++ch) {
+        const auto rr = buf_rsrc(rhat + ((int64_t)ch * A.ft + f0) * rstride, rbytes);
+        // conjugate multiply-accumulate over the pieces and the L-point inverse over k1
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                float2 t[L];
+#pragma unroll
+                for (int m = 0; m < L; ++m) t[m] = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (c < A.nc) {
+#pragma unroll
+                        for (int mp = 0; mp < L / 2; ++mp) {
+                            const float4 v = buf_f4(rr, rvoff, (uint32_t)((c * L + 2 * mp) * TPF * 8));
+                            t[2 * mp] = cfma(dacc[b][c][2 * mp], make_float2(v.x, -v.y), t[2 * mp]);
+                            t[2 * mp + 1] = cfma(dacc[b][c][2 * mp + 1], make_float2(v.z, -v.w), t[2 * mp + 1]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < L; ++m) t[m] = cconj(t[m]);
+                Dft<L>::run(t);
+                const int bf = b * NF + fl;
+                if constexpr (RS == 1) {
+                    float2* yr = yb + (bf * FS + kx) * YB;
+#pragma unroll
+                    for (int n = 0; n < L; ++n)
+                        if (n < By) yr[n] = cconj(t[n]);
+                } else {
+                    float2* gr = gbuf + ((bf * FS + kx) * L) * RS + k2;
+#pragma unroll
+                    for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (RS > 1) {
+            for (int i = tid; i < NB * NF * FS * L; i += NT) {
+                const int n1 = i % L;
+                const int r = i / L;   // bf * FS + kx
+                const float2* gr = gbuf + (r * L + n1) * RS;
+                float2 t[RS];
+#pragma unroll
+                for (int k = 0; k < RS; ++k) t[k] = gr[k];
+                Dft<RS>::run(t);
+                float2* yr = yb + r * YB;
+#pragma unroll
+                for (int n2 = 0; n2 < RS; ++n2) {
+                    const int py = P::n_of(n1, n2);
+                    if (py < By) yr[py] = cconj(t[n2]);
+                }
+            }
+            __syncthreads();
+        }
+        // x inverse: L-point stage over kx = k_of(k1, kk) for every py
+        for (int i = tid; i < NB * NF * By * RS; i += NT) {
+            const int kk = i % RS;
+            const int r = i / RS;     // bf * By + py
+            const int py = r % By, bf = r / By;
+            const float2* yr = yb + bf * FS * YB + py;
+            float2 t[L];
+#pragma unroll
+            for (int m = 0; m < L; ++m) t[m] = cconj(yr[P::k_of(m, kk) * YB]);
+            Dft<L>::run(t);
+            if constexpr (RS == 1) {
+#pragma unroll
+                for (int n = 0; n < L; ++n)
+                    if (n < Bx) ob[(bf * Bx + n) * By + py] = cconj(t[n]);
+            } else {
+                float2* gr = g2 + (r * L) * RS + kk;
+#pragma unroll
+                for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
+            }
+        }
+        __syncthreads();
+        if constexpr (RS > 1) {
+            for (int i = tid; i < NB * NF * By * L; i += NT) {
+                const int n1 = i % L;
+                const int r = i / L;  // bf * By + py
+                const int py = r % By, bf = r / By;
+                const float2* gr = g2 + (r * L + n1) * RS;
+                float2 t[RS];
+#pragma unroll
+                for (int k = 0; k < RS; ++k) t[k] = gr[k];
+                Dft<RS>::run(t);
+#pragma unroll
+                for (int n2 = 0; n2 < RS; ++n2) {
+                    const int px = P::n_of(n1, n2);
+                    if (px < Bx) ob[(bf * Bx + px) * By + py] = cconj(t[n2]);
+                }
+            }
+            __syncthreads();
+        }
+        // dT[b][ch][p / kTileT][f][p % kTileT] for the bin's pixels p = px * By + py
+        const int npx = Bx * By;
+        for (int i = tid; i < NB * NF * npx; i += NT) {
+            const int p = i % npx;
+            const int r = i / npx;   // b * NF + fl2
+            const int fl2 = r % NF, b = r / NF;
+            if (b < nbv)
+                dT[((int64_t)(bl0 + b) * A.nch + ch) * tstride +
+                   ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT + p % kTileT] = ob[r * npx + p];
+        }
+        __syncthreads();
+    }
+}
+
 int pow2_at_least(int v, int lo) {
     int p = lo;
     while (p < v) p <<= 1;
@@ -1128,7 +1491,7 @@ tred_status launch_time_fwd(const ConvArgs& A, int b0, int nb, const int32_t* na
         return tred_fail(TRED_EUNSUPPORTED, "time forward: %lld B per bin", (long long)(A.vblk * 4));
     // persistent workgroups: a multiple of 2 kXcd (tile halves on one XCD), a few per CU
     const int64_t groups = (int64_t)(A.ppad / kTile) * A.nch * nb;
-    const int64_t cap = 4096;
+    const int64_t cap = TRED_TF_GRID;
     const int64_t G = std::min(cap, (groups + 2 * kXcd - 1) / (2 * kXcd) * (2 * kXcd));
     if (G <= 0) return TRED_OK;
     if (2 * A.Bt <= FT) {
@@ -1194,6 +1557,60 @@ tred_status launch_spp(const ConvArgs& A, int b0, int nb, const int32_t* na, con
     hipLaunchKernelGGL((k_spp<FS, L, NIN, NB>), dim3((nb + NB - 1) / NB, A.ft / S::NF), dim3(S::NT),
                        lds, st, A, b0, nb, na, T, rhat, tws, U);
     return tred_check_launch("tred_block_conv space");
+}
+
+template <int FS, int L, int NIN, int NB>
+tred_status launch_spp_adj(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* dU,
+                           const float2* rhat, const float2* tws, float2* dT, hipStream_t st) {
+    using S = SppShape<FS, L, NIN, NB>;
+    const auto Ls = spp_adj_lds<FS, L, NIN, NB, S::NF>(A.box, A.boy, A.Bx, A.By);
+    const size_t lds = (size_t)Ls.total * sizeof(float2);
+    if (lds > 160 * 1024)
+        return tred_fail(TRED_EUNSUPPORTED, "adjoint spatial stage needs %zu B of LDS", lds);
+    allow_lds(k_spp_adj<FS, L, NIN, NB>, lds);
+    hipLaunchKernelGGL((k_spp_adj<FS, L, NIN, NB>), dim3((nb + NB - 1) / NB, A.ft / S::NF),
+                       dim3(S::NT), lds, st, A, b0, nb, na, dU, rhat, tws, dT);
+    return tred_check_launch("tred_block_conv_adjoint space");
+}
+
+tred_status launch_space_adj(const tred_conv_plan* P, const ConvArgs& A, int b0, int nb,
+                             const int32_t* na, const float2* dU, const float2* rhat,
+                             const float2* tws, float2* dT, hipStream_t st) {
+    if (!P->pfa)
+        return tred_fail(TRED_EUNSUPPORTED, "adjoint: spatial size %d (sizes 8, 16, 24, 40, 48 only)",
+                         P->fs);
+    const bool two = P->nin == 2 * P->ls;
+    switch (P->fs) {
+        case 8: return launch_spp_adj<8, 8, 8, 1>(A, b0, nb, na, dU, rhat, tws, dT, st);
+        case 16: return launch_spp_adj<16, 16, 16, 1>(A, b0, nb, na, dU, rhat, tws, dT, st);
+        case 24:
+            return two ? launch_spp_adj<24, 8, 16, 1>(A, b0, nb, na, dU, rhat, tws, dT, st)
+                       : launch_spp_adj<24, 8, 8, 1>(A, b0, nb, na, dU, rhat, tws, dT, st);
+        case 40:
+            return two ? launch_spp_adj<40, 8, 16, 1>(A, b0, nb, na, dU, rhat, tws, dT, st)
+                       : launch_spp_adj<40, 8, 8, 1>(A, b0, nb, na, dU, rhat, tws, dT, st);
+        case 48:
+            return two ? launch_spp_adj<48, 16, 32, 1>(A, b0, nb, na, dU, rhat, tws, dT, st)
+                       : launch_spp_adj<48, 16, 16, 1>(A, b0, nb, na, dU, rhat, tws, dT, st);
+        default: return tred_fail(TRED_EUNSUPPORTED, "adjoint: spatial size %d", P->fs);
+    }
+}
+
+template <int FT>
+tred_status launch_time_adj(const ConvArgs& A, int b0, int nb, const int32_t* na, const float* dout,
+                            const float2* tw, float2* dU, float2* dT, float* dblocks, int stage,
+                            hipStream_t st) {
+    const size_t lds = (size_t)tf_lds_floats<FT>() * sizeof(float) + (size_t)FT * sizeof(float2);
+    if (stage == 0) {
+        allow_lds(k_ti_adj<FT>, lds);
+        hipLaunchKernelGGL((k_ti_adj<FT>), dim3(A.qpad / kTile, A.nc, nb), dim3(512), lds, st, A, b0,
+                           na, dout, tw, dU);
+    } else {
+        allow_lds(k_tf_adj<FT>, lds);
+        hipLaunchKernelGGL((k_tf_adj<FT>), dim3(A.ppad / kTile, A.nch, nb), dim3(512), lds, st, A, b0,
+                           na, dT, tw, dblocks);
+    }
+    return tred_check_launch("tred_block_conv_adjoint time");
 }
 
 tred_status launch_space_any(const tred_conv_plan* P, const ConvArgs& A, int b0, int nb,
@@ -1407,8 +1824,9 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
     auto mark = [&](int b0, int k) {
         if (P->timing && b0 == 0) (void)hipEventRecord(P->ev[k], st);
     };
-    for (int b0 = 0; b0 < cap; b0 += P->batch) {
-        const int nb = std::min(P->batch, cap - b0);
+    const int pass = std::min(P->batch, 65535);   // bins per pass (a grid dimension)
+    for (int b0 = 0; b0 < cap; b0 += pass) {
+        const int nb = std::min(pass, cap - b0);
         mark(b0, 0);
         TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
             return launch_time_fwd<decltype(ftc)::value>(A, b0, nb, n_active, blocks, twt, T, st);
@@ -1422,6 +1840,39 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
             return launch_time_inv<decltype(ftc)::value>(A, b0, nb, n_active, U, twt, out_blocks, st);
         }));
         mark(b0, 5);
+    }
+    return TRED_OK;
+}
+
+extern "C" tred_status tred_block_conv_adjoint(const tred_conv_plan* P, const int32_t* n_active,
+                                               int32_t cap, const float* d_out_blocks,
+                                               float* d_blocks, void* stream) {
+    TRED_REQUIRE(P && n_active, "plan/n_active is NULL");
+    TRED_REQUIRE(P->ready, "plan has no response (call tred_conv_plan_set_response)");
+    TRED_REQUIRE(cap >= 0, "cap must be >= 0");
+    if (cap == 0) return TRED_OK;
+    TRED_REQUIRE(d_out_blocks && d_blocks, "d_out_blocks/d_blocks is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    ConvArgs A = make_args(P);
+    A.cap = cap;
+    char* ws = (char*)P->ws;
+    const float2* twt = (const float2*)(ws + P->off_tw_t);
+    const float2* tws = (const float2*)(ws + P->off_tw_s);
+    const float2* rhat = (const float2*)(ws + P->off_rhat);
+    float2* T = (float2*)(ws + P->off_scratch_t);
+    float2* U = (float2*)(ws + P->off_scratch_u);
+    const int pass = std::min(P->batch, 65535);   // bins per pass (a grid dimension)
+    for (int b0 = 0; b0 < cap; b0 += pass) {
+        const int nb = std::min(pass, cap - b0);
+        TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
+            return launch_time_adj<decltype(ftc)::value>(A, b0, nb, n_active, d_out_blocks, twt, U,
+                                                         T, d_blocks, 0, st);
+        }));
+        TRED_TRY(launch_space_adj(P, A, b0, nb, n_active, U, rhat, tws, T, st));
+        TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
+            return launch_time_adj<decltype(ftc)::value>(A, b0, nb, n_active, d_out_blocks, twt, U,
+                                                         T, d_blocks, 1, st);
+        }));
     }
     return TRED_OK;
 }

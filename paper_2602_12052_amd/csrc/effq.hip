@@ -483,6 +483,277 @@ void launch_effq(const EffqParams& P, int64_t n_dep, const float* seg, const int
                        fp, off, val, val_cap, cs);
 }
 
+// ---------------------------------------------------------------------------
+// Gradient of the effective charge (Sec. V-A). The node charge q = Qp g(r, D, sigma)
+// is differentiated in forward mode with respect to the node offset r (3), the
+// segment vector D (3) and the widths sigma (3) (dual numbers, binary32); per node the
+// gradient of the loss with respect to its charge is the transposed trilinear spread
+// G_n = sum over the grid points g whose stencil holds n of u(g, n) dL/dV_g. The
+// sums over nodes (binary64) are carried through the chain rule of the transport
+// (t = z / v, t_mid, the widths and Qp = Q exp(-t_mid / lifetime)) per deposition.
+// ---------------------------------------------------------------------------
+constexpr int kNd = 9;   // partials: r_x, r_y, r_t, D_x, D_y, D_t, sigma_x, sigma_y, sigma_t
+struct Dual {
+    float v;
+    float d[kNd];
+};
+__device__ __forceinline__ Dual dconst(float v) {
+    Dual a;
+    a.v = v;
+#pragma unroll
+    for (int k = 0; k < kNd; ++k) a.d[k] = 0.f;
+    return a;
+}
+__device__ __forceinline__ Dual dvar(float v, int j) {
+    Dual a = dconst(v);
+#pragma unroll
+    for (int k = 0; k < kNd; ++k) a.d[k] = k == j ? 1.f : 0.f;
+    return a;
+}
+__device__ __forceinline__ Dual operator+(const Dual& a, const Dual& b) {
+    Dual c;
+    c.v = a.v + b.v;
+#pragma unroll
+    for (int k = 0; k < kNd; ++k) c.d[k] = a.d[k] + b.d[k];
+    return c;
+}
+__device__ __forceinline__ Dual operator-(const Dual& a, const Dual& b) {
+    Dual c;
+    c.v = a.v - b.v;
+#pragma unroll
+    for (int k = 0; k < kNd; ++k) c.d[k] = a.d[k] - b.d[k];
+    return c;
+}
+__device__ __forceinline__ Dual operator*(const Dual& a, const Dual& b) {
+    Dual c;
+    c.v = a.v * b.v;
+#pragma unroll
+    for (int k = 0; k < kNd; ++k) c.d[k] = a.d[k] * b.v + a.v * b.d[k];
+    return c;
+}
+__device__ __forceinline__ Dual operator*(float s, const Dual& a) {
+    Dual c;
+    c.v = s * a.v;
+#pragma unroll
+    for (int k = 0; k < kNd; ++k) c.d[k] = s * a.d[k];
+    return c;
+}
+// f(a) with f(a.v) = fv and f'(a.v) = fp
+__device__ __forceinline__ Dual dapply(const Dual& a, float fv, float fp) {
+    Dual c;
+    c.v = fv;
+#pragma unroll
+    for (int k = 0; k < kNd; ++k) c.d[k] = fp * a.d[k];
+    return c;
+}
+__device__ __forceinline__ Dual drcp(const Dual& a) {
+    const float r = 1.0f / a.v;
+    return dapply(a, r, -r * r);
+}
+__device__ __forceinline__ Dual dsqrt(const Dual& a) {
+    const float r = sqrtf(a.v);
+    return dapply(a, r, 0.5f / r);
+}
+
+__global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
+                                                  const float* __restrict__ seg,
+                                                  const int32_t* __restrict__ fp,
+                                                  const int64_t* __restrict__ off,
+                                                  const float* __restrict__ dval, int64_t val_cap,
+                                                  float* __restrict__ dseg,
+                                                  double* __restrict__ dphys) {
+    constexpr int NT = 256, NW = NT / kWave, NA = 10;
+    __shared__ double red[NW][NA];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const tred_grid& g = P.g;
+    const int ngl = P.ph.n_gl;
+    for (int64_t d = blockIdx.x; d < n_dep; d += gridDim.x) {
+        const int32_t* f = fp + 6 * d;
+        const int F0[3] = {f[0], f[1], f[2]}, F1[3] = {f[3], f[4], f[5]};
+        const bool empty = F1[0] < F0[0] || F1[1] < F0[1] || F1[2] < F0[2] || off[d + 1] > val_cap;
+        float s[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) s[k] = seg[7 * d + k];
+        const Win W = window_f32(g, P.ph, s);
+        // transport, as the forward kernel
+        const double v = P.ph.v_drift;
+        const double t0 = (double)s[2] / v, t1 = (double)s[5] / v;
+        const double tm_raw = 0.5 * (t0 + t1);
+        const double tm = tm_raw < 0.0 ? 0.0 : tm_raw;
+        const double att = exp(-tm / (double)P.ph.lifetime);
+        const double Qp = (double)s[6] * att;
+        const double sT = sqrt(2.0 * (double)P.ph.diff_T * tm);
+        const double sLr = sqrt(2.0 * (double)P.ph.diff_L * tm) / v;
+        const bool fl[3] = {!(sT >= (double)P.ph.sigma_min[0]), !(sT >= (double)P.ph.sigma_min[1]),
+                            !(sLr >= (double)P.ph.sigma_min[2])};
+        const double sg[3] = {fl[0] ? (double)P.ph.sigma_min[0] : sT, fl[1] ? (double)P.ph.sigma_min[1] : sT,
+                              fl[2] ? (double)P.ph.sigma_min[2] : sLr};
+        const double h[3] = {g.spacing[0], g.spacing[1], g.spacing[2]};
+        const double D[3] = {(double)s[3] - (double)s[0], (double)s[4] - (double)s[1], t1 - t0};
+        double base[3];
+        base[0] = (double)g.origin[0] + ((double)W.lo[0] + 0.5) * h[0] - (double)s[0];
+        base[1] = (double)g.origin[1] + ((double)W.lo[1] + 0.5) * h[1] - (double)s[1];
+        base[2] = (double)g.origin[2] + (double)W.lo[2] * h[2] - t0;
+        const bool point = W.point != 0;
+        float fb[3], fh[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            fb[a] = (float)(point ? base[a] - 0.5 * D[a] : base[a]);
+            fh[a] = (float)h[a];
+        }
+        const float jac = (float)(h[0] * h[1] * h[2] / 8.0);
+        int C0[3], C1[3], nn[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C0[a] = max(W.lo[a], F0[a] - 1);
+            C1[a] = min(W.hi[a], F1[a] + 1);
+            nn[a] = empty ? 0 : max(0, C1[a] - C0[a] + 1) * ngl;
+        }
+        const int FY = F1[1] - F0[1] + 1, FTt = F1[2] - F0[2] + 1;
+        const float* dv = dval + (empty ? 0 : off[d]);
+        double acc[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+        const int64_t total = (int64_t)nn[0] * nn[1] * nn[2];
+        for (int64_t i = tid; i < total; i += NT) {
+            const int kt = (int)(i % nn[2]);
+            const int64_t r = i / nn[2];
+            const int ky = (int)(r % nn[1]), kx = (int)(r / nn[1]);
+            const int cc[3] = {C0[0] + kx / ngl, C0[1] + ky / ngl, C0[2] + kt / ngl};
+            const int ll[3] = {kx % ngl, ky % ngl, kt % ngl};
+            // transposed spread: grid points c (1 - |xi| / 2) and c + sign(xi) (|xi| / 2)
+            float xi[3], wt = 1.0f;
+            int g2[3];
+            float u1[3], u2[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xi[a] = P.xi[ll[a]];
+                wt *= P.w[ll[a]];
+                u1[a] = 1.0f - 0.5f * fabsf(xi[a]);
+                u2[a] = 0.5f * fabsf(xi[a]);
+                g2[a] = xi[a] > 0.0f ? cc[a] + 1 : (xi[a] < 0.0f ? cc[a] - 1 : cc[a]);
+            }
+            float G = 0.0f;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                int gp[3];
+                float u = 1.0f;
+                bool ok = true;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const bool second = (m >> a) & 1;
+                    if (second && g2[a] == cc[a]) ok = false;
+                    gp[a] = second ? g2[a] : cc[a];
+                    u *= second ? u2[a] : u1[a];
+                    if (gp[a] < F0[a] || gp[a] > F1[a]) ok = false;
+                }
+                if (ok)
+                    G += u * dv[((int64_t)(gp[0] - F0[0]) * FY + (gp[1] - F0[1])) * FTt + (gp[2] - F0[2])];
+            }
+            if (G == 0.0f) continue;
+            const float rx = fb[0] + ((float)(cc[0] - W.lo[0]) + 0.5f * xi[0]) * fh[0];
+            const float ry = fb[1] + ((float)(cc[1] - W.lo[1]) + 0.5f * xi[1]) * fh[1];
+            const float rt = fb[2] + ((float)(cc[2] - W.lo[2]) + 0.5f * xi[2]) * fh[2];
+            const Dual R[3] = {dvar(rx, 0), dvar(ry, 1), dvar(rt, 2)};
+            const Dual SG[3] = {dvar((float)sg[0], 6), dvar((float)sg[1], 7), dvar((float)sg[2], 8)};
+            Dual IS[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) IS[a] = drcp(SG[a] * SG[a]);
+            const Dual ssp = SG[0] * SG[1] * SG[2];
+            Dual gq;
+            if (point) {
+                const Dual e = R[0] * R[0] * IS[0] + R[1] * R[1] * IS[1] + R[2] * R[2] * IS[2];
+                const float ex = exp_neg(-0.5f * e.v);
+                const Dual E = dapply(e, ex, -0.5f * ex);
+                gq = (0.0634936359342409697f) * (E * drcp(ssp));   // (2 pi)^(-3/2)
+            } else {
+                const Dual Dd[3] = {dvar((float)D[0], 3), dvar((float)D[1], 4), dvar((float)D[2], 5)};
+                const Dual al = Dd[0] * Dd[0] * IS[0] + Dd[1] * Dd[1] * IS[1] + Dd[2] * Dd[2] * IS[2];
+                const Dual be = R[0] * Dd[0] * IS[0] + R[1] * Dd[1] * IS[1] + R[2] * Dd[2] * IS[2];
+                const Dual sst = be * drcp(al);
+                Dual e = dconst(0.f);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const Dual pa = R[a] - sst * Dd[a];
+                    e = e + pa * pa * IS[a];
+                }
+                const float ex = exp_neg(-0.5f * e.v);
+                const Dual E = dapply(e, ex, -0.5f * ex);
+                const Dual kq = dsqrt(0.5f * al);
+                const Dual A1 = dconst(0.f) - kq * sst;         // lower limit
+                const Dual B1 = kq - kq * sst;                  // upper limit
+                const float ed = erf_diff(B1.v, A1.v);
+                const float gb = 1.12837916709551257f * exp_neg(-B1.v * B1.v);
+                const float ga = 1.12837916709551257f * exp_neg(-A1.v * A1.v);
+                Dual Ed;
+                Ed.v = ed;
+#pragma unroll
+                for (int k = 0; k < kNd; ++k) Ed.d[k] = gb * B1.d[k] - ga * A1.d[k];
+                // 1 / (4 pi sigma_x sigma_y sigma_t sqrt(alpha))
+                gq = (0.0795774715459476679f) * (E * Ed * drcp(ssp * dsqrt(al)));
+            }
+            const double Gw = (double)G * (double)wt * (double)jac;
+            acc[9] += Gw * (double)gq.v;
+#pragma unroll
+            for (int k = 0; k < kNd; ++k) acc[k] += Gw * Qp * (double)gq.d[k];
+        }
+        // workgroup reduction of the ten sums
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            double x = acc[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+            if (lane == 0) red[wave][k] = x;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double A[NA];
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+                A[k] = 0.0;
+                for (int w = 0; w < NW; ++w) A[k] += red[w][k];
+            }
+            // A[0..2]: d/dr, A[3..5]: d/dD, A[6..8]: d/dsigma, A[9]: d/dQp
+            double dP0[3], dP1[3];
+            for (int a = 0; a < 3; ++a) {
+                if (point) {
+                    dP0[a] = -0.5 * A[a];
+                    dP1[a] = -0.5 * A[a];
+                } else {
+                    dP0[a] = -A[a] - A[3 + a];
+                    dP1[a] = A[3 + a];
+                }
+            }
+            const double tau = P.ph.lifetime, DT = P.ph.diff_T, DL = P.ph.diff_L;
+            const double dsx = fl[0] || sT <= 0.0 ? 0.0 : DT / sT;
+            const double dsy = fl[1] || sT <= 0.0 ? 0.0 : DT / sT;
+            const double dst = fl[2] || sLr <= 0.0 ? 0.0 : DL / (v * v * sLr);
+            const double dtm = tm_raw < 0.0 ? 0.0 : 0.5;   // d t_mid / d t0 = d t_mid / d t1
+            const double Stm = A[6] * dsx + A[7] * dsy + A[8] * dst - A[9] * Qp / tau;
+            dP0[2] += dtm * Stm;
+            dP1[2] += dtm * Stm;
+            float* o = dseg + 7 * d;
+            o[0] = empty ? 0.f : (float)dP0[0];
+            o[1] = empty ? 0.f : (float)dP0[1];
+            o[2] = empty ? 0.f : (float)(dP0[2] / v);
+            o[3] = empty ? 0.f : (float)dP1[0];
+            o[4] = empty ? 0.f : (float)dP1[1];
+            o[5] = empty ? 0.f : (float)(dP1[2] / v);
+            o[6] = empty ? 0.f : (float)(A[9] * att);
+            if (dphys && !empty) {
+                const double gT = (fl[0] || sT <= 0.0 ? 0.0 : A[6] * tm / sT) +
+                                  (fl[1] || sT <= 0.0 ? 0.0 : A[7] * tm / sT);
+                const double gL = fl[2] || sLr <= 0.0 ? 0.0 : A[8] * tm / (v * v * sLr);
+                const double gTau = A[9] * Qp * tm / (tau * tau);
+                atomicAdd(dphys + 0, gT);
+                atomicAdd(dphys + 1, gL);
+                atomicAdd(dphys + 2, gTau);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 extern "C" tred_status tred_effq_windows(const tred_grid* grid, const tred_physics* phys,
@@ -504,6 +775,36 @@ extern "C" tred_status tred_effq_windows(const tred_grid* grid, const tred_physi
         TRED_TRY(tred_check_launch("tred_effq_windows scan"));
     }
     return TRED_OK;
+}
+
+extern "C" tred_status tred_effq_adjoint(const tred_grid* grid, const tred_physics* phys,
+                                         int64_t n_dep, const float* seg, const int32_t* fp,
+                                         const int64_t* off, const float* d_val, int64_t val_cap,
+                                         float* d_seg, double* d_phys, void* stream) {
+    TRED_TRY(validate_grid(grid));
+    TRED_TRY(validate_physics(phys));
+    TRED_REQUIRE(phys->point_frac > 0.0f, "physics.point_frac must be > 0 for the line form");
+    TRED_REQUIRE(n_dep >= 0, "n_dep must be >= 0");
+    TRED_REQUIRE(val_cap >= 0, "val_cap must be >= 0");
+    if (n_dep == 0) return TRED_OK;
+    TRED_REQUIRE(seg && fp && off && d_seg, "seg/fp/off/d_seg is NULL");
+    TRED_REQUIRE(d_val != nullptr || val_cap == 0, "d_val is NULL");
+    EffqParams P;
+    P.g = *grid;
+    P.ph = *phys;
+    double xi[8], w[8];
+    const int n = phys->n_gl;
+    gl_rule(n, xi, w);
+    for (int i = 0; i < 8; ++i) {
+        P.xi[i] = i < n ? (float)xi[i] : 0.f;
+        P.w[i] = i < n ? (float)w[i] : 0.f;
+    }
+    for (int k = 0; k < 16; ++k) P.u[k] = 0.f;
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned nb = (unsigned)std::min<int64_t>(n_dep, 1 << 20);
+    hipLaunchKernelGGL(k_effq_adj, dim3(nb), dim3(256), 0, st, P, n_dep, seg, fp, off, d_val,
+                       val_cap, d_seg, d_phys);
+    return tred_check_launch("tred_effq_adjoint");
 }
 
 extern "C" tred_status tred_effq(const tred_grid* grid, const tred_physics* phys, int64_t n_dep,

@@ -144,6 +144,44 @@ __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __res
     }
 }
 
+// Transpose of the overlap-add: every block-output sample takes the waveform gradient
+// of its pixel and tick; samples of pixels outside the region, of pixels without a
+// slot below pix_cap, or past the waveform end get zero. One workgroup per (output
+// bin, output pixel).
+__global__ __launch_bounds__(256) void k_scatter_adj(ScatArgs S, const int32_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ n_active,
+                                                     const int32_t* __restrict__ pix,
+                                                     const int32_t* __restrict__ n_pix,
+                                                     const float* __restrict__ dwf,
+                                                     float* __restrict__ dout) {
+    const int b = blockIdx.x, q = blockIdx.y;
+    if (b >= min(*n_active, S.cap)) return;
+    const int32_t* k = keys + (int64_t)S.kst * b;
+    const int e = S.kst == 4 ? k[0] : 0;
+    const int32_t* kb = k + (S.kst == 4 ? 1 : 0);
+    const int qx = q / S.boy, qy = q % S.boy;
+    const int px = kb[0] * S.Bx - S.hx + qx, py = kb[1] * S.By - S.hy + qy;
+    int slot = -1;
+    if (px >= 0 && px < S.npx && py >= 0 && py < S.npy) {
+        const int32_t id = (int32_t)(e * ((int64_t)S.npx * S.npy) + (int64_t)px * S.npy + py);
+        int lo = 0, hi = min(*n_pix, S.pix_cap) - 1;
+        while (lo <= hi) {                       // pix is ascending
+            const int mid = (lo + hi) >> 1;
+            const int32_t v = pix[mid];
+            if (v == id) { slot = mid; break; }
+            if (v < id) lo = mid + 1;
+            else hi = mid - 1;
+        }
+    }
+    float* row = dout + (int64_t)b * S.vout + (int64_t)q * S.bot;
+    const int T0 = kb[2] * S.Bt;
+    const float* w = dwf + (int64_t)(slot < 0 ? 0 : slot) * S.lwf;
+    for (int t = threadIdx.x; t < S.bot; t += blockDim.x) {
+        const int T = T0 + t;
+        row[t] = (slot >= 0 && T < S.lwf) ? w[T] : 0.0f;
+    }
+}
+
 ScatArgs make_sargs(const tred_conv_plan* P) {
     ScatArgs S;
     S.npx = P->grid.npix[0];
@@ -218,6 +256,26 @@ extern "C" tred_status tred_scatter_waveforms(const tred_conv_plan* P, const int
                                               float* wf, int32_t pix_cap, void* work,
                                               void* stream) {
     return scatter(P, 1, 3, keys, n_active, cap, out_blocks, pix, n_pix, wf, pix_cap, work, stream);
+}
+
+extern "C" tred_status tred_scatter_waveforms_adjoint(const tred_conv_plan* P, const int32_t* keys,
+                                                      const int32_t* n_active, int32_t cap,
+                                                      const int32_t* pix, const int32_t* n_pix,
+                                                      int32_t pix_cap, const float* d_wf,
+                                                      float* d_out_blocks, void* stream) {
+    TRED_REQUIRE(P && n_active && n_pix, "plan/n_active/n_pix is NULL");
+    TRED_REQUIRE(cap >= 0 && pix_cap >= 0, "capacities must be >= 0");
+    if (cap == 0) return TRED_OK;
+    TRED_REQUIRE(keys && d_out_blocks, "keys/d_out_blocks is NULL");
+    TRED_REQUIRE(pix_cap == 0 || (pix && d_wf), "pix/d_wf is NULL");
+    ScatArgs S = make_sargs(P);
+    S.cap = cap;
+    S.pix_cap = pix_cap;
+    hipStream_t st = (hipStream_t)stream;
+    TRED_REQUIRE(S.box * S.boy <= 65535, "output block of %d pixels", S.box * S.boy);
+    hipLaunchKernelGGL(k_scatter_adj, dim3(cap, S.box * S.boy), dim3(256), 0, st, S, keys, n_active,
+                       pix, n_pix, d_wf, d_out_blocks);
+    return tred_check_launch("tred_scatter_waveforms_adjoint");
 }
 
 extern "C" int64_t tred_scatter_events_workspace(const tred_conv_plan* P, int32_t n_ev) {

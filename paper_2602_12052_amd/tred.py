@@ -71,6 +71,8 @@ EXPORTS = [
     "tred_direct_plan_create", "tred_direct_plan_set_response", "tred_block_conv_direct",
     "tred_direct_plan_destroy", "tred_block_bin_events_workspace", "tred_block_bin_events",
     "tred_scatter_events_workspace", "tred_scatter_waveforms_events",
+    "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint", "tred_block_bin_adjoint",
+    "tred_effq_adjoint",
 ]
 
 _lib = None
@@ -119,12 +121,18 @@ def lib():
     L.tred_scatter_events_workspace.argtypes = [P, I32]
     L.tred_scatter_events_workspace.restype = I64
     L.tred_scatter_waveforms_events.argtypes = [P, I32, P, P, I32, P, P, P, P, I32, P, P]
+    L.tred_scatter_waveforms_adjoint.argtypes = [P, P, P, I32, P, P, I32, P, P, P]
+    L.tred_block_conv_adjoint.argtypes = [P, P, I32, P, P, P]
+    L.tred_block_bin_adjoint.argtypes = [P, P, I64, P, P, I64, P, P, P, I32, P, P, P]
+    L.tred_effq_adjoint.argtypes = [P, P, I64, P, P, P, P, I64, P, P, P]
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
                  "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
                  "tred_scatter_waveforms", "tred_direct_plan_create",
                  "tred_direct_plan_set_response", "tred_block_conv_direct",
-                 "tred_block_bin_events", "tred_scatter_waveforms_events"):
+                 "tred_block_bin_events", "tred_scatter_waveforms_events",
+                 "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint",
+                 "tred_block_bin_adjoint", "tred_effq_adjoint"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -370,6 +378,54 @@ def tred_scatter_waveforms(plan: ConvPlan, keys, n_active, out_blocks, pix, n_pi
 
 
 # ---------------------------------------------------------------------------
+# Gradients: transposes of the four calls (same names with _adjoint)
+# ---------------------------------------------------------------------------
+
+
+def tred_scatter_waveforms_adjoint(plan: ConvPlan, keys, n_active, pix, n_pix, d_wf, d_out_blocks,
+                                   stream=None):
+    import torch
+    _dt(d_wf, torch.float32, "d_wf"), _dt(d_out_blocks, torch.float32, "d_out_blocks")
+    cap = keys.shape[0]
+    _check(lib().tred_scatter_waveforms_adjoint(plan.handle, _ptr(keys), _ptr(n_active), cap,
+                                                _ptr(pix), _ptr(n_pix), pix.shape[0], _ptr(d_wf),
+                                                _ptr(d_out_blocks), _stream(stream)))
+
+
+def tred_block_conv_adjoint(plan: ConvPlan, n_active, d_out_blocks, d_blocks, stream=None):
+    import torch
+    _dt(d_out_blocks, torch.float32, "d_out_blocks"), _dt(d_blocks, torch.float32, "d_blocks")
+    cap = d_blocks.shape[0]
+    if d_out_blocks.shape[0] < cap:
+        raise ValueError("d_out_blocks has fewer rows than d_blocks")
+    _check(lib().tred_block_conv_adjoint(plan.handle, _ptr(n_active), cap, _ptr(d_out_blocks),
+                                         _ptr(d_blocks), _stream(stream)))
+
+
+def tred_block_bin_adjoint(grid, blocking, fp, off, keys, n_active, d_blocks, d_val, work,
+                           stream=None):
+    import torch
+    _dt(d_blocks, torch.float32, "d_blocks"), _dt(d_val, torch.float32, "d_val")
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    cap = keys.shape[0]
+    _check(lib().tred_block_bin_adjoint(C.byref(g), C.byref(b), fp.shape[0], _ptr(fp), _ptr(off),
+                                        d_val.numel(), _ptr(keys), _ptr(n_active), _ptr(d_blocks),
+                                        cap, _ptr(d_val), _ptr(work), _stream(stream)))
+
+
+def tred_effq_adjoint(grid, phys, seg, fp, off, d_val, d_seg, d_phys=None, stream=None):
+    """d_seg [n][7] out; d_phys (float64 [3], accumulated) gets dL/d(diff_T, diff_L,
+    lifetime)."""
+    import torch
+    _dt(d_val, torch.float32, "d_val"), _dt(d_seg, torch.float32, "d_seg")
+    _dt(d_phys, torch.float64, "d_phys")
+    g, p = grid_struct(grid), physics_struct(phys)
+    _check(lib().tred_effq_adjoint(C.byref(g), C.byref(p), seg.shape[0], _ptr(seg), _ptr(fp),
+                                   _ptr(off), _ptr(d_val), d_val.numel(), _ptr(d_seg),
+                                   _ptr(d_phys), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
 # Whole path
 # ---------------------------------------------------------------------------
 
@@ -421,6 +477,29 @@ class Pipeline:
         tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
         tred_scatter_waveforms(self.plan, self.keys, self.n_active, self.out_blocks, self.pix,
                                self.n_pix, self.wf, self.scat_work, stream)
+
+    def backward(self, seg, d_wf, stream=None):
+        """Gradients of a loss L with respect to the depositions and the transport
+        parameters, given dL/dwf for the waveforms of the last run(seg): returns
+        (d_seg [n][7] float32, d_phys float64 [3] = dL/d(diff_T, diff_L, lifetime)).
+        The chain runs the four adjoint calls on the integer structures of run()
+        (footprints, keys, pixel list); the effective charge is recomputed."""
+        import torch
+        if not hasattr(self, "d_out_blocks"):
+            self.d_out_blocks = torch.empty_like(self.out_blocks)
+            self.d_blocks = torch.empty_like(self.blocks)
+            self.d_val = torch.empty_like(self.val)
+            self.d_seg = torch.empty((self.n_dep, 7), dtype=torch.float32, device="cuda")
+            self.d_phys = torch.zeros(3, dtype=torch.float64, device="cuda")
+        tred_scatter_waveforms_adjoint(self.plan, self.keys, self.n_active, self.pix, self.n_pix,
+                                       d_wf, self.d_out_blocks, stream)
+        tred_block_conv_adjoint(self.plan, self.n_active, self.d_out_blocks, self.d_blocks, stream)
+        tred_block_bin_adjoint(self.grid, self.blocking, self.fp, self.off, self.keys,
+                               self.n_active, self.d_blocks, self.d_val, self.bin_work, stream)
+        self.d_phys.zero_()
+        tred_effq_adjoint(self.grid, self.phys, seg, self.fp, self.off, self.d_val, self.d_seg,
+                          self.d_phys, stream)
+        return self.d_seg, self.d_phys
 
     def results(self):
         """Host copies of the outputs (synchronises)."""
@@ -588,3 +667,29 @@ def simulate(seg, resp, grid, phys, blocking, kpix, kticks, fft=None, mpcp=True,
                   pix_cap, fft, mpcp, batch)
     pl.run(seg)
     return pl.results()
+
+
+class Simulate:
+    """torch.autograd.Function over a Pipeline: waveforms of the depositions seg
+    (float32 [n][7] on the GPU, requires_grad for d/d(end points, charge)). The pixel
+    list of the forward pass fixes the waveform rows; backward returns dL/dseg and
+    accumulates dL/d(diff_T, diff_L, lifetime) into pipeline.d_phys."""
+
+    @staticmethod
+    def apply(pipeline, seg):
+        import torch
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, s):
+                pipeline.run(s)
+                ctx.save_for_backward(s)
+                return pipeline.wf.clone()
+
+            @staticmethod
+            def backward(ctx, g):
+                (s,) = ctx.saved_tensors
+                d_seg, _ = pipeline.backward(s, g.contiguous())
+                return d_seg.clone()
+
+        return _F.apply(seg)
