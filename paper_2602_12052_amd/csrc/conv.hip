@@ -30,6 +30,10 @@
 #ifndef TRED_XCD_REMAP
 #define TRED_XCD_REMAP 1
 #endif
+// bins per workgroup of the transposed spatial stage at fs = 40
+#ifndef TRED_SPP_ADJ_NB
+#define TRED_SPP_ADJ_NB 1
+#endif
 // persistent workgroups of the forward time FFTs (at most)
 #ifndef TRED_TF_GRID
 #define TRED_TF_GRID 4096
@@ -1587,8 +1591,8 @@ tred_status launch_space_adj(const tred_conv_plan* P, const ConvArgs& A, int b0,
             return two ? launch_spp_adj<24, 8, 16, 1>(A, b0, nb, na, dU, rhat, tws, dT, st)
                        : launch_spp_adj<24, 8, 8, 1>(A, b0, nb, na, dU, rhat, tws, dT, st);
         case 40:
-            return two ? launch_spp_adj<40, 8, 16, 1>(A, b0, nb, na, dU, rhat, tws, dT, st)
-                       : launch_spp_adj<40, 8, 8, 1>(A, b0, nb, na, dU, rhat, tws, dT, st);
+            return two ? launch_spp_adj<40, 8, 16, TRED_SPP_ADJ_NB>(A, b0, nb, na, dU, rhat, tws, dT, st)
+                       : launch_spp_adj<40, 8, 8, TRED_SPP_ADJ_NB>(A, b0, nb, na, dU, rhat, tws, dT, st);
         case 48:
             return two ? launch_spp_adj<48, 16, 32, 1>(A, b0, nb, na, dU, rhat, tws, dT, st)
                        : launch_spp_adj<48, 16, 16, 1>(A, b0, nb, na, dU, rhat, tws, dT, st);

@@ -185,10 +185,16 @@ __device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t voff
 __device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
+// Streaming stores of data read only by a later kernel (larger than the L2) may carry
+// the non-temporal cache policy (TRED_NT_STORE).
+#ifndef TRED_NT_STORE
+#define TRED_NT_STORE 0
+#endif
 __device__ __forceinline__ void buf_st_f2(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
                                           uint32_t soff) {
     using u2 = __attribute__((ext_vector_type(2))) unsigned int;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff,
+                                          TRED_NT_STORE ? 2 : 0);
 }
 
 __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
