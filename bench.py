@@ -83,12 +83,24 @@ def conv_flops_per_block(blk, sub, kpix, kticks, fft, mpcp):
     return dict(tf=tf, sp=sp, ti=ti, total=tf + sp + ti)
 
 
-def src_sha(paths):
+def src_sha(parts):
+    """Hash of source text: each part is a path, or (path, first marker, end marker) for
+    the lines from the first marker up to the end marker."""
     h = hashlib.sha256()
-    for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+    for part in parts:
+        path, a, b = (part, None, None) if isinstance(part, str) else part
+        with open(os.path.join(ROOT, path), "rb") as f:
+            text = f.read()
+        if a is not None:
+            i = text.index(a.encode())
+            text = text[i:text.index(b.encode(), i)]
+        h.update(text)
     return h.hexdigest()[:16]
+
+
+# the source of the k_spp kernel: its section of conv.hip and the shared device helpers
+KSPP_SOURCE = [("paper_2602_12052_amd/csrc/conv.hip", "// k_spp: the spatial stage",
+                "// k_ti: inverse time FFT"), "paper_2602_12052_amd/csrc/tred_internal.hpp"]
 
 
 def profile_traffic(kernel_key, sha):
@@ -502,7 +514,7 @@ def main():
     sp_blocks = min(batch, n_act)
     sp_ms = float(conv_stages[:, 1].mean())
     achieved = fl["sp"] * sp_blocks / (sp_ms * 1e-3) / 1e12
-    sha = src_sha(["paper_2602_12052_amd/csrc/conv.hip", "paper_2602_12052_amd/csrc/tred_internal.hpp"])
+    sha = src_sha(KSPP_SOURCE)
     traffic = profile_traffic("k_spp", sha) if args.workload == "module" else None
     vblk = Bx * cfg.grid.sub[0] * By * cfg.grid.sub[1] * Bt
     vout = box * boy * (Bt + cfg.kticks - 1)
