@@ -1169,7 +1169,7 @@ __host__ __device__ inline SppAdjLds<FS, L, NIN, NB> spp_adj_lds(int box, int bo
     s.a2 = NB * NF * FS * s.P2;
     s.gb = RS > 1 ? NB * NF * FS * L * RS : 0;
     s.yb = NB * NF * FS * s.YB;
-    s.g2 = RS > 1 ? NB * NF * By * L * RS : 0;
+    s.g2 = RS > 1 ? NB * NF * NIN * L * RS : 0;
     s.ob = NB * NF * Bx * By;
     s.A = even_up(s.du + s.a2);
     int bb = s.gb > s.g2 + s.ob ? s.gb : s.g2 + s.ob;
@@ -1293,6 +1293,28 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     const uint32_t rvoff = (uint32_t)(fl * rstride * 8 + item * 16);
     const int ptiles = A.ppad / kTileT;
     const int64_t tstride = (int64_t)ptiles * A.ft * kTileT;   // one channel of T
+    // output items of this thread (b, fl2, p): LDS source and byte offset in channel ch of
+    // bin bl0 (the host keeps NB channels' worth of bins below 2^31 bytes)
+    constexpr int IT5 = (NB * NF * NIN * NIN + NT - 1) / NT;
+    int o_src[IT5];
+    uint32_t o_off[IT5];
+    bool o_ok[IT5];
+    {
+        const int npx = Bx * By;
+#pragma unroll
+        for (int k = 0; k < IT5; ++k) {
+            const int i = tid + k * NT;
+            const int p = i % npx;
+            const int r = i / npx;   // b * NF + fl2
+            const int fl2 = r % NF, b = r / NF;
+            o_ok[k] = i < NB * NF * npx && b < nbv;
+            o_src[k] = o_ok[k] ? r * npx + p : 0;
+            o_off[k] = o_ok[k] ? (uint32_t)(8 * ((int64_t)b * A.nch * tstride +
+                                                  ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT +
+                                                  p % kTileT))
+                               : 0u;
+        }
+    }
     for (int ch = 0; ch < A.nch; ++ch) {
         const auto rr = buf_rsrc(rhat + ((int64_t)ch * A.ft + f0) * rstride, rbytes);
         // conjugate multiply-accumulate over the pieces and the L-point inverse over k1
@@ -1340,62 +1362,78 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 for (int k = 0; k < RS; ++k) t[k] = gr[k];
                 Dft<RS>::run(t);
                 float2* yr = yb + r * YB;
+                int py = (RS * n1) % FS;   // n_of(n1, n2), stepping n2 by L (mod FS)
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
-                    const int py = P::n_of(n1, n2);
                     if (py < By) yr[py] = cconj(t[n2]);
+                    py += L;
+                    py = py >= FS ? py - FS : py;
                 }
             }
             __syncthreads();
         }
-        // x inverse: L-point stage over kx = k_of(k1, kk) for every py
-        for (int i = tid; i < NB * NF * By * RS; i += NT) {
+        // x inverse: L-point stage over kx = k_of(k1, kk) for every py. Items run over
+        // py < NIN (a compile-time bound) so that their decomposition is shifts and
+        // multiplies by constants; rows py >= By are skipped.
+#pragma unroll
+        for (int it = 0; it < (NB * NF * NIN * RS + NT - 1) / NT; ++it) {
+            const int i = tid + it * NT;
             const int kk = i % RS;
-            const int r = i / RS;     // bf * By + py
-            const int py = r % By, bf = r / By;
+            const int r = i / RS;     // bf * NIN + py
+            const int py = r % NIN, bf = r / NIN;
+            if (i >= NB * NF * NIN * RS || py >= By) continue;
             const float2* yr = yb + bf * FS * YB + py;
             float2 t[L];
+            const int kb = (Pfa<L, RS>::k_of(0, 1) * kk) % FS;   // k_of(0, kk)
 #pragma unroll
-            for (int m = 0; m < L; ++m) t[m] = cconj(yr[P::k_of(m, kk) * YB]);
+            for (int m = 0; m < L; ++m) {
+                int kxm = kb + P::k_of(m, 0);
+                kxm = kxm >= FS ? kxm - FS : kxm;
+                t[m] = cconj(yr[kxm * YB]);
+            }
             Dft<L>::run(t);
             if constexpr (RS == 1) {
 #pragma unroll
                 for (int n = 0; n < L; ++n)
                     if (n < Bx) ob[(bf * Bx + n) * By + py] = cconj(t[n]);
             } else {
-                float2* gr = g2 + (r * L) * RS + kk;
+                float2* gr = g2 + ((bf * NIN + py) * L) * RS + kk;   // [bf][py][n1][kk]
 #pragma unroll
                 for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
             }
         }
         __syncthreads();
         if constexpr (RS > 1) {
-            for (int i = tid; i < NB * NF * By * L; i += NT) {
+#pragma unroll
+            for (int it = 0; it < (NB * NF * NIN * L + NT - 1) / NT; ++it) {
+                const int i = tid + it * NT;
                 const int n1 = i % L;
-                const int r = i / L;  // bf * By + py
-                const int py = r % By, bf = r / By;
+                const int r = i / L;  // bf * NIN + py
+                const int py = r % NIN, bf = r / NIN;
+                if (i >= NB * NF * NIN * L || py >= By) continue;
                 const float2* gr = g2 + (r * L + n1) * RS;
                 float2 t[RS];
 #pragma unroll
                 for (int k = 0; k < RS; ++k) t[k] = gr[k];
                 Dft<RS>::run(t);
+                int px = (RS * n1) % FS;   // n_of(n1, n2)
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
-                    const int px = P::n_of(n1, n2);
                     if (px < Bx) ob[(bf * Bx + px) * By + py] = cconj(t[n2]);
+                    px += L;
+                    px = px >= FS ? px - FS : px;
                 }
             }
             __syncthreads();
         }
-        // dT[b][ch][p / kTileT][f][p % kTileT] for the bin's pixels p = px * By + py
-        const int npx = Bx * By;
-        for (int i = tid; i < NB * NF * npx; i += NT) {
-            const int p = i % npx;
-            const int r = i / npx;   // b * NF + fl2
-            const int fl2 = r % NF, b = r / NF;
-            if (b < nbv)
-                dT[((int64_t)(bl0 + b) * A.nch + ch) * tstride +
-                   ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT + p % kTileT] = ob[r * npx + p];
+        // dT[b][ch][p / kTileT][f][p % kTileT] for the bin's pixels p = px * By + py, with
+        // the per-thread offsets computed before the channel loop
+        {
+            const auto tr = buf_rsrc(dT + ((int64_t)bl0 * A.nch + ch) * tstride,
+                                     (uint32_t)(((int64_t)nbv * A.nch - ch) * tstride * 8));
+#pragma unroll
+            for (int k = 0; k < IT5; ++k)
+                if (o_ok[k]) buf_st_f2(ob[o_src[k]], tr, o_off[k], 0u);
         }
         __syncthreads();
     }
@@ -1571,6 +1609,10 @@ tred_status launch_spp_adj(const ConvArgs& A, int b0, int nb, const int32_t* na,
     const size_t lds = (size_t)Ls.total * sizeof(float2);
     if (lds > 160 * 1024)
         return tred_fail(TRED_EUNSUPPORTED, "adjoint spatial stage needs %zu B of LDS", lds);
+    const int64_t tbytes = (int64_t)NB * A.nch * (A.ppad / kTileT) * A.ft * kTileT * 8;
+    if (tbytes > INT32_MAX)
+        return tred_fail(TRED_EUNSUPPORTED, "adjoint spatial stage: %lld B of spectra per workgroup",
+                         (long long)tbytes);
     allow_lds(k_spp_adj<FS, L, NIN, NB>, lds);
     hipLaunchKernelGGL((k_spp_adj<FS, L, NIN, NB>), dim3((nb + NB - 1) / NB, A.ft / S::NF),
                        dim3(S::NT), lds, st, A, b0, nb, na, dU, rhat, tws, dT);

@@ -563,7 +563,9 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
                                                   float* __restrict__ dseg,
                                                   double* __restrict__ dphys) {
     constexpr int NT = 256, NW = NT / kWave, NA = 10;
+    constexpr int CAPA = 12288;   // patch cells staged in LDS (larger patches read memory)
     __shared__ double red[NW][NA];
+    __shared__ float sdv[CAPA];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const tred_grid& g = P.g;
     const int ngl = P.ph.n_gl;
@@ -611,6 +613,12 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
         }
         const int FY = F1[1] - F0[1] + 1, FTt = F1[2] - F0[2] + 1;
         const float* dv = dval + (empty ? 0 : off[d]);
+        const int64_t cnt = empty ? 0 : off[d + 1] - off[d];
+        const bool staged = cnt <= CAPA;
+        if (staged) {
+            for (int64_t k = tid; k < cnt; k += NT) sdv[k] = dv[k];
+            __syncthreads();
+        }
         double acc[NA];
 #pragma unroll
         for (int k = 0; k < NA; ++k) acc[k] = 0.0;
@@ -647,8 +655,11 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
                     u *= second ? u2[a] : u1[a];
                     if (gp[a] < F0[a] || gp[a] > F1[a]) ok = false;
                 }
-                if (ok)
-                    G += u * dv[((int64_t)(gp[0] - F0[0]) * FY + (gp[1] - F0[1])) * FTt + (gp[2] - F0[2])];
+                if (ok) {
+                    const int64_t at = ((int64_t)(gp[0] - F0[0]) * FY + (gp[1] - F0[1])) * FTt +
+                                       (gp[2] - F0[2]);
+                    G += u * (staged ? sdv[at] : dv[at]);
+                }
             }
             if (G == 0.0f) continue;
             const float rx = fb[0] + ((float)(cc[0] - W.lo[0]) + 0.5f * xi[0]) * fh[0];
