@@ -68,7 +68,8 @@ def fft_flops(n, nnz=None):
 
 
 def conv_flops_per_block(blk, sub, kpix, kticks, fft, mpcp):
-    """Algorithmic FLOPs of the three convolution stages for one bin."""
+    """Algorithmic FLOPs of the three convolution stages for one bin: 5 N log2 N per N-point
+    complex FFT (pruned inputs credited for power-of-two N), 8 per complex multiply-add."""
     Bx, By, Bt = blk
     fs, ft = fft[0], fft[2]
     nch = (sub[0] * sub[1] + 1) // 2 if mpcp else sub[0] * sub[1]
