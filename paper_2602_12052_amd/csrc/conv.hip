@@ -275,7 +275,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     };
     // twiddle table in LDS after the FFT scratch / staging region
     float2* twl = (float2*)(lds + tf_lds_floats<FT>());
-    for (int i = threadIdx.x; i < FT; i += blockDim.x) twl[i] = tw[i];
+    fft_tw_fill<FT>(twl, tw, threadIdx.x, blockDim.x);
     int q = blockIdx.x;
     if (q < total) load(q);
     __syncthreads();
@@ -978,7 +978,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     for (int m = 0; m < MH; ++m) carry[m] = 0.0f;
     // twiddle table in LDS after the FFT scratch / staging region
     float2* twl = (float2*)(lds + tf_lds_floats<FT>());
-    for (int i = threadIdx.x; i < FT; i += blockDim.x) twl[i] = tw[i];
+    fft_tw_fill<FT>(twl, tw, threadIdx.x, blockDim.x);
     for (int c = 0; c < A.nc; ++c) {
         const float2* s2 = U + ((((int64_t)bl * A.nc + c) * qtiles + qt) * FT) * kTile;
         float2* stage = (float2*)lds;   // [f][kTile], columns swizzled (tf_col)
@@ -1067,7 +1067,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     const int q = qt * kTile + wv;
     const bool valid = q < A.box * A.boy;
     float2* twl = (float2*)(lds + tf_lds_floats<FT>());
-    for (int i = threadIdx.x; i < FT; i += blockDim.x) twl[i] = tw[i];
+    fft_tw_fill<FT>(twl, tw, threadIdx.x, blockDim.x);
     const float* row = dout + (int64_t)b * A.vout + (int64_t)(valid ? q : 0) * A.bot;
     float2 v[M];
 #pragma unroll
@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int pt = blockIdx.x / (kTileT / kTile), half = blockIdx.x % (kTileT / kTile);
     float2* twl = (float2*)(lds + tf_lds_floats<FT>());
-    for (int i = threadIdx.x; i < FT; i += blockDim.x) twl[i] = tw[i];
+    fft_tw_fill<FT>(twl, tw, threadIdx.x, blockDim.x);
     // stage the half tile [f][kTile] of T-layout gradients
     const float2* s2 = dT + (((int64_t)bl * A.nch + ch) * (A.ppad / kTileT) + pt) * FT * kTileT +
                        half * kTile;

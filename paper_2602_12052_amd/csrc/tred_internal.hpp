@@ -248,7 +248,8 @@ __device__ __forceinline__ void pfa_gather(const float2* x, const float2* w, flo
 // Per-wavefront Stockham FFT of length N = 64 * M (M in {4, 8, 16, 32, 64}).
 // On entry lane l holds x[l + 64 m] in v[m]; on exit X[l + 64 m] (forward DFT,
 // natural order). `buf` is the wave's private LDS scratch of kFftLds<N> floats;
-// `tw` is a table of exp(-2 pi i k / N), k < N, in device memory or (TWL) in LDS.
+// `tw` is a table of exp(-2 pi i k / N), k < N, in device memory, or (TWL) the
+// per-stage tables of FftTw<N> in LDS.
 // Radix sequence: N = R1 * R2 * ... with every radix <= 16. The scratch is private
 // to the wave (no workgroup barrier inside).
 // Stage (radix R, Ns = product of earlier radices): butterfly j reads
@@ -262,6 +263,47 @@ template <> struct FftPlan<512>  { static constexpr int R[4] = {8, 8, 8, 1}; sta
 template <> struct FftPlan<1024> { static constexpr int R[4] = {16, 16, 4, 1}; static constexpr int S = 3; };
 template <> struct FftPlan<2048> { static constexpr int R[4] = {16, 16, 8, 1}; static constexpr int S = 3; };
 template <> struct FftPlan<4096> { static constexpr int R[4] = {16, 16, 16, 1}; static constexpr int S = 3; };
+
+// Per-stage twiddle tables for LDS: stage s (radix R, Ns = product of the earlier
+// radices, Ns > 1) holds W_N^(r j (N / (Ns R))) at [r - 1][j], r = 1 .. R-1, j < Ns, so
+// the lanes of a wave (consecutive j) read consecutive words. The tables of all stages
+// take fewer than N entries.
+template <int N>
+struct FftTw {
+    using P = FftPlan<N>;
+    static constexpr int ns(int s) {
+        int v = 1;
+        for (int t = 0; t < s; ++t) v *= P::R[t];
+        return v;
+    }
+    static constexpr int size(int s) { return s == 0 ? 0 : ns(s) * (P::R[s] - 1); }
+    static constexpr int off(int s) {
+        int o = 0;
+        for (int t = 0; t < s; ++t) o += size(t);
+        return o;
+    }
+    static constexpr int stage_of(int nsv) {
+        for (int t = 0; t < P::S; ++t)
+            if (ns(t) == nsv) return t;
+        return -1;
+    }
+    static constexpr int total() { return off(P::S); }
+    static_assert(total() <= N, "stage twiddles exceed the table");
+};
+
+// fill the per-stage tables at dst (LDS) from the N-entry table tw (device memory)
+template <int N>
+__device__ __forceinline__ void fft_tw_fill(float2* dst, const float2* __restrict__ tw, int tid,
+                                            int nthreads) {
+    using F = FftTw<N>;
+    for (int s = 1; s < F::P::S; ++s) {
+        const int nsv = F::ns(s), R = F::P::R[s];
+        for (int i = tid; i < F::size(s); i += nthreads) {
+            const int r = i / nsv + 1, j = i % nsv;
+            dst[F::off(s) + i] = tw[r * j * (N / (nsv * R))];
+        }
+    }
+}
 
 // Ordering of LDS accesses within one wavefront: the wave's LDS operations execute
 // in issue order, so it suffices to keep the compiler from moving accesses across
@@ -284,7 +326,7 @@ __device__ __forceinline__ void fft_sync() {
     else __syncthreads();
 }
 
-// TWL: the twiddle table is in LDS and read where it is used (LDS loads leave the
+// TWL: the per-stage twiddle tables (FftTw) are in LDS and read where they are used (LDS loads leave the
 // vector-memory counter alone, so loads in flight from before the FFT are not waited
 // for); otherwise it is in device memory, read through a buffer resource (32-bit
 // offsets), and a stage requests all its twiddles before its first butterfly.
@@ -332,10 +374,15 @@ __device__ __forceinline__ void fft_stage(float2* v, float* buf, const float2* t
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = FIRST ? u[i + r * PER] : u[i * R + r];
         if constexpr (NS > 1) {
-            const int jm = j % NS;
+            if constexpr (TWL) {
+                // one base per butterfly, the radix index in the immediate offset
+                const float2* twb = tw + FftTw<N>::off(FftTw<N>::stage_of(NS)) + j % NS;
 #pragma unroll
-            for (int r = 1; r < R; ++r)
-                x[r] = cmul(x[r], TWL ? tw[r * jm * (N / (NS * R))] : w[i][NW > 1 ? r : 0]);
+                for (int r = 1; r < R; ++r) x[r] = cmul(x[r], twb[(r - 1) * NS]);
+            } else {
+#pragma unroll
+                for (int r = 1; r < R; ++r) x[r] = cmul(x[r], w[i][NW > 1 ? r : 0]);
+            }
         }
         Dft<R>::run(x);
         int base = (j / NS) * NS * R + (j % NS);
