@@ -644,7 +644,8 @@ __host__ __device__ inline SppLds spp_lds(int box, int boy) {
     return s;
 }
 
-template <int FS, int L, int NIN, int NB>
+// NC: response pieces the accumulators hold (the plan's piece count rounded up to 2 or 4)
+template <int FS, int L, int NIN, int NB, int NC>
 __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdgpu_waves_per_eu(2))) void k_spp(
     ConvArgs A, int b0, int nbp, const int32_t* __restrict__ n_active,
     const float2* __restrict__ T, const float2* __restrict__ rhat,
@@ -730,11 +731,12 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         }
     };
 
-    float2 acc[NB][4][L];
+    static_assert(NC == 2 || NC == 4, "pieces");
+    float2 acc[NB][NC][L];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
             for (int m = 0; m < L; ++m) acc[b][c][m] = make_float2(0.f, 0.f);
     load_T(0);
@@ -815,8 +817,8 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 Dft<L>::run(s[b]);
             }
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (c < 3) load_w(w[(c + 1) & 1], min(c + 1, clast));
+            for (int c = 0; c < NC; ++c) {
+                if (c < NC - 1) load_w(w[(c + 1) & 1], min(c + 1, clast));
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
@@ -837,7 +839,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     float2* g2 = regA;                      // [NB][NF][boy qy][L n1][RS k2]
     float2* y2 = RS > 1 ? regB : regA;      // [NB][NF][box qx][YB qy]
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NC; ++c) {
         if (c >= A.nc) break;
         // y-inverse, L-point stage over k1 (conj(DFT(conj .)) = inverse DFT)
         if (active) {
@@ -1584,9 +1586,9 @@ tred_status launch_space(const ConvArgs& A0, int b0, int nb, const int32_t* na, 
     return tred_check_launch("tred_block_conv space");
 }
 
-template <int FS, int L, int NIN, int NB>
-tred_status launch_spp(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
-                       const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
+template <int FS, int L, int NIN, int NB, int NC>
+tred_status launch_spp_nc(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
+                          const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
     using S = SppShape<FS, L, NIN, NB>;
     const SppLds Ls = spp_lds<FS, L, NIN, NB, S::NF>(A.box, A.boy);
     const size_t lds = (size_t)Ls.total * sizeof(float2);
@@ -1595,12 +1597,18 @@ tred_status launch_spp(const ConvArgs& A, int b0, int nb, const int32_t* na, con
     if (tbytes > INT32_MAX)
         return tred_fail(TRED_EUNSUPPORTED, "spatial stage: %lld B of time spectra per workgroup",
                          (long long)tbytes);
-    allow_lds(k_spp<FS, L, NIN, NB>, lds);
-    hipLaunchKernelGGL((k_spp<FS, L, NIN, NB>), dim3((nb + NB - 1) / NB, A.ft / S::NF), dim3(S::NT),
+    allow_lds(k_spp<FS, L, NIN, NB, NC>, lds);
+    hipLaunchKernelGGL((k_spp<FS, L, NIN, NB, NC>), dim3((nb + NB - 1) / NB, A.ft / S::NF), dim3(S::NT),
                        lds, st, A, b0, nb, na, T, rhat, tws, U);
     return tred_check_launch("tred_block_conv space");
 }
 
+template <int FS, int L, int NIN, int NB>
+tred_status launch_spp(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* T,
+                       const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
+    return A.nc <= 2 ? launch_spp_nc<FS, L, NIN, NB, 2>(A, b0, nb, na, T, rhat, tws, U, st)
+                     : launch_spp_nc<FS, L, NIN, NB, 4>(A, b0, nb, na, T, rhat, tws, U, st);
+}
 template <int FS, int L, int NIN, int NB>
 tred_status launch_spp_adj(const ConvArgs& A, int b0, int nb, const int32_t* na, const float2* dU,
                            const float2* rhat, const float2* tws, float2* dT, hipStream_t st) {
