@@ -554,7 +554,7 @@ def main():
                      "conv_space_mac": float(conv_stages[:, 1].mean()),
                      "conv_time_inv": float(conv_stages[:, 2].mean())},
         "roofline": {
-            "kernel": ("k_spp<40,8,16,2,4>" if args.workload == "module" else "k_spp<8,8,8,1,2>") +
+            "kernel": ("k_spp<40,8,16,2,4>" if args.workload == "module" else "k_spp<8,8,4,1,2>") +
                       " (spatial transforms + spectral multiply-accumulate)",
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,

@@ -597,7 +597,9 @@ void k_sp(ConvArgs A, int b0, int nbp,
 // 48), using the prime-factor index maps (Pfa): each L-point sub-DFT gathers its
 // inputs with the RS-point phase factors W_RS^(n2 k2) only (RS - 1 distinct values
 // per thread, held in registers), and no twiddles sit between the stages. Inputs are
-// zero-padded to NIN = L or 2 L per axis, so every loop is unrolled without branches.
+// zero-padded to NIN = L / 2 (sizes 8 and 16), L or 2 L per axis, so every loop is
+// unrolled without branches; with NIN = L / 2 half of each sub-DFT's inputs are known
+// zeros and their arithmetic is folded away at compile time.
 // A workgroup holds NB bins at NF frequencies; thread (fl, kx, k2) owns spectrum
 // column kx, rows ky = k_of(k1, k2), of every bin, so each response-spectrum load
 // feeds NB multiply-accumulates. The time spectra of the next channel are loaded
@@ -1673,9 +1675,14 @@ tred_status launch_space_any(const tred_conv_plan* P, const ConvArgs& A, int b0,
     constexpr int NB8 = TRED_SPP_NB8;
     if (P->pfa) {
         const bool two = P->nin == 2 * P->ls;
+        const bool half = 2 * P->nin == P->ls;
         switch (P->fs) {
-            case 8: return launch_spp<8, 8, 8, 1>(A, b0, nb, na, T, rhat, tws, U, st);
-            case 16: return launch_spp<16, 16, 16, 1>(A, b0, nb, na, T, rhat, tws, U, st);
+            case 8:
+                return half ? launch_spp<8, 8, 4, 1>(A, b0, nb, na, T, rhat, tws, U, st)
+                            : launch_spp<8, 8, 8, 1>(A, b0, nb, na, T, rhat, tws, U, st);
+            case 16:
+                return half ? launch_spp<16, 16, 8, 1>(A, b0, nb, na, T, rhat, tws, U, st)
+                            : launch_spp<16, 16, 16, 1>(A, b0, nb, na, T, rhat, tws, U, st);
             case 24:
                 return two ? launch_spp<24, 8, 16, NB8>(A, b0, nb, na, T, rhat, tws, U, st)
                            : launch_spp<24, 8, 8, NB8>(A, b0, nb, na, T, rhat, tws, U, st);
@@ -1753,7 +1760,8 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     P->fs = fsx;
     P->ls = L;
     P->pfa = (fsx % 32) != 0;   // 8, 16, 24, 40, 48: fs / L is 1 or odd, coprime to L
-    P->nin = std::max(Bx, By) <= L ? L : 2 * L;
+    // inputs per axis of the prime-factor stage: L / 2 (sizes 8 and 16 only), L or 2 L
+    P->nin = (fsx <= 16 && std::max(Bx, By) <= L / 2) ? L / 2 : (std::max(Bx, By) <= L ? L : 2 * L);
     P->spp_nb = L == 8 ? TRED_SPP_NB8 : 1;
     P->ft = ft;
     P->ct = ft - Bt;

@@ -232,10 +232,16 @@ struct Pfa {
 };
 
 // t[n1] = sum over inputs n < NIN with n1(n) = n1 of x[n] W_RS^(n2(n) k2), where
-// w[j] = W_RS^(j k2) (w[0] = 1); NIN <= 2 L, every n1 receives an input n < L.
+// w[j] = W_RS^(j k2) (w[0] = 1). The inputs n < L meet distinct n1; with NIN < L the
+// classes that receive no input are zero (known to the compiler, so the DFT that
+// follows folds them away).
 template <int L, int RS, int NIN>
 __device__ __forceinline__ void pfa_gather(const float2* x, const float2* w, float2* t) {
     using P = Pfa<L, RS>;
+    if constexpr (NIN < L) {
+#pragma unroll
+        for (int a = 0; a < L; ++a) t[a] = make_float2(0.f, 0.f);
+    }
 #pragma unroll
     for (int n = 0; n < NIN; ++n) {
         const int a = P::n1(n), b = P::n2(n);
@@ -426,7 +432,7 @@ struct tred_conv_plan {
     int32_t fs;          // spatial FFT size (square)
     int32_t ls;          // length of the register sub-DFTs of the spatial transform
     int32_t pfa;         // spatial stage by prime-factor maps (fs = ls * RS, coprime)
-    int32_t nin;         // inputs per axis of the prime-factor stage (ls or 2 ls)
+    int32_t nin;         // inputs per axis of the prime-factor stage (ls / 2, ls or 2 ls)
     int32_t spp_nb;      // bins per workgroup of the prime-factor stage
     int32_t ft;          // time FFT size
     int32_t ct;          // response ticks per piece

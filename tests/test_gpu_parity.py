@@ -139,6 +139,11 @@ def test_footprints_bitexact_adversarial(T, orc):
                                 fft=(8, 8, 256), n=12, seed=6), True),
     ("sub4-even-plain", dict(npix=6, sub=4, nticks=256, blk=(3, 3, 64), kpix=(3, 3), kticks=64,
                              fft=(8, 8, 256), n=15, seed=7), False),
+    # blocks wider than half the spatial size: the stage takes all fs inputs per axis
+    ("fs8-full-input", dict(npix=10, blk=(5, 5, 64), kpix=(3, 3), kticks=100, fft=(8, 8, 256),
+                            n=15, seed=15), True),
+    ("fs16-full-input", dict(npix=20, blk=(10, 10, 64), kpix=(5, 5), kticks=120,
+                             fft=(16, 16, 256), n=15, seed=16), True),
 ])
 def test_small_paths_match_oracle(T, orc, name, kw, mpcp):
     say(f"test_small_paths_match_oracle[{name}]")
