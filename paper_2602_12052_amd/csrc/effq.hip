@@ -207,12 +207,16 @@ struct Idx3 {
 // One workgroup of NT threads per deposition (grid-stride over depositions). The
 // footprint is cut into tiles; for a tile of cells [X0, X1] x [Y0, Y1] x [Z0, Z1]
 // the node charges w * q of the cells one beyond the tile on every side (zero for
-// cells outside the quadrature window) are evaluated once into LDS, so that the
-// spread stencil of every output cell (the S = NGL + 2 (NGL / 2) nodes per axis of
-// cells g-1, g, g+1 that reach g) lies inside the tile and the 3-D gather is fully
-// unrolled. Along t (the axis consecutive lanes walk) the nodes are stored in planes
-// of equal local index, V[..][l][cell], so the lanes' stencil reads are unit-stride
-// (no LDS bank conflicts); along x and y they are interleaved, V[cell * NGL + l].
+// cells outside the quadrature window) are held in LDS, so that the spread stencil
+// of every output cell (the S = NGL + 2 (NGL / 2) nodes per axis of cells g-1, g, g+1
+// that reach g) lies inside the tile and the 3-D gather is fully unrolled. Tiles
+// follow each other along t; a ring of cell slots along t keeps the two cells that
+// consecutive tiles share, so every node is evaluated once per x-y column of tiles,
+// and only the cells inside the window are evaluated (the other slots are zeroed
+// once per column). Along t (the axis consecutive lanes walk) the nodes are stored
+// in planes of equal local index, V[..][l][slot], so the lanes' stencil reads are
+// unit-stride (no LDS bank conflicts); along x and y they are interleaved,
+// V[cell * NGL + l].
 template <int NGL, int CAP, int NT>
 __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                                              const float* __restrict__ seg,
@@ -224,7 +228,7 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
     constexpr int NPOS = NGL / 2;                 // nodes with xi > 0 in a cell
     constexpr int S = NGL + 2 * NPOS;             // stencil nodes per axis
     constexpr int NW = NT / kWave;
-    __shared__ float V[CAP];
+    __shared__ __align__(16) float V[CAP];
     __shared__ double red[NW];
     __shared__ float sxi[8], sw[8];
     const int tid = threadIdx.x;
@@ -315,73 +319,110 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
         const int64_t FY = Fs[1], FT = Fs[2];
         double nsum = 0.0;
 
+        // node charge w * q of node (lx, ly, lt) of cell (cx, cy, ct), inside the window
+        auto node_charge = [&](int cx, int lx, int cy, int ly, int ct, int lt) -> float {
+            float xx, xy, xt, wt;
+            if constexpr (NGL == 2) {
+                // nodes -+1/sqrt(3), weights 1
+                constexpr float xi2 = 0.57735026918962576f;
+                xx = lx ? xi2 : -xi2;
+                xy = ly ? xi2 : -xi2;
+                xt = lt ? xi2 : -xi2;
+                wt = 1.0f;
+            } else {
+                xx = sxi[lx];
+                xy = sxi[ly];
+                xt = sxi[lt];
+                wt = sw[lx] * sw[ly] * sw[lt];
+            }
+            const float rx = fb[0] + ((float)(cx - W.lo[0]) + 0.5f * xx) * fh[0];
+            const float ry = fb[1] + ((float)(cy - W.lo[1]) + 0.5f * xy) * fh[1];
+            const float rt = fb[2] + ((float)(ct - W.lo[2]) + 0.5f * xt) * fh[2];
+            float q;
+            if (point) {
+                const float e = rx * rx * isg2[0] + ry * ry * isg2[1] + rt * rt * isg2[2];
+                q = pref * exp_neg(-0.5f * e);
+            } else {
+                const float beta = rx * gvec[0] + ry * gvec[1] + rt * gvec[2];
+                const float sst = beta * inv_alpha;       // closest point on the line
+                const float px = rx - sst * fd[0], py = ry - sst * fd[1], pt = rt - sst * fd[2];
+                const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
+                q = pref * exp_neg(-0.5f * e) * erf_diff(kq * (1.0f - sst), -kq * sst);
+            }
+            return wt * jac * q;
+        };
+
+        // Along t a tile holds cells Z0-1 .. Z1+1 at slots 0 .. Z1-Z0+2 of a row of
+        // R = T[2] + 2; the two cells that consecutive tiles share are copied down from
+        // slots R-2, R-1 instead of evaluated again.
+        const int R = T[2] + 2;
         for (int X0 = F0[0]; X0 <= F1[0]; X0 += T[0])
-            for (int Y0 = F0[1]; Y0 <= F1[1]; Y0 += T[1])
+            for (int Y0 = F0[1]; Y0 <= F1[1]; Y0 += T[1]) {
+                const int X1 = min(X0 + T[0] - 1, F1[0]);
+                const int Y1 = min(Y0 + T[1] - 1, F1[1]);
+                const int nn0 = (X1 - X0 + 3) * NGL, nn1 = (Y1 - Y0 + 3) * NGL, nn2 = NGL * R;
+                const int sxs = nn1 * nn2;
+                // cells of the window among x in X0-1 .. X1+1, y in Y0-1 .. Y1+1; the node
+                // slots of the other cells stay zero
+                const int ex0 = max(X0 - 1, C0[0]), ex1 = min(X1 + 1, C1[0]);
+                const int ey0 = max(Y0 - 1, C0[1]), ey1 = min(Y1 + 1, C1[1]);
+                // cells whose nodes this column counts in the charge sum (x, y tiles share
+                // their edge cells; along t every cell is evaluated once)
+                const int ox0 = max(X0 == F0[0] ? X0 - 1 : X0, C0[0]);
+                const int ox1 = min(X1 == F1[0] ? X1 + 1 : X1, C1[0]);
+                const int oy0 = max(Y0 == F0[1] ? Y0 - 1 : Y0, C0[1]);
+                const int oy1 = min(Y1 == F1[1] ? Y1 + 1 : Y1, C1[1]);
+                {
+                    const int n4 = (nn0 * sxs + 3) / 4;   // <= CAP / 4
+                    float4* V4 = reinterpret_cast<float4*>(V);
+                    for (int i = tid; i < n4; i += NT) V4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                __syncthreads();
                 for (int Z0 = F0[2]; Z0 <= F1[2]; Z0 += T[2]) {
-                    const int X1 = min(X0 + T[0] - 1, F1[0]);
-                    const int Y1 = min(Y0 + T[1] - 1, F1[1]);
                     const int Z1 = min(Z0 + T[2] - 1, F1[2]);
-                    const int t0c[3] = {X0, Y0, Z0}, t1c[3] = {X1, Y1, Z1};
-                    int nn[3], own0[3], own1[3];
-                    const int nct = t1c[2] - t0c[2] + 3;          // padded cells along t
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        nn[a] = (t1c[a] - t0c[a] + 3) * NGL;   // cells t0c-1 .. t1c+1
-                        // cells whose nodes this tile counts in the charge sum
-                        own0[a] = max(t0c[a] == F0[a] ? t0c[a] - 1 : t0c[a], C0[a]);
-                        own1[a] = min(t1c[a] == F1[a] ? t1c[a] + 1 : t1c[a], C1[a]);
-                    }
-                    const int total = nn[0] * nn[1] * nn[2];
-                    // 1) node charges w * q(node) into LDS (zero outside the window)
-                    {
-                        Idx3 it;
-                        it.init(tid, NT, nn[1], nn[2]);
-                        for (int i = tid; i < total; i += NT, it.next()) {
-                            const int cx = X0 - 1 + it.i / NGL, lx = it.i % NGL;
-                            const int cy = Y0 - 1 + it.j / NGL, ly = it.j % NGL;
-                            int lt;
-                            if constexpr (NGL == 2) lt = it.k >= nct ? 1 : 0;
-                            else lt = it.k / nct;
-                            const int ct = Z0 - 1 + (it.k - lt * nct);
-                            const bool inside = cx >= C0[0] && cx <= C1[0] && cy >= C0[1] &&
-                                                cy <= C1[1] && ct >= C0[2] && ct <= C1[2];
-                            float vq = 0.0f;
-                            if (inside) {
-                                float xx, xy, xt, wt;
-                                if constexpr (NGL == 2) {
-                                    // nodes -+1/sqrt(3), weights 1
-                                    constexpr float xi2 = 0.57735026918962576f;
-                                    xx = lx ? xi2 : -xi2;
-                                    xy = ly ? xi2 : -xi2;
-                                    xt = lt ? xi2 : -xi2;
-                                    wt = 1.0f;
-                                } else {
-                                    xx = sxi[lx];
-                                    xy = sxi[ly];
-                                    xt = sxi[lt];
-                                    wt = sw[lx] * sw[ly] * sw[lt];
-                                }
-                                const float rx = fb[0] + ((float)(cx - W.lo[0]) + 0.5f * xx) * fh[0];
-                                const float ry = fb[1] + ((float)(cy - W.lo[1]) + 0.5f * xy) * fh[1];
-                                const float rt = fb[2] + ((float)(ct - W.lo[2]) + 0.5f * xt) * fh[2];
-                                float q;
-                                if (point) {
-                                    const float e = rx * rx * isg2[0] + ry * ry * isg2[1] + rt * rt * isg2[2];
-                                    q = pref * exp_neg(-0.5f * e);
-                                } else {
-                                    const float beta = rx * gvec[0] + ry * gvec[1] + rt * gvec[2];
-                                    const float sst = beta * inv_alpha;       // closest point on the line
-                                    const float px = rx - sst * fd[0], py = ry - sst * fd[1],
-                                                pt = rt - sst * fd[2];
-                                    const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
-                                    q = pref * exp_neg(-0.5f * e) * erf_diff(kq * (1.0f - sst), -kq * sst);
-                                }
-                                vq = wt * jac * q;
-                                if (cx >= own0[0] && cx <= own1[0] && cy >= own0[1] && cy <= own1[1] &&
-                                    ct >= own0[2] && ct <= own1[2])
-                                    nsum += (double)vq;
+                    const bool first = Z0 == F0[2];
+                    const bool xy = ex0 <= ex1 && ey0 <= ey1;
+                    const int mx = (ex1 - ex0 + 1) * NGL, my = (ey1 - ey0 + 1) * NGL;
+                    const int xo = (ex0 - X0 + 1) * NGL, yo = (ey0 - Y0 + 1) * NGL;
+                    if (!first) {
+                        // cells Z0-1, Z0 were the previous (full) tile's slots R-2, R-1
+                        if (xy) {
+                            const int rows = mx * my * NGL;
+                            for (int r = tid; r < rows; r += NT) {
+                                const int lt = r % NGL, q = r / NGL;
+                                const int j = q % my, i = q / my;
+                                float* row = V + (xo + i) * sxs + (yo + j) * nn2 + lt * R;
+                                const float v0 = row[R - 2], v1 = row[R - 1];
+                                row[0] = v0;
+                                row[1] = v1;
                             }
-                            V[i] = vq;
+                        }
+                        __syncthreads();
+                    }
+                    // 1) node charges of the cells new to the tile: Z0-1 .. Z1+1 for the
+                    //    first tile, Z0+1 .. Z1+1 after it (zero outside the window)
+                    const int cs = first ? Z0 - 1 : Z0 + 1;
+                    const int ntn = Z1 + 2 - cs;
+                    const int kb = cs - (Z0 - 1);   // slot of cell cs
+                    if (xy) {
+                        const int mt = ntn * NGL;
+                        const int total = mx * my * mt;
+                        Idx3 it;
+                        it.init(tid, NT, my, mt);
+                        for (int i = tid; i < total; i += NT, it.next()) {
+                            const int cx = ex0 + it.i / NGL, lx = it.i % NGL;
+                            const int cy = ey0 + it.j / NGL, ly = it.j % NGL;
+                            int lt;
+                            if constexpr (NGL == 2) lt = it.k >= ntn ? 1 : 0;
+                            else lt = it.k / ntn;
+                            const int d = it.k - lt * ntn;
+                            const int ct = cs + d;
+                            float vq = 0.0f;
+                            if (ct >= C0[2] && ct <= C1[2]) {
+                                vq = node_charge(cx, lx, cy, ly, ct, lt);
+                                if (cx >= ox0 && cx <= ox1 && cy >= oy0 && cy <= oy1) nsum += (double)vq;
+                            }
+                            V[(xo + it.i) * sxs + (yo + it.j) * nn2 + lt * R + kb + d] = vq;
                         }
                     }
                     __syncthreads();
@@ -389,7 +430,6 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                     {
                         const int nx = X1 - X0 + 1, ny = Y1 - Y0 + 1, nz = Z1 - Z0 + 1;
                         const int count = nx * ny * nz;
-                        const int sxs = nn[1] * nn[2], sys = nn[2];
                         // t stencil: nodes NGL-NPOS.. of cell g-1, all of g, ..NPOS-1 of g+1,
                         // at plane l, cell offset -1 / 0 / +1 from g
                         int offt[S];
@@ -397,22 +437,22 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                         for (int c = 0; c < S; ++c) {
                             const int l = c < NPOS ? NGL - NPOS + c : (c < NPOS + NGL ? c - NPOS : c - NPOS - NGL);
                             const int dc = c < NPOS ? -1 : (c < NPOS + NGL ? 0 : 1);
-                            offt[c] = l * nct + dc;
+                            offt[c] = l * R + dc;
                         }
                         Idx3 it;
                         it.init(tid, NT, ny, nz);
                         for (int k = tid; k < count; k += NT, it.next()) {
                             // first x/y stencil node of cell g: node NGL - NPOS of cell g - 1;
-                            // along t cell g sits at padded index it.k + 1
+                            // along t cell g sits at slot it.k + 1
                             const float* vb = V + (it.i * NGL + (NGL - NPOS)) * sxs +
-                                              (it.j * NGL + (NGL - NPOS)) * sys + it.k + 1;
+                                              (it.j * NGL + (NGL - NPOS)) * nn2 + it.k + 1;
                             float acc = 0.0f;
 #pragma unroll
                             for (int a = 0; a < S; ++a) {
                                 float ay = 0.0f;
 #pragma unroll
                                 for (int b = 0; b < S; ++b) {
-                                    const float* vr = vb + a * sxs + b * sys;
+                                    const float* vr = vb + a * sxs + b * nn2;
                                     float az = 0.0f;
 #pragma unroll
                                     for (int c = 0; c < S; ++c) az = fmaf(su[c], vr[offt[c]], az);
@@ -426,6 +466,7 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                     }
                     __syncthreads();
                 }
+            }
         if (charge_sum) {
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) nsum += __shfl_down(nsum, o, kWave);

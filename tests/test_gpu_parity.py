@@ -222,6 +222,46 @@ def test_block_values_match_oracle(T, orc):
     assert e < TOL
 
 
+@pytest.mark.parametrize("name,diff_T,n_gl,n", [
+    ("gl2-t-tiles", 8.8e-6, 2, 12),
+    ("gl2-xy-tiles", 1.0e-4, 2, 8),
+    ("gl3-xy-tiles", 1.0e-4, 3, 6),
+    ("gl1", 8.8e-6, 1, 12),
+    ("gl4", 8.8e-6, 4, 8),
+])
+def test_effq_tiles_match_oracle(T, orc, name, diff_T, n_gl, n):
+    """Patches and node-charge sum of footprints that span several tiles of the
+    effective-charge kernel along t (long drift, segments up to 2 mm) and, with wide
+    transverse diffusion, along x and y; 1 to 4 Gauss-Legendre points per axis."""
+    import torch
+    say(f"test_effq_tiles_match_oracle[{name}]")
+    npix = 24
+    g = W._grid(npix, 6250)
+    ph = W.Physics(diff_T=diff_T, n_gl=n_gl)
+    seg = W.gen_uniform_segments(n, (npix * W.PITCH, npix * W.PITCH), (30.0, 50.0),
+                                 length_range=(0.01, 0.2), seed=21)
+    ofp, ooff, _ = orc.footprints(g, ph, seg)
+    ext = ofp[:, 3:] - ofp[:, :3] + 1
+    assert ext[:, 2].min() > 30
+    if diff_T > 1e-5:
+        assert ext[:, :2].min() > 24
+    oval, ons = orc.effq(g, ph, seg, ofp, ooff)
+    sd = dev(seg)
+    fp = torch.empty((n, 6), dtype=torch.int32, device="cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    T.tred_effq_windows(g, ph, sd, fp, off)
+    val = torch.empty(int(ooff[-1]), dtype=torch.float32, device="cuda")
+    cs = torch.zeros(1, dtype=torch.float64, device="cuda")
+    T.tred_effq(g, ph, sd, fp, off, val, cs)
+    torch.cuda.synchronize()
+    assert np.array_equal(fp.cpu().numpy(), ofp)
+    assert np.array_equal(off.cpu().numpy(), ooff)
+    e = rel_l2(val.cpu().numpy(), oval)
+    say(f"  footprint cells {int(ooff[-1])}, rel-L2 patches {e:.2e}")
+    assert e < TOL
+    assert abs(float(cs.item()) - ons.sum()) < 1e-6 * abs(ons.sum())
+
+
 def test_empty_and_outside_events(T, orc):
     say("test_empty_and_outside_events")
     g, ph, blk, kpix, kticks, fft, seg = small_cfg()
