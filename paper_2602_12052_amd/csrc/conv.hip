@@ -52,7 +52,9 @@ struct ConvArgs {
     int32_t mpcp, chx, cap;
     int32_t e1, e2;      // row order of the response spectra: ky = (e1 m + e2 ry) mod fs
     int32_t rpair;       // response spectra stored as row pairs [m / 2][item][m % 2]
+    int32_t tskip;       // the spectra of groups flagged all-zero are not written
     int64_t vblk, vout;
+    uint8_t* tflag;      // [bin of the pass][nch][ppad / kTile]: 1 = spectra written
 };
 
 // ---------------------------------------------------------------------------
@@ -276,17 +278,36 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     // twiddle table in LDS after the FFT scratch / staging region
     float2* twl = (float2*)(lds + tf_lds_floats<FT>());
     fft_tw_fill<FT>(twl, tw, threadIdx.x, blockDim.x);
+    // per-wave "row pair not all zero", by iteration parity: a wave runs at most one
+    // iteration ahead of the others (one barrier per iteration)
+    __shared__ int wlive[2][8];
     int q = blockIdx.x;
     if (q < total) load(q);
     __syncthreads();
-    for (; q < total; q += gridDim.x) {
+    for (int it = 0; q < total; q += gridDim.x, ++it) {
         const TfGroup g = tf_group(A, q);
         float2 v[M];
+        bool nz = false;
 #pragma unroll
-        for (int m = 0; m < M; ++m) v[m] = m < MB ? make_float2(ra[m], rb[m]) : make_float2(0.f, 0.f);
+        for (int m = 0; m < M; ++m) {
+            v[m] = m < MB ? make_float2(ra[m], rb[m]) : make_float2(0.f, 0.f);
+            if (m < MB) nz = nz || ra[m] != 0.0f || rb[m] != 0.0f;
+        }
         if (q + (int)gridDim.x < total) load(q + gridDim.x);   // in flight during the FFT
-        wave_fft<FT, true, true>(v, lds + wv * kFftLds<FT>, twl, lane);
+        // the transform of zeros is zero: such a wave keeps v
+        const bool wlv = __builtin_amdgcn_ballot_w64(nz) != 0;
+        if (wlv) wave_fft<FT, true, true>(v, lds + wv * kFftLds<FT>, twl, lane);
+        if (lane == 0) wlive[it & 1][wv] = wlv;
         __syncthreads();   // the staging tile overlaps the other waves' FFT scratch
+        {
+            bool live = false;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) live = live || wlive[it & 1][w] != 0;
+            if (threadIdx.x == 0)
+                A.tflag[((int64_t)g.bl * A.nch + g.ch) * (A.ppad / kTile) + g.pt * (kTileT / kTile) + g.half] =
+                    live ? 1 : 0;
+            if (!live && A.tskip) continue;   // uniform over the workgroup; nothing was staged
+        }
         float2* stage = (float2*)lds;   // [f][kTile], columns swizzled
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -700,7 +721,10 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     // arithmetic that follows.
     // (byte offsets from channel ch of bin bl0; the host keeps NB channels' worth of
     // bins below 2^31 bytes)
-    uint32_t zoff[ZPT];
+    // Row groups of all-zero rows were flagged by the time FFT (tflag) and their spectra
+    // not written: the flag of each staged element's group is loaded with it.
+    const int ng = A.ppad / kTile;
+    uint32_t zoff[ZPT], zfo[ZPT];
     bool zval[ZPT];
 #pragma unroll
     for (int k = 0; k < ZPT; ++k) {
@@ -717,7 +741,12 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                                                 ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT +
                                                 p % kTileT
                                           : (int64_t)f0 * kTileT));
+        zfo[k] = zval[k] ? (uint32_t)(b * A.nch * ng + p / kTile) : 0u;
     }
+    // the flags of this workgroup's bins, [b][ch][group], staged in LDS once
+    uint8_t* zflag = reinterpret_cast<uint8_t*>(sm + Ls.total);
+    for (int i = tid; i < NB * A.nch * ng; i += NT)
+        zflag[i] = i < nbv * A.nch * ng ? A.tflag[(int64_t)bl0 * A.nch * ng + i] : 0;
     float2 zpre[ZPT];
     auto load_T = [&](int ch) {
         const auto tr = buf_rsrc(Tb + (int64_t)ch * tstride,
@@ -725,11 +754,12 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
 #pragma unroll
         for (int k = 0; k < ZPT; ++k) zpre[k] = buf_f2(tr, zoff[k], 0u);
     };
-    auto store_T = [&]() {
+    auto store_T = [&](int ch) {   // the spectra of channel ch, loaded by load_T(ch)
 #pragma unroll
         for (int k = 0; k < ZPT; ++k) {
             const int i = tid + k * NT;
-            if (i < NZ) zbuf[i] = zval[k] ? zpre[k] : make_float2(0.f, 0.f);
+            if (i < NZ)
+                zbuf[i] = (zval[k] && zflag[zfo[k] + ch * ng] != 0) ? zpre[k] : make_float2(0.f, 0.f);
         }
     };
 
@@ -746,7 +776,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     float2 wy[RS];   // W_RS^(j k2) of this thread's rows
 #pragma unroll
     for (int j = 0; j < RS; ++j) wy[j] = twl[((j * k2) % RS) * L];
-    store_T();
+    store_T(0);
     __syncthreads();
     const int64_t rstride = (int64_t)A.nc * L * TPF;   // nc * fs * fs values per (ch, f)
     // response spectra of (ch, f0 .. f0 + NF - 1) as row pairs [c][m / 2][item][m % 2]
@@ -830,7 +860,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
-        store_T();
+        store_T(min(ch + 1, A.nch - 1));
         __syncthreads();
     }
 
@@ -1510,6 +1540,8 @@ ConvArgs make_args(const tred_conv_plan* P) {
     }
     A.vblk = (int64_t)A.Bx * A.sx * A.NYf * A.Bt;
     A.vout = (int64_t)A.box * A.boy * A.bot;
+    A.tskip = 0;
+    A.tflag = nullptr;
     return A;
 }
 
@@ -1593,7 +1625,8 @@ tred_status launch_spp_nc(const ConvArgs& A, int b0, int nb, const int32_t* na, 
                           const float2* rhat, const float2* tws, float2* U, hipStream_t st) {
     using S = SppShape<FS, L, NIN, NB>;
     const SppLds Ls = spp_lds<FS, L, NIN, NB, S::NF>(A.box, A.boy);
-    const size_t lds = (size_t)Ls.total * sizeof(float2);
+    // + the row-group flags of NB bins
+    const size_t lds = (size_t)Ls.total * sizeof(float2) + ((size_t)NB * A.nch * (A.ppad / kTile) + 15) / 16 * 16;
     if (lds > 160 * 1024) return tred_fail(TRED_EUNSUPPORTED, "spatial stage needs %zu B of LDS", lds);
     const int64_t tbytes = (int64_t)NB * A.nch * (A.ppad / kTileT) * A.ft * kTileT * 8;
     if (tbytes > INT32_MAX)
@@ -1790,6 +1823,8 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     const int64_t scr = std::max(tbytes + ubytes, setup);
     P->off_scratch_u = o + tbytes;
     o += scr;
+    P->off_tflag = o;
+    o = align256(o + (int64_t)batch * P->nch * (ppad / kTile));
     P->ws_bytes = o;
     P->ws = nullptr;
     P->ready = 0;
@@ -1883,6 +1918,10 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
     const float2* rhat = (const float2*)(ws + P->off_rhat);
     float2* T = (float2*)(ws + P->off_scratch_t);
     float2* U = (float2*)(ws + P->off_scratch_u);
+    // the prime-factor spatial stage reads the group flags: groups of all-zero rows
+    // (most of a block-sparse event) skip their transform and spectra
+    A.tskip = P->pfa;
+    A.tflag = (uint8_t*)(ws + P->off_tflag);
     auto mark = [&](int b0, int k) {
         if (P->timing && b0 == 0) (void)hipEventRecord(P->ev[k], st);
     };

@@ -444,6 +444,7 @@ struct tred_conv_plan {
     int32_t qpad;        // output pixels per block padded to the tile of 8
     // workspace layout (byte offsets)
     int64_t off_tw_t, off_tw_s, off_rhat, off_chan, off_scratch_t, off_scratch_u;
+    int64_t off_tflag;   // liveness of the time-FFT row groups (one byte each)
     int64_t ws_bytes;
     void* ws;            // bound by set_response
     int ready;
