@@ -4,7 +4,8 @@ A step is one pass of the path over one synthetic module-scale event (1e5 line
 depositions from muon-like tracks and shower blobs in a 256 x 256-pixel region,
 21 x 21 x 2048 field response, 16 x 16-pixel x 512-tick bins):
 
-  tred_effq_windows -> tred_effq -> tred_block_bin -> tred_block_conv -> tred_scatter_waveforms
+  tred_effq_windows -> tred_effq -> tred_block_bin_rows -> tred_block_conv_rows ->
+  tred_scatter_waveforms
 
 Inputs (depositions, response spectra) are resident in HBM before the timed region;
 the convolution plan is built once, untimed. Prints one JSON line.
@@ -154,7 +155,7 @@ def bench_direct(args, split):
         val_cap, bcap, pix_cap = tred.size_event(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, sd)
         n = bcap if nbins is None else min(nbins, bcap)
         pl = tred.Pipeline(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, dresp,
-                           seg.shape[0], val_cap, bcap, pix_cap, cfg.fft, True, n)
+                           seg.shape[0], val_cap, bcap, pix_cap, cfg.fft, True, n, row_masks=False)
         pl.run(sd, stop_after="bin")
         nact = torch.tensor([n], dtype=torch.int32, device="cuda")
         blocks = pl.blocks[:n]
@@ -476,11 +477,11 @@ def main():
         tred.tred_effq(pl.grid, pl.phys, dev_seg, pl.fp, pl.off, pl.val, pl.charge_sum, stream)
         if record:
             ev.record(1, stream)
-        tred.tred_block_bin(pl.grid, pl.blocking, pl.fp, pl.off, pl.val, pl.keys, pl.n_active,
-                            pl.blocks, pl.bin_work, stream)
+        tred.tred_block_bin_rows(pl.grid, pl.blocking, pl.fp, pl.off, pl.val, pl.keys,
+                                 pl.n_active, pl.blocks, pl.rows, pl.bin_work, stream)
         if record:
             ev.record(2, stream)
-        tred.tred_block_conv(pl.plan, pl.n_active, pl.blocks, pl.out_blocks, stream)
+        tred.tred_block_conv_rows(pl.plan, pl.n_active, pl.blocks, pl.rows, pl.out_blocks, stream)
         if record:
             ev.record(3, stream)
         tred.tred_scatter_waveforms(pl.plan, pl.keys, pl.n_active, pl.out_blocks, pl.pix,

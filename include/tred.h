@@ -145,6 +145,22 @@ tred_status tred_block_bin(const tred_grid* grid, const tred_blocking* blocking,
                            int64_t val_cap, int32_t* keys, int32_t* n_active, float* blocks,
                            int32_t cap, void* work, void* stream);
 
+/* Block-sparse binning with row masks: as tred_block_bin, and additionally marks the
+ * rows of each active bin that can hold charge, so that only those are written. A
+ * row is the blk_ticks cells of one fine (x, y) cell of the bin, r = x * (blk_pix[1] *
+ * sub[1]) + y; it is marked when it meets some footprint box.
+ * rows [cap][tred_block_row_words()] out: bit (r % 32) of word r / 32 of bin s is set
+ *      for the marked rows of bin s (4-byte aligned).
+ * blocks: marked rows hold the binned charge; the other rows are NOT written (their
+ *      contents are whatever the buffer held) and are zero in the binned tensor. Pass
+ *      both to tred_block_conv_rows. */
+int32_t tred_block_row_words(const tred_grid* grid, const tred_blocking* blocking);
+tred_status tred_block_bin_rows(const tred_grid* grid, const tred_blocking* blocking,
+                                int64_t n_dep, const int32_t* fp, const int64_t* off,
+                                const float* val, int64_t val_cap, int32_t* keys,
+                                int32_t* n_active, float* blocks, uint32_t* rows, int32_t cap,
+                                void* work, void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Interlaced convolution with the field response (Sec. II-D, eq. interlaced),
  * evaluated per active bin by FFT with the channel sum in the frequency domain
@@ -201,6 +217,11 @@ tred_status tred_conv_plan_set_timing(tred_conv_plan* plan, void* const* events)
 /* out_blocks [cap][blk_pix[0]+kpix[0]-1][blk_pix[1]+kpix[1]-1][blk_ticks+kticks-1]. */
 tred_status tred_block_conv(const tred_conv_plan* plan, const int32_t* n_active, int32_t cap,
                             const float* blocks, float* out_blocks, void* stream);
+/* As tred_block_conv on blocks whose unmarked rows (rows from tred_block_bin_rows)
+ * are zero: only the marked rows of `blocks` are read. */
+tred_status tred_block_conv_rows(const tred_conv_plan* plan, const int32_t* n_active,
+                                 int32_t cap, const float* blocks, const uint32_t* rows,
+                                 float* out_blocks, void* stream);
 
 /* ------------------------------------------------------------------------- */
 /* Overlap-add onto unique electrodes (Sec. III-B): the waveform of every pixel in

@@ -124,6 +124,60 @@ __global__ __launch_bounds__(256) void k_zero_tail(float* __restrict__ blocks,
     if (i < n) blocks[i] = 0.f;
 }
 
+// Row masks: bit r of bin s (word s * nrw + r / 32) is set when row r = x * bf[1] + y
+// (the bf[2] ticks of fine cell (x, y) of the bin) meets a footprint box. One
+// workgroup per deposition; a task is one x column of one (bin y, bin t) pair, and
+// sets the bits of the column's y range word by word.
+__global__ __launch_bounds__(256) void k_mark_rows(BinGeom G, int64_t n, const int32_t* __restrict__ fp,
+                                                   const int64_t* __restrict__ ev_off,
+                                                   const int32_t* __restrict__ slot_all, int nrw,
+                                                   uint32_t* __restrict__ rows) {
+    for (int64_t d = blockIdx.x; d < n; d += gridDim.x) {
+        const int32_t* f = fp + 6 * d;
+        if (f[3] < f[0] || f[4] < f[1] || f[5] < f[2]) continue;
+        const int32_t* slot = slot_all + (int64_t)event_of(d, ev_off, G.nev) * G.nbins;
+        const int nx = f[3] - f[0] + 1;
+        const int by0 = f[1] / G.bf[1], nby = f[4] / G.bf[1] - by0 + 1;
+        const int bt0 = f[2] / G.bf[2], nbt = f[5] / G.bf[2] - bt0 + 1;
+        for (int i = threadIdx.x; i < nx * nby * nbt; i += blockDim.x) {
+            const int ix = i % nx, r = i / nx;
+            const int by = by0 + r % nby, bt = bt0 + r / nby;
+            const int gx = f[0] + ix, bx = gx / G.bf[0];
+            const int s = slot[((int64_t)bx * G.nb[1] + by) * G.nb[2] + bt];
+            if (s < 0) continue;
+            const int y0 = max(f[1], by * G.bf[1]) - by * G.bf[1];
+            const int y1 = min(f[4], by * G.bf[1] + G.bf[1] - 1) - by * G.bf[1];
+            const int r0 = (gx - bx * G.bf[0]) * G.bf[1] + y0, r1 = r0 + (y1 - y0);
+            uint32_t* w = rows + (int64_t)s * nrw;
+            for (int k = r0 >> 5; k <= r1 >> 5; ++k) {
+                const int lo = max(r0, k * 32) - k * 32, hi = min(r1, k * 32 + 31) - k * 32;
+                const uint32_t m = (hi - lo == 31) ? 0xffffffffu : (((1u << (hi - lo + 1)) - 1u) << lo);
+                atomicOr(w + k, m);
+            }
+        }
+    }
+}
+
+// zero the marked rows of the first min(n_active, cap) bins: one wave per mask word
+__global__ __launch_bounds__(256) void k_zero_rows(float* __restrict__ blocks,
+                                                   const uint32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ n_active, int32_t cap,
+                                                   int64_t vblk, int nrw, int bt) {
+    const int64_t na = min(*n_active, cap);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t w = (int64_t)blockIdx.x * 4 + wv; w < na * nrw; w += (int64_t)gridDim.x * 4) {
+        const int64_t s = w / nrw;
+        uint32_t bits = rows[w];
+        float* base = blocks + s * vblk + (w - s * nrw) * 32 * (int64_t)bt;
+        while (bits != 0u) {
+            const int b = __builtin_ctz(bits);
+            bits &= bits - 1u;
+            float* row = base + (int64_t)b * bt;
+            for (int k = lane; k < bt; k += kWave) row[k] = 0.0f;
+        }
+    }
+}
+
 // one workgroup per deposition: add its patch into the bins (FP32 atomics; the
 // reduction order over overlapping patches is unspecified)
 __global__ __launch_bounds__(256) void k_accum(BinGeom G, int64_t n, const int32_t* __restrict__ fp,
@@ -202,6 +256,9 @@ __global__ __launch_bounds__(256) void k_accum_adj(BinGeom G, int64_t n, const i
     }
 }
 
+// 32-bit words of the row mask of one bin (rows: bin cells along x and y)
+int row_words(const BinGeom& G) { return (int)(((int64_t)G.bf[0] * G.bf[1] + 31) / 32); }
+
 BinGeom geom(const tred_grid* g, const tred_blocking* b, int nev, int kst) {
     BinGeom G;
     G.bf[0] = b->blk_pix[0] * g->sub[0];
@@ -215,10 +272,12 @@ BinGeom geom(const tred_grid* g, const tred_blocking* b, int nev, int kst) {
     return G;
 }
 
+// rows NULL: every bin is zeroed whole; otherwise the row masks are written and only
+// the marked rows of each bin are zeroed (the other rows are left as they were)
 tred_status block_bin(const tred_grid* grid, const tred_blocking* blocking, int32_t n_ev,
                       const int64_t* ev_off, int64_t n_dep, const int32_t* fp, const int64_t* off,
                       const float* val, int64_t val_cap, int32_t* keys, int32_t* n_active,
-                      float* blocks, int32_t cap, void* work, void* stream) {
+                      float* blocks, uint32_t* rows, int32_t cap, void* work, void* stream) {
     TRED_TRY(validate_grid(grid));
     TRED_TRY(validate_blocking(blocking));
     TRED_REQUIRE(n_dep >= 0, "n_dep must be >= 0");
@@ -242,9 +301,21 @@ tred_status block_bin(const tred_grid* grid, const tred_blocking* blocking, int3
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, G, flag, keys, n_active, cap);
     TRED_TRY(tred_check_launch("tred_block_bin compact"));
     if (cap > 0) {
-        hipLaunchKernelGGL(k_zero_blocks, dim3(2048), dim3(256), 0, st, (float4*)blocks, n_active,
-                           cap, G.vblk);
-        hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(4), 0, st, blocks, n_active, cap, G.vblk);
+        if (rows) {
+            const int nrw = row_words(G);
+            const int64_t nw = (int64_t)cap * nrw;
+            hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((nw + 255) / 256, 4096)),
+                               dim3(256), 0, st, (int32_t*)rows, nw, 0);
+            if (n_dep > 0)
+                hipLaunchKernelGGL(k_mark_rows, dim3((unsigned)std::min<int64_t>(n_dep, 1 << 20)),
+                                   dim3(256), 0, st, G, n_dep, fp, ev_off, flag, nrw, rows);
+            hipLaunchKernelGGL(k_zero_rows, dim3(4096), dim3(256), 0, st, blocks, rows, n_active, cap,
+                               G.vblk, nrw, G.bf[2]);
+        } else {
+            hipLaunchKernelGGL(k_zero_blocks, dim3(2048), dim3(256), 0, st, (float4*)blocks, n_active,
+                               cap, G.vblk);
+            hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(4), 0, st, blocks, n_active, cap, G.vblk);
+        }
         if (n_dep > 0) {
             unsigned nb = (unsigned)std::min<int64_t>(n_dep, 1 << 20);
             hipLaunchKernelGGL(k_accum, dim3(nb), dim3(256), 0, st, G, n_dep, fp, off, val, val_cap,
@@ -274,7 +345,24 @@ extern "C" tred_status tred_block_bin(const tred_grid* grid, const tred_blocking
                                       int32_t* n_active,
                                       float* blocks, int32_t cap, void* work, void* stream) {
     return block_bin(grid, blocking, 1, nullptr, n_dep, fp, off, val, val_cap, keys, n_active,
-                     blocks, cap, work, stream);
+                     blocks, nullptr, cap, work, stream);
+}
+
+extern "C" int32_t tred_block_row_words(const tred_grid* grid, const tred_blocking* blocking) {
+    if (validate_grid(grid) != TRED_OK || validate_blocking(blocking) != TRED_OK) return -1;
+    const int64_t r = (int64_t)blocking->blk_pix[0] * grid->sub[0] * blocking->blk_pix[1] * grid->sub[1];
+    return r > (int64_t)INT32_MAX - 31 ? -1 : (int32_t)((r + 31) / 32);
+}
+
+extern "C" tred_status tred_block_bin_rows(const tred_grid* grid, const tred_blocking* blocking,
+                                           int64_t n_dep, const int32_t* fp, const int64_t* off,
+                                           const float* val, int64_t val_cap, int32_t* keys,
+                                           int32_t* n_active, float* blocks, uint32_t* rows,
+                                           int32_t cap, void* work, void* stream) {
+    TRED_REQUIRE(cap == 0 || rows, "rows is NULL");
+    TRED_REQUIRE(((uintptr_t)rows & 3) == 0, "rows must be 4-byte aligned");
+    return block_bin(grid, blocking, 1, nullptr, n_dep, fp, off, val, val_cap, keys, n_active,
+                     blocks, rows, cap, work, stream);
 }
 
 extern "C" tred_status tred_block_bin_adjoint(const tred_grid* grid, const tred_blocking* blocking,
@@ -321,5 +409,5 @@ extern "C" tred_status tred_block_bin_events(const tred_grid* grid, const tred_b
     TRED_REQUIRE(n_ev > 0, "n_ev must be > 0");
     TRED_REQUIRE(ev_off != nullptr, "ev_off is NULL");
     return block_bin(grid, blocking, n_ev, ev_off, n_dep, fp, off, val, val_cap, keys, n_active,
-                     blocks, cap, work, stream);
+                     blocks, nullptr, cap, work, stream);
 }

@@ -55,6 +55,8 @@ struct ConvArgs {
     int32_t tskip;       // the spectra of groups flagged all-zero are not written
     int64_t vblk, vout;
     uint8_t* tflag;      // [bin of the pass][nch][ppad / kTile]: 1 = spectra written
+    const uint32_t* rows;   // row masks of the bins (NULL: every row is read)
+    int32_t nrw;            // mask words per bin
 };
 
 // ---------------------------------------------------------------------------
@@ -261,18 +263,26 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
         const bool live = p < A.Bx * A.By;
         const auto br = buf_rsrc(blocks + (int64_t)(b0 + g.bl) * A.vblk, (uint32_t)(A.vblk * 4));
         const int px = live ? p / A.By : 0, py = live ? p % A.By : 0;
-        const uint32_t o0 = 4u * (uint32_t)(((px * A.sx + jx) * A.NYf + (py * A.sy + jy)) * A.Bt + lane);
+        const int r0 = (px * A.sx + jx) * A.NYf + (py * A.sy + jy);
         const int jbx = jb / A.sy, jby = jb % A.sy;
-        const uint32_t o1 = 4u * (uint32_t)((((A.Bx - 1 - px) * A.sx + jbx) * A.NYf +
-                                             ((A.By - 1 - py) * A.sy + jby)) * A.Bt + lane);
+        const int r1 = ((A.Bx - 1 - px) * A.sx + jbx) * A.NYf + ((A.By - 1 - py) * A.sy + jby);
+        // with row masks, unmarked rows are zero and not read
+        bool la = live, lb = live && pair;
+        if (A.rows) {
+            const uint32_t* rw = A.rows + (int64_t)(b0 + g.bl) * A.nrw;
+            la = la && ((rw[r0 >> 5] >> (r0 & 31)) & 1u);
+            lb = lb && ((rw[r1 >> 5] >> (r1 & 31)) & 1u);
+        }
+        const uint32_t o0 = 4u * (uint32_t)(r0 * A.Bt + lane);
+        const uint32_t o1 = 4u * (uint32_t)(r1 * A.Bt + lane);
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
-            ra[m] = (live && m < mb) ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                           br, o0, (uint32_t)(m * kWave * 4), 0))
-                                     : 0.0f;
-            rb[m] = (live && pair && m < mb) ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                   br, o1, (uint32_t)(m * kWave * 4), 0))
-                                             : 0.0f;
+            ra[m] = (la && m < mb) ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                         br, o0, (uint32_t)(m * kWave * 4), 0))
+                                   : 0.0f;
+            rb[m] = (lb && m < mb) ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                         br, o1, (uint32_t)(m * kWave * 4), 0))
+                                   : 0.0f;
         }
     };
     // twiddle table in LDS after the FFT scratch / staging region
@@ -1542,6 +1552,8 @@ ConvArgs make_args(const tred_conv_plan* P) {
     A.vout = (int64_t)A.box * A.boy * A.bot;
     A.tskip = 0;
     A.tflag = nullptr;
+    A.rows = nullptr;
+    A.nrw = (int32_t)(((int64_t)A.Bx * A.sx * A.NYf + 31) / 32);
     return A;
 }
 
@@ -1899,9 +1911,9 @@ extern "C" tred_status tred_conv_plan_set_response(tred_conv_plan* P, const floa
     return TRED_OK;
 }
 
-extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n_active,
-                                       int32_t cap, const float* blocks, float* out_blocks,
-                                       void* stream) {
+namespace {
+tred_status block_conv(const tred_conv_plan* P, const int32_t* n_active, int32_t cap,
+                       const float* blocks, const uint32_t* rows, float* out_blocks, void* stream) {
     TRED_REQUIRE(P && n_active, "plan/n_active is NULL");
     TRED_REQUIRE(P->ready, "plan has no response (call tred_conv_plan_set_response)");
     TRED_REQUIRE(cap >= 0, "cap must be >= 0");
@@ -1922,6 +1934,7 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
     // (most of a block-sparse event) skip their transform and spectra
     A.tskip = P->pfa;
     A.tflag = (uint8_t*)(ws + P->off_tflag);
+    A.rows = rows;
     auto mark = [&](int b0, int k) {
         if (P->timing && b0 == 0) (void)hipEventRecord(P->ev[k], st);
     };
@@ -1943,6 +1956,21 @@ extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n
         mark(b0, 5);
     }
     return TRED_OK;
+}
+}  // namespace
+
+extern "C" tred_status tred_block_conv(const tred_conv_plan* P, const int32_t* n_active,
+                                       int32_t cap, const float* blocks, float* out_blocks,
+                                       void* stream) {
+    return block_conv(P, n_active, cap, blocks, nullptr, out_blocks, stream);
+}
+
+extern "C" tred_status tred_block_conv_rows(const tred_conv_plan* P, const int32_t* n_active,
+                                            int32_t cap, const float* blocks, const uint32_t* rows,
+                                            float* out_blocks, void* stream) {
+    TRED_REQUIRE(cap == 0 || rows, "rows is NULL");
+    TRED_REQUIRE(((uintptr_t)rows & 3) == 0, "rows must be 4-byte aligned");
+    return block_conv(P, n_active, cap, blocks, rows, out_blocks, stream);
 }
 
 extern "C" tred_status tred_block_conv_adjoint(const tred_conv_plan* P, const int32_t* n_active,

@@ -72,7 +72,7 @@ EXPORTS = [
     "tred_direct_plan_destroy", "tred_block_bin_events_workspace", "tred_block_bin_events",
     "tred_scatter_events_workspace", "tred_scatter_waveforms_events",
     "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint", "tred_block_bin_adjoint",
-    "tred_effq_adjoint",
+    "tred_effq_adjoint", "tred_block_row_words", "tred_block_bin_rows", "tred_block_conv_rows",
 ]
 
 _lib = None
@@ -125,6 +125,10 @@ def lib():
     L.tred_block_conv_adjoint.argtypes = [P, P, I32, P, P, P]
     L.tred_block_bin_adjoint.argtypes = [P, P, I64, P, P, I64, P, P, P, I32, P, P, P]
     L.tred_effq_adjoint.argtypes = [P, P, I64, P, P, P, P, I64, P, P, P]
+    L.tred_block_row_words.argtypes = [P, P]
+    L.tred_block_row_words.restype = I32
+    L.tred_block_bin_rows.argtypes = [P, P, I64, P, P, P, I64, P, P, P, P, I32, P, P]
+    L.tred_block_conv_rows.argtypes = [P, P, I32, P, P, P, P]
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
                  "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
@@ -132,7 +136,8 @@ def lib():
                  "tred_direct_plan_set_response", "tred_block_conv_direct",
                  "tred_block_bin_events", "tred_scatter_waveforms_events",
                  "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint",
-                 "tred_block_bin_adjoint", "tred_effq_adjoint"):
+                 "tred_block_bin_adjoint", "tred_effq_adjoint", "tred_block_bin_rows",
+                 "tred_block_conv_rows"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -302,6 +307,40 @@ def tred_block_conv(plan: ConvPlan, n_active, blocks, out_blocks, stream=None):
                                  _stream(stream)))
 
 
+def tred_block_row_words(grid, blocking) -> int:
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    return int(lib().tred_block_row_words(C.byref(g), C.byref(b)))
+
+
+def tred_block_bin_rows(grid, blocking, fp, off, val, keys, n_active, blocks, rows, work,
+                        stream=None):
+    """As tred_block_bin, writing only the rows marked in `rows` [cap][row words] (int32
+    tensor viewed as 32-bit masks)."""
+    import torch
+    _dt(keys, torch.int32, "keys"), _dt(n_active, torch.int32, "n_active")
+    _dt(blocks, torch.float32, "blocks"), _dt(rows, torch.int32, "rows")
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    n = fp.shape[0]
+    cap = keys.shape[0]
+    if blocks.shape[0] < cap or rows.shape[0] < cap:
+        raise ValueError("blocks/rows have fewer rows than keys")
+    if rows.shape[1] != tred_block_row_words(grid, blocking):
+        raise ValueError("rows must have tred_block_row_words() columns")
+    _check(lib().tred_block_bin_rows(C.byref(g), C.byref(b), n, _ptr(fp), _ptr(off), _ptr(val),
+                                     val.numel(), _ptr(keys), _ptr(n_active), _ptr(blocks),
+                                     _ptr(rows), cap, _ptr(work), _stream(stream)))
+
+
+def tred_block_conv_rows(plan: ConvPlan, n_active, blocks, rows, out_blocks, stream=None):
+    import torch
+    _dt(out_blocks, torch.float32, "out_blocks"), _dt(rows, torch.int32, "rows")
+    cap = blocks.shape[0]
+    if out_blocks.shape[0] < cap or rows.shape[0] < cap:
+        raise ValueError("out_blocks/rows have fewer rows than blocks")
+    _check(lib().tred_block_conv_rows(plan.handle, _ptr(n_active), cap, _ptr(blocks), _ptr(rows),
+                                      _ptr(out_blocks), _stream(stream)))
+
+
 class DirectPlan:
     """Owner of a tred_direct_plan (block-direct convolution on BF16 matrix cores)
     and its device workspace."""
@@ -435,7 +474,9 @@ class Pipeline:
     host synchronisation (capacities fixed at construction)."""
 
     def __init__(self, grid, phys, blocking, kpix, kticks, resp, n_dep, val_cap, block_cap,
-                 pix_cap, fft=None, mpcp=True, batch=64):
+                 pix_cap, fft=None, mpcp=True, batch=64, row_masks=True):
+        """row_masks: bin with row masks (only the rows a footprint reaches are written
+        and transformed); False leaves every row of `blocks` defined (dense blocks)."""
         import torch
         dev = "cuda"
         self.grid, self.phys, self.blocking = grid_struct(grid), physics_struct(phys), \
@@ -452,6 +493,8 @@ class Pipeline:
         g, b = self.grid, self.blocking
         vblk = b.blk_pix[0] * g.sub[0] * b.blk_pix[1] * g.sub[1] * b.blk_ticks
         self.blocks = torch.empty((int(block_cap), vblk), dtype=torch.float32, device=dev)
+        self.rows = torch.empty((int(block_cap), tred_block_row_words(g, b)), dtype=torch.int32,
+                                device=dev) if row_masks else None
         o = self.plan.out_shape
         self.out_blocks = torch.empty((int(block_cap), o[0] * o[1] * o[2]), dtype=torch.float32,
                                       device=dev)
@@ -470,13 +513,27 @@ class Pipeline:
         tred_effq(self.grid, self.phys, seg, self.fp, self.off, self.val, self.charge_sum, stream)
         if stop_after == "effq":
             return
-        tred_block_bin(self.grid, self.blocking, self.fp, self.off, self.val, self.keys,
-                       self.n_active, self.blocks, self.bin_work, stream)
+        self.bin(stream)
         if stop_after == "bin":
             return
-        tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
+        self.conv(stream)
         tred_scatter_waveforms(self.plan, self.keys, self.n_active, self.out_blocks, self.pix,
                                self.n_pix, self.wf, self.scat_work, stream)
+
+    def bin(self, stream=None):
+        if self.rows is not None:
+            tred_block_bin_rows(self.grid, self.blocking, self.fp, self.off, self.val, self.keys,
+                                self.n_active, self.blocks, self.rows, self.bin_work, stream)
+        else:
+            tred_block_bin(self.grid, self.blocking, self.fp, self.off, self.val, self.keys,
+                           self.n_active, self.blocks, self.bin_work, stream)
+
+    def conv(self, stream=None):
+        if self.rows is not None:
+            tred_block_conv_rows(self.plan, self.n_active, self.blocks, self.rows, self.out_blocks,
+                                 stream)
+        else:
+            tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
 
     def backward(self, seg, d_wf, stream=None):
         """Gradients of a loss L with respect to the depositions and the transport

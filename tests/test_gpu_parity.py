@@ -262,6 +262,61 @@ def test_effq_tiles_match_oracle(T, orc, name, diff_T, n_gl, n):
     assert abs(float(cs.item()) - ons.sum()) < 1e-6 * abs(ons.sum())
 
 
+@pytest.mark.parametrize("name,kw,mpcp", [
+    ("odd-sub", dict(), True),
+    ("fs16", dict(npix=8, blk=(4, 4, 64), kpix=(9, 9), kticks=120, fft=(16, 16, 256), seed=3), True),
+    ("fs40-plain", dict(npix=32, nticks=1100, blk=(16, 16, 512), kpix=(21, 21), kticks=600,
+                        fft=(40, 40, 1024), n=20, seed=12), False),
+])
+def test_row_masks_match_dense(T, orc, name, kw, mpcp):
+    """Binning with row masks marks every row that holds charge, writes those rows as the
+    dense binning does, and leaves the others untouched (here NaN); the convolution of
+    the masked blocks never reads an unmarked row and equals the dense convolution."""
+    import torch
+    say(f"test_row_masks_match_dense[{name}]")
+    g, ph, blk, kpix, kticks, fft, seg = small_cfg(**kw)
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=11)
+    sd = dev(seg)
+    val_cap, bcap, pix_cap = T.size_event(g, ph, blk, kpix, sd)
+    pl = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap, bcap, pix_cap, fft,
+                    mpcp, 3, row_masks=False)
+    pl.run(sd, stop_after="effq")
+    n = seg.shape[0]
+    keys_d = torch.empty_like(pl.keys)
+    na_d = torch.zeros(1, dtype=torch.int32, device="cuda")
+    blocks_d = torch.empty_like(pl.blocks)
+    T.tred_block_bin(g, blk, pl.fp, pl.off, pl.val, keys_d, na_d, blocks_d, pl.bin_work)
+    out_d = torch.empty_like(pl.out_blocks)
+    T.tred_block_conv(pl.plan, na_d, blocks_d, out_d)
+    nrw = T.tred_block_row_words(g, blk)
+    keys_r = torch.empty_like(pl.keys)
+    na_r = torch.zeros(1, dtype=torch.int32, device="cuda")
+    blocks_r = torch.full_like(pl.blocks, float("nan"))
+    rows = torch.full((bcap, nrw), -1, dtype=torch.int32, device="cuda")
+    T.tred_block_bin_rows(g, blk, pl.fp, pl.off, pl.val, keys_r, na_r, blocks_r, rows, pl.bin_work)
+    out_r = torch.full_like(pl.out_blocks, float("nan"))
+    T.tred_block_conv_rows(pl.plan, na_r, blocks_r, rows, out_r)
+    torch.cuda.synchronize()
+    na = int(na_d.item())
+    assert na == int(na_r.item()) and na > 0
+    assert torch.equal(keys_d[:na], keys_r[:na])
+    nrow = blk.blk_pix[0] * g.sub[0] * blk.blk_pix[1] * g.sub[1]
+    bits = rows[:na].cpu().numpy().view(np.uint32)
+    marked = ((bits[:, np.arange(nrow) // 32] >> (np.arange(nrow) % 32).astype(np.uint32)) & 1) != 0
+    bd = blocks_d[:na].cpu().numpy().reshape(na, nrow, blk.blk_ticks)
+    br = blocks_r[:na].cpu().numpy().reshape(na, nrow, blk.blk_ticks)
+    assert not np.any(bd[~marked])                       # charge only in marked rows
+    assert np.all(np.isnan(br[~marked]))                 # unmarked rows not written
+    assert np.all(np.isfinite(br[marked]))
+    e_b = rel_l2(br[marked], bd[marked])
+    od = out_d[:na].cpu().numpy()
+    orr = out_r[:na].cpu().numpy()
+    assert np.all(np.isfinite(orr))
+    e_o = rel_l2(orr, od)
+    say(f"  marked rows {marked.mean():.3f}, rel-L2 blocks {e_b:.2e}, outputs {e_o:.2e}")
+    assert e_b < 1e-6 and e_o < 1e-6
+
+
 def test_empty_and_outside_events(T, orc):
     say("test_empty_and_outside_events")
     g, ph, blk, kpix, kticks, fft, seg = small_cfg()

@@ -63,7 +63,7 @@ def direct_path(T, g, ph, blk, kpix, kticks, seg, resp, split, batch=16):
     val_cap, bcap, pix_cap = T.size_event(g, ph, blk, kpix, sd)
     # the FFT pipeline's buffers and plan give effq, binning and the scatter geometry
     pl = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap, bcap, pix_cap,
-                    None, False, 4)
+                    None, False, 4, row_masks=False)
     pl.run(sd, stop_after="bin")
     dp = T.DirectPlan(g, blk, kpix, kticks, split=split, batch=batch)
     dp.set_response(dev(resp))
@@ -130,7 +130,7 @@ def test_direct_module_sampled_bins(T, orc):
     sd = dev(seg)
     val_cap, bcap, pix_cap = T.size_event(g, ph, blk, cfg.kpix, sd)
     pl = T.Pipeline(g, ph, blk, cfg.kpix, cfg.kticks, dev(resp), seg.shape[0], val_cap, bcap,
-                    pix_cap, cfg.fft, True, 8)
+                    pix_cap, cfg.fft, True, 8, row_masks=False)
     pl.run(sd, stop_after="bin")
     torch.cuda.synchronize()
     na = int(pl.n_active.item())
