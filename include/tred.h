@@ -258,6 +258,14 @@ tred_status tred_block_bin_events(const tred_grid* grid, const tred_blocking* bl
                                   const int32_t* fp, const int64_t* off, const float* val,
                                   int64_t val_cap, int32_t* keys, int32_t* n_active, float* blocks,
                                   int32_t cap, void* work, void* stream);
+/* As tred_block_bin_events with the row masks of tred_block_bin_rows (rows
+ * [cap][tred_block_row_words()]); convolve with tred_block_conv_rows. */
+tred_status tred_block_bin_events_rows(const tred_grid* grid, const tred_blocking* blocking,
+                                       int32_t n_ev, const int64_t* ev_off, int64_t n_dep,
+                                       const int32_t* fp, const int64_t* off, const float* val,
+                                       int64_t val_cap, int32_t* keys, int32_t* n_active,
+                                       float* blocks, uint32_t* rows, int32_t cap, void* work,
+                                       void* stream);
 int64_t tred_scatter_events_workspace(const tred_conv_plan* plan, int32_t n_ev);
 tred_status tred_scatter_waveforms_events(const tred_conv_plan* plan, int32_t n_ev,
                                           const int32_t* keys, const int32_t* n_active,

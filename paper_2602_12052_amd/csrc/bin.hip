@@ -411,3 +411,18 @@ extern "C" tred_status tred_block_bin_events(const tred_grid* grid, const tred_b
     return block_bin(grid, blocking, n_ev, ev_off, n_dep, fp, off, val, val_cap, keys, n_active,
                      blocks, nullptr, cap, work, stream);
 }
+
+extern "C" tred_status tred_block_bin_events_rows(const tred_grid* grid,
+                                                  const tred_blocking* blocking, int32_t n_ev,
+                                                  const int64_t* ev_off, int64_t n_dep,
+                                                  const int32_t* fp, const int64_t* off,
+                                                  const float* val, int64_t val_cap, int32_t* keys,
+                                                  int32_t* n_active, float* blocks, uint32_t* rows,
+                                                  int32_t cap, void* work, void* stream) {
+    TRED_REQUIRE(n_ev > 0, "n_ev must be > 0");
+    TRED_REQUIRE(ev_off != nullptr, "ev_off is NULL");
+    TRED_REQUIRE(cap == 0 || rows, "rows is NULL");
+    TRED_REQUIRE(((uintptr_t)rows & 3) == 0, "rows must be 4-byte aligned");
+    return block_bin(grid, blocking, n_ev, ev_off, n_dep, fp, off, val, val_cap, keys, n_active,
+                     blocks, rows, cap, work, stream);
+}

@@ -73,6 +73,7 @@ EXPORTS = [
     "tred_scatter_events_workspace", "tred_scatter_waveforms_events",
     "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint", "tred_block_bin_adjoint",
     "tred_effq_adjoint", "tred_block_row_words", "tred_block_bin_rows", "tred_block_conv_rows",
+    "tred_block_bin_events_rows",
 ]
 
 _lib = None
@@ -129,6 +130,8 @@ def lib():
     L.tred_block_row_words.restype = I32
     L.tred_block_bin_rows.argtypes = [P, P, I64, P, P, P, I64, P, P, P, P, I32, P, P]
     L.tred_block_conv_rows.argtypes = [P, P, I32, P, P, P, P]
+    L.tred_block_bin_events_rows.argtypes = [P, P, I32, P, I64, P, P, P, I64, P, P, P, P, I32,
+                                             P, P]
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
                  "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
@@ -137,7 +140,7 @@ def lib():
                  "tred_block_bin_events", "tred_scatter_waveforms_events",
                  "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint",
                  "tred_block_bin_adjoint", "tred_effq_adjoint", "tred_block_bin_rows",
-                 "tred_block_conv_rows"):
+                 "tred_block_conv_rows", "tred_block_bin_events_rows"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -573,6 +576,28 @@ class Pipeline:
                     wf=self.wf[:min(npx, self.pix.shape[0])].cpu().numpy())
 
 
+def tred_block_bin_events_rows(grid, blocking, ev_off, fp, off, val, keys, n_active, blocks, rows,
+                               work, stream=None):
+    """tred_block_bin_events with row masks `rows` [cap][row words] (int32 tensor)."""
+    import torch
+    _dt(ev_off, torch.int64, "ev_off"), _dt(keys, torch.int32, "keys")
+    _dt(n_active, torch.int32, "n_active"), _dt(blocks, torch.float32, "blocks")
+    _dt(rows, torch.int32, "rows")
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    n = fp.shape[0]
+    cap = keys.shape[0]
+    if keys.shape[1] != 4:
+        raise ValueError("keys must be [cap][4]")
+    if blocks.shape[0] < cap or rows.shape[0] < cap:
+        raise ValueError("blocks/rows have fewer rows than keys")
+    if rows.shape[1] != tred_block_row_words(grid, blocking):
+        raise ValueError("rows must have tred_block_row_words() columns")
+    _check(lib().tred_block_bin_events_rows(C.byref(g), C.byref(b), ev_off.numel() - 1,
+                                            _ptr(ev_off), n, _ptr(fp), _ptr(off), _ptr(val),
+                                            val.numel(), _ptr(keys), _ptr(n_active), _ptr(blocks),
+                                            _ptr(rows), cap, _ptr(work), _stream(stream)))
+
+
 class BatchPipeline:
     """Buffers and plan for batches of events sharing one grid and response. A batch
     is a concatenation of depositions with device offsets ev_off (event e owns rows
@@ -583,7 +608,7 @@ class BatchPipeline:
     capture it in a HIP graph per batch shape)."""
 
     def __init__(self, grid, phys, blocking, kpix, kticks, resp, n_ev_max, n_dep_max, val_cap,
-                 block_cap, pix_cap, fft=None, mpcp=True, batch=64, plan=None):
+                 block_cap, pix_cap, fft=None, mpcp=True, batch=64, plan=None, row_masks=True):
         import torch
         dev = "cuda"
         self.grid, self.phys, self.blocking = grid_struct(grid), physics_struct(phys), \
@@ -602,6 +627,8 @@ class BatchPipeline:
         self.n_active = torch.zeros(1, dtype=torch.int32, device=dev)
         vblk = b.blk_pix[0] * g.sub[0] * b.blk_pix[1] * g.sub[1] * b.blk_ticks
         self.blocks = torch.empty((int(block_cap), vblk), dtype=torch.float32, device=dev)
+        self.rows = torch.empty((int(block_cap), tred_block_row_words(g, b)), dtype=torch.int32,
+                                device=dev) if row_masks else None
         o = self.plan.out_shape
         self.out_blocks = torch.empty((int(block_cap), o[0] * o[1] * o[2]), dtype=torch.float32,
                                       device=dev)
@@ -624,9 +651,16 @@ class BatchPipeline:
         tred_effq_windows(self.grid, self.phys, seg, fp, off, stream)
         self.charge_sum.zero_()
         tred_effq(self.grid, self.phys, seg, fp, off, self.val, self.charge_sum, stream)
-        tred_block_bin_events(self.grid, self.blocking, ev_off, fp, off, self.val, self.keys,
-                              self.n_active, self.blocks, self.bin_work, stream)
-        tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
+        if self.rows is not None:
+            tred_block_bin_events_rows(self.grid, self.blocking, ev_off, fp, off, self.val,
+                                       self.keys, self.n_active, self.blocks, self.rows,
+                                       self.bin_work, stream)
+            tred_block_conv_rows(self.plan, self.n_active, self.blocks, self.rows, self.out_blocks,
+                                 stream)
+        else:
+            tred_block_bin_events(self.grid, self.blocking, ev_off, fp, off, self.val, self.keys,
+                                  self.n_active, self.blocks, self.bin_work, stream)
+            tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
         tred_scatter_waveforms_events(self.plan, n_ev, self.keys, self.n_active, self.out_blocks,
                                       self.pix, self.n_pix, self.wf, self.scat_work, stream)
 
