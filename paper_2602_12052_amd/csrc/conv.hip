@@ -726,13 +726,13 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     const float2* Tb = T + (int64_t)bl0 * A.nch * tstride;
     // Staged time spectra of one channel: element i of zbuf (py fastest, then px, fl,
     // bin) comes from T at a fixed per-thread offset plus the channel stride. The
-    // loads are unconditional (elements outside the bin read a valid element of bin 0
-    // and are masked when stored), so that no wait for them is forced before the
-    // arithmetic that follows.
+    // loads are unconditional, so that no wait for them is forced before the
+    // arithmetic that follows: elements outside the bins and elements of row groups
+    // that the time FFT flagged empty (their spectra were not written) take an offset
+    // past the end of the buffer resource, which reads zero without touching memory.
     // (byte offsets from channel ch of bin bl0; the host keeps NB channels' worth of
     // bins below 2^31 bytes)
-    // Row groups of all-zero rows were flagged by the time FFT (tflag) and their spectra
-    // not written: the flag of each staged element's group is loaded with it.
+    constexpr uint32_t kOob = 0xfffffff0u;
     const int ng = A.ppad / kTile;
     uint32_t zoff[ZPT], zfo[ZPT];
     bool zval[ZPT];
@@ -757,19 +757,27 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     uint8_t* zflag = reinterpret_cast<uint8_t*>(sm + Ls.total);
     for (int i = tid; i < NB * A.nch * ng; i += NT)
         zflag[i] = i < nbv * A.nch * ng ? A.tflag[(int64_t)bl0 * A.nch * ng + i] : 0;
+    __syncthreads();
+    // the flag bytes of channel ch's elements, read one channel ahead of their loads
+    // (unconditional LDS reads: the element's own group, or group 0 of bin 0)
+    uint32_t zfb[ZPT];
+    auto flags = [&](int ch) {
+#pragma unroll
+        for (int k = 0; k < ZPT; ++k) zfb[k] = zflag[zfo[k] + ch * ng];
+    };
     float2 zpre[ZPT];
-    auto load_T = [&](int ch) {
+    auto load_T = [&](int ch) {   // with zfb read for channel ch
         const auto tr = buf_rsrc(Tb + (int64_t)ch * tstride,
                                  (uint32_t)(((int64_t)nbv * A.nch - ch) * tstride * 8));
 #pragma unroll
-        for (int k = 0; k < ZPT; ++k) zpre[k] = buf_f2(tr, zoff[k], 0u);
+        for (int k = 0; k < ZPT; ++k)
+            zpre[k] = buf_f2(tr, (zval[k] & (zfb[k] != 0u)) ? zoff[k] : kOob, 0u);
     };
-    auto store_T = [&](int ch) {   // the spectra of channel ch, loaded by load_T(ch)
+    auto store_T = [&]() {
 #pragma unroll
         for (int k = 0; k < ZPT; ++k) {
             const int i = tid + k * NT;
-            if (i < NZ)
-                zbuf[i] = (zval[k] && zflag[zfo[k] + ch * ng] != 0) ? zpre[k] : make_float2(0.f, 0.f);
+            if (i < NZ) zbuf[i] = zpre[k];
         }
     };
 
@@ -781,12 +789,13 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         for (int c = 0; c < NC; ++c)
 #pragma unroll
             for (int m = 0; m < L; ++m) acc[b][c][m] = make_float2(0.f, 0.f);
+    flags(0);
     load_T(0);
-    __syncthreads();
+    flags(min(1, A.nch - 1));
     float2 wy[RS];   // W_RS^(j k2) of this thread's rows
 #pragma unroll
     for (int j = 0; j < RS; ++j) wy[j] = twl[((j * k2) % RS) * L];
-    store_T(0);
+    store_T();
     __syncthreads();
     const int64_t rstride = (int64_t)A.nc * L * TPF;   // nc * fs * fs values per (ch, f)
     // response spectra of (ch, f0 .. f0 + NF - 1) as row pairs [c][m / 2][item][m % 2]
@@ -843,6 +852,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         __builtin_amdgcn_sched_barrier(0);   // vector loads complete in issue order
         load_T(min(ch + 1, A.nch - 1));
         __builtin_amdgcn_sched_barrier(0);
+        flags(min(ch + 2, A.nch - 1));
         if (active) {
             float2 s[NB][L];
 #pragma unroll
@@ -870,7 +880,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
-        store_T(min(ch + 1, A.nch - 1));
+        store_T();
         __syncthreads();
     }
 
