@@ -5,6 +5,14 @@
 #include "tred_internal.hpp"
 #include "validate.hpp"
 
+// threads per deposition and LDS floats of a tile of the effective-charge kernel
+#ifndef TRED_EFFQ_NT
+#define TRED_EFFQ_NT 512
+#endif
+#ifndef TRED_EFFQ_CAP
+#define TRED_EFFQ_CAP 16384
+#endif
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -152,6 +160,11 @@ __device__ __forceinline__ float exp_neg(float x) {
     return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
 }
 
+// exp(-e / 2) for e >= 0, the factor -log2(e) / 2 folded into one product
+__device__ __forceinline__ float exp_neg_half(float e) {
+    return __builtin_amdgcn_exp2f(e * -0.72134752044448170f);
+}
+
 // erfc(z) for z >= 0 in the form t exp(-z^2 + P(t)), t = 1 / (1 + z / 2) (the Chebyshev
 // form of Numerical Recipes' erfcc); P is a degree-9 least-squares fit made for this
 // library (erfc_fit.py: relative error below 6e-7 on [0, 2], below 7e-6 up to z = 9).
@@ -162,10 +175,12 @@ __device__ __forceinline__ float erfc_pos(float z) {
                              1.705782861e-01f};
     constexpr float l2e = 1.44269504088896341f;
     const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
-    float p = c[9];
+    // P(t) log2(e) by Horner on the coefficients times log2(e) (binary32 products,
+    // folded at compile time)
+    float p = c[9] * l2e;
 #pragma unroll
-    for (int k = 8; k >= 0; --k) p = fmaf(p, t, c[k]);
-    return t * __builtin_amdgcn_exp2f(fmaf(-z * l2e, z, p * l2e));
+    for (int k = 8; k >= 0; --k) p = fmaf(p, t, c[k] * l2e);
+    return t * __builtin_amdgcn_exp2f(fmaf(-z * l2e, z, p));
 }
 
 // erf(b) - erf(a) for a <= b from erfc(|a|) and erfc(|b|): erfc(a) - erfc(b) when both
@@ -173,7 +188,10 @@ __device__ __forceinline__ float erfc_pos(float z) {
 // 2 - erfc(|a|) - erfc(|b|) across zero. Branch free.
 __device__ __forceinline__ float erf_diff(float b, float a) {
     const float ea = erfc_pos(fabsf(a)), eb = erfc_pos(fabsf(b));
-    return a >= 0.0f ? ea - eb : (b <= 0.0f ? eb - ea : 2.0f - ea - eb);
+    // all three forms, then selects (no divergent branches)
+    const float pos = ea - eb, neg = eb - ea, across = (2.0f - ea) - eb;
+    const float r = b <= 0.0f ? neg : across;
+    return a >= 0.0f ? pos : r;
 }
 
 // Small 3-D index iterator advancing by a fixed stride (avoids per-element divisions).
@@ -341,13 +359,13 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
             float q;
             if (point) {
                 const float e = rx * rx * isg2[0] + ry * ry * isg2[1] + rt * rt * isg2[2];
-                q = pref * exp_neg(-0.5f * e);
+                q = pref * exp_neg_half(e);
             } else {
                 const float beta = rx * gvec[0] + ry * gvec[1] + rt * gvec[2];
                 const float sst = beta * inv_alpha;       // closest point on the line
                 const float px = rx - sst * fd[0], py = ry - sst * fd[1], pt = rt - sst * fd[2];
                 const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
-                q = pref * exp_neg(-0.5f * e) * erf_diff(kq * (1.0f - sst), -kq * sst);
+                q = pref * exp_neg_half(e) * erf_diff(kq * (1.0f - sst), -kq * sst);
             }
             return wt * jac * q;
         };
@@ -422,7 +440,8 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                                 vq = node_charge(cx, lx, cy, ly, ct, lt);
                                 if (cx >= ox0 && cx <= ox1 && cy >= oy0 && cy <= oy1) nsum += (double)vq;
                             }
-                            V[(xo + it.i) * sxs + (yo + it.j) * nn2 + lt * R + kb + d] = vq;
+                            // (indices below 2^24: full-rate 24-bit products)
+                            V[__mul24(xo + it.i, sxs) + __mul24(yo + it.j, nn2) + lt * R + kb + d] = vq;
                         }
                     }
                     __syncthreads();
@@ -517,8 +536,9 @@ void gl_rule(int n, double* xi, double* w) {
 template <int NGL>
 void launch_effq(const EffqParams& P, int64_t n_dep, const float* seg, const int32_t* fp,
                  const int64_t* off, float* val, int64_t val_cap, double* cs, hipStream_t st) {
-    constexpr int CAP = 16384;   // node charges of one tile (64 KiB of LDS)
-    constexpr int NT = 512;
+    // node charges of one tile (floats of LDS): at least one cell and its neighbours
+    constexpr int CAP = TRED_EFFQ_CAP > 27 * NGL * NGL * NGL ? TRED_EFFQ_CAP : 27 * NGL * NGL * NGL;
+    constexpr int NT = TRED_EFFQ_NT;
     int64_t grid = n_dep < (1 << 20) ? n_dep : (1 << 20);
     hipLaunchKernelGGL((k_effq<NGL, CAP, NT>), dim3((unsigned)grid), dim3(NT), 0, st, P, n_dep, seg,
                        fp, off, val, val_cap, cs);

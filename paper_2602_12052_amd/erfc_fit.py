@@ -29,18 +29,18 @@ def fit(degree: int = DEGREE, zmax: float = ZMAX, n: int = 200001) -> np.ndarray
 
 def eval_f32(coef, z) -> np.ndarray:
     """The kernel's evaluation order in binary32: t by a reciprocal, Horner with fused
-    multiply-adds, exp2 of fma(-z log2e, z, P log2e), times t."""
+    multiply-adds on the coefficients times log2e (binary32 products), exp2 of
+    fma(-z log2e, z, P log2e), times t."""
     f32 = np.float32
     z = np.asarray(z, np.float32)
-    c = [f32(a) for a in coef]
+    l2e = f32(LOG2E)
+    c = [f32(f32(a) * l2e) for a in coef]
     t = (f32(1) / (f32(1) + f32(0.5) * z)).astype(f32)
     p = np.full_like(z, c[-1])
     for a in c[-2::-1]:
         p = (p.astype(np.float64) * t + a).astype(f32)            # one rounding per fma
-    l2e = f32(LOG2E)
-    u = (p.astype(np.float64) * l2e).astype(f32)
     v = (-(z.astype(np.float64) * l2e)).astype(f32)
-    arg = (v.astype(np.float64) * z + u).astype(f32)
+    arg = (v.astype(np.float64) * z + p).astype(f32)
     e = np.exp2(arg.astype(np.float64)).astype(f32)
     return (t * e).astype(f32)
 
