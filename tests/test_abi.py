@@ -143,6 +143,36 @@ def test_block_conv_requires_response(T):
     T.lib().tred_conv_plan_destroy(h)
 
 
+def test_row_words(T):
+    cfg = _cfg()        # 4x4-pixel bins, 10x10 impacts: 40 x 40 rows
+    assert T.tred_block_row_words(cfg.grid, cfg.blocking) == 50
+    cfg2 = W.cfg_module()
+    assert T.tred_block_row_words(cfg2.grid, cfg2.blocking) == 160 * 160 // 32
+    bad = T.grid_struct(cfg.grid)
+    bad.sub[0] = 0
+    assert T.lib().tred_block_row_words(C.byref(bad), C.byref(T.blocking_struct(cfg.blocking))) == -1
+
+
+def test_row_mask_calls_reject(T):
+    """The masked binning and convolution need their row masks (4-byte aligned) when
+    cap > 0; the checks run on the host before any work is enqueued."""
+    L = T.lib()
+    cfg = _cfg()
+    g, b = T.grid_struct(cfg.grid), T.blocking_struct(cfg.blocking)
+    p = C.c_void_p(0x1000)  # never dereferenced
+    assert L.tred_block_bin_rows(C.byref(g), C.byref(b), 1, p, p, p, 10, p, p, p, None, 4, p,
+                                 None) == T.TRED_EINVAL
+    assert b"rows" in L.tred_last_error()
+    assert L.tred_block_bin_rows(C.byref(g), C.byref(b), 1, p, p, p, 10, p, p, p,
+                                 C.c_void_p(0x1002), 4, p, None) == T.TRED_EINVAL
+    assert L.tred_block_bin_events_rows(C.byref(g), C.byref(b), 2, p, 1, p, p, p, 10, p, p, p, None,
+                                        4, p, None) == T.TRED_EINVAL
+    st, h, ws = _plan(T, cfg, fft=(8, 8, 256))
+    assert L.tred_block_conv_rows(h, p, 4, p, None, p, None) == T.TRED_EINVAL
+    assert b"rows" in L.tred_last_error()
+    T.lib().tred_conv_plan_destroy(h)
+
+
 def _dplan(T, cfg, kpix=None, kticks=None, flags=1, batch=8):
     g, b = T.grid_struct(cfg.grid), T.blocking_struct(cfg.blocking)
     kp = (C.c_int32 * 2)(*(kpix or cfg.kpix))
