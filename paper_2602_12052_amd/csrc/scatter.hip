@@ -88,9 +88,12 @@ __global__ __launch_bounds__(1024) void k_compact_pix(ScatArgs S, int32_t* __res
 }
 
 // One workgroup per pixel slot. Its threads walk the waveform in spans of 1024 ticks,
-// four ticks per thread, so the pixel's bin lookups are made once per span and each
-// thread keeps several block-output loads in flight. Per sample the covering bins are
-// summed in (bx, by, bt) order.
+// four ticks per thread, so the pixel's bin lookups are made once per span. Per
+// sample the covering bins are summed in (bx, by, bt) order. The loads carry no
+// branches, so a thread keeps the loads of every bin of a column in flight: each
+// block-output row is read through a buffer resource of its own length (ticks
+// outside it read zero), an inactive bin through an empty resource, and the bin
+// slots of a column are loaded once per wave (one per lane) and taken with readlane.
 constexpr int kGatherSpan = 1024;
 
 __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __restrict__ pix,
@@ -104,6 +107,7 @@ __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __res
     const int e = (int)(pix[slot] / npix);
     const int p = (int)(pix[slot] % npix);
     const int px = p / S.npy, py = p % S.npy;
+    const int lane = threadIdx.x & (kWave - 1);
     bmap += e * (int64_t)S.nb[0] * S.nb[1] * S.nb[2];
     // bins whose output footprint contains this pixel: b*B - h <= p <= b*B + B - 1 + h
     const int bx0 = max(0, (px - S.hx - S.Bx + 1 + S.Bx * 4096) / S.Bx - 4096);
@@ -111,6 +115,7 @@ __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __res
     const int by0 = max(0, (py - S.hy - S.By + 1 + S.By * 4096) / S.By - 4096);
     const int by1 = min(S.nb[1] - 1, (py + S.hy) / S.By);
     constexpr int NJ = kGatherSpan / 256;
+    const uint32_t rowb = (uint32_t)S.bot * 4u;
     float* wrow = wf + (int64_t)slot * S.lwf;
     for (int T0 = 0; T0 < S.lwf; T0 += kGatherSpan) {
         // bins whose ticks [bt Bt, bt Bt + bot) meet [T0, T0 + span)
@@ -124,15 +129,31 @@ __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __res
                 const int qx = px - bx * S.Bx + S.hx, qy = py - by * S.By + S.hy;
                 if (qx < 0 || qx >= S.box || qy < 0 || qy >= S.boy) continue;
                 const int32_t* bcol = bmap + ((int64_t)bx * S.nb[1] + by) * S.nb[2];
-                for (int bt = bt0; bt <= bt1; ++bt) {
-                    const int b = bcol[bt];
-                    if (b < 0) continue;
-                    const float* row = outb + (int64_t)b * S.vout + ((int64_t)qx * S.boy + qy) * S.bot;
-                    const int tb = T0 + (int)threadIdx.x - bt * S.Bt;   // tick within the row
+                const int64_t qoff = ((int64_t)qx * S.boy + qy) * S.bot;
+                for (int c0 = bt0; c0 <= bt1; c0 += kWave) {
+                    const int nc = min(kWave, bt1 - c0 + 1);
+                    const int vb = lane < nc ? bcol[c0 + lane] : -1;
+                    // four bins at a time: their loads in flight together, then the adds
+                    // in bin order
+                    for (int k0 = 0; k0 < nc; k0 += 4) {
+                        float v[4][NJ];
 #pragma unroll
-                    for (int j = 0; j < NJ; ++j) {
-                        const int t = tb + 256 * j;
-                        if (t >= 0 && t < S.bot) acc[j] += row[t];
+                        for (int u = 0; u < 4; ++u) {
+                            const int k = k0 + u;
+                            const int bl = __builtin_amdgcn_readlane(vb, min(k, nc - 1));
+                            const int b = k < nc ? bl : -1;
+                            const auto rr = buf_rsrc(outb + (int64_t)max(b, 0) * S.vout + qoff,
+                                                     b < 0 ? 0u : rowb);
+                            // tick within the row (negative ticks wrap past the end: zero)
+                            const uint32_t tb =
+                                (uint32_t)(T0 + (int)threadIdx.x - (c0 + k) * S.Bt) * 4u;
+#pragma unroll
+                            for (int j = 0; j < NJ; ++j) v[u][j] = buf_f1(rr, tb + 1024u * j, 0u);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int j = 0; j < NJ; ++j) acc[j] += v[u][j];
                     }
                 }
             }
