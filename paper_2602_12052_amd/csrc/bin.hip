@@ -179,35 +179,49 @@ __global__ __launch_bounds__(256) void k_zero_rows(float* __restrict__ blocks,
 }
 
 // one workgroup per deposition: add its patch into the bins (FP32 atomics; the
-// reduction order over overlapping patches is unspecified)
+// reduction order over overlapping patches is unspecified). A wave takes one patch row
+// (fixed x, y: nt cells along t) at a time, so the row's bin column and offsets are
+// found once per row; its lanes walk the row's ticks, the t bin advanced as they
+// cross bin edges.
 __global__ __launch_bounds__(256) void k_accum(BinGeom G, int64_t n, const int32_t* __restrict__ fp,
                                                const int64_t* __restrict__ off,
                                                const float* __restrict__ val, int64_t val_cap,
                                                const int64_t* __restrict__ ev_off,
                                                const int32_t* __restrict__ slot_all,
                                                float* __restrict__ blocks) {
+    // the wave index is uniform over the wave: row set-up runs on the scalar unit
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
     for (int64_t d = blockIdx.x; d < n; d += gridDim.x) {
         const int32_t* f = fp + 6 * d;
         if (f[3] < f[0] || f[4] < f[1] || f[5] < f[2]) continue;
+        if (off[d + 1] > val_cap) continue;
         const int32_t* slot = slot_all + (int64_t)event_of(d, ev_off, G.nev) * G.nbins;
         const int ny = f[4] - f[1] + 1, nt = f[5] - f[2] + 1;
-        if (off[d + 1] > val_cap) continue;
-        const int64_t cnt = off[d + 1] - off[d];
+        const int nrow = (f[3] - f[0] + 1) * ny;
         const float* v = val + off[d];
-        for (int64_t k = threadIdx.x; k < cnt; k += blockDim.x) {
-            const float q = v[k];
-            if (q == 0.0f) continue;
-            const int it = (int)(k % nt);
-            const int64_t r = k / nt;
-            const int iy = (int)(r % ny), ix = (int)(r / ny);
-            const int gx = f[0] + ix, gy = f[1] + iy, gt = f[2] + it;
-            const int bx = gx / G.bf[0], by = gy / G.bf[1], bt = gt / G.bf[2];
-            const int s = slot[((int64_t)bx * G.nb[1] + by) * G.nb[2] + bt];
-            if (s < 0) continue;
-            float* dst = blocks + (int64_t)s * G.vblk +
-                         ((int64_t)(gx - bx * G.bf[0]) * G.bf[1] + (gy - by * G.bf[1])) * G.bf[2] +
-                         (gt - bt * G.bf[2]);
-            unsafeAtomicAdd(dst, q);
+        // t bin of this lane's first tick, and the first tick past that bin
+        const int bt0 = (f[2] + lane) / G.bf[2];
+        const int be0 = (bt0 + 1) * G.bf[2];
+        for (int r = wv; r < nrow; r += nw) {
+            const int ix = r / ny, iy = r - ix * ny;
+            const int gx = f[0] + ix, gy = f[1] + iy;
+            const int bx = gx / G.bf[0], by = gy / G.bf[1];
+            const int32_t* scol = slot + ((int64_t)bx * G.nb[1] + by) * G.nb[2];
+            float* brow = blocks + ((int64_t)(gx - bx * G.bf[0]) * G.bf[1] + (gy - by * G.bf[1])) * G.bf[2];
+            const float* vrow = v + (int64_t)r * nt;
+            int bt = bt0, be = be0;
+            for (int t = lane; t < nt; t += kWave) {
+                const int gt = f[2] + t;
+                while (gt >= be) {
+                    ++bt;
+                    be += G.bf[2];
+                }
+                const float q = vrow[t];
+                const int s = scol[bt];
+                if (q == 0.0f || s < 0) continue;
+                unsafeAtomicAdd(brow + (int64_t)s * G.vblk + (gt - (be - G.bf[2])), q);
+            }
         }
     }
 }
@@ -232,26 +246,41 @@ __global__ __launch_bounds__(256) void k_accum_adj(BinGeom G, int64_t n, const i
                                                    const int32_t* __restrict__ slot_all,
                                                    const float* __restrict__ dblocks,
                                                    float* __restrict__ dval) {
+    // rows of the patch as in k_accum; cells past val_cap are not written
+    // the wave index is uniform over the wave: row set-up runs on the scalar unit
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave, nw = blockDim.x / kWave;
     for (int64_t d = blockIdx.x; d < n; d += gridDim.x) {
         const int32_t* f = fp + 6 * d;
         if (f[3] < f[0] || f[4] < f[1] || f[5] < f[2]) continue;
         const int32_t* slot = slot_all + (int64_t)event_of(d, ev_off, G.nev) * G.nbins;
         const int ny = f[4] - f[1] + 1, nt = f[5] - f[2] + 1;
+        const int nrow = (f[3] - f[0] + 1) * ny;
         const int64_t o0 = off[d], o1 = min(off[d + 1], val_cap);
         const bool kept = off[d + 1] <= val_cap;
-        for (int64_t k = threadIdx.x; k < o1 - o0; k += blockDim.x) {
-            const int it = (int)(k % nt);
-            const int64_t r = k / nt;
-            const int iy = (int)(r % ny), ix = (int)(r / ny);
-            const int gx = f[0] + ix, gy = f[1] + iy, gt = f[2] + it;
-            const int bx = gx / G.bf[0], by = gy / G.bf[1], bt = gt / G.bf[2];
-            const int s = slot[((int64_t)bx * G.nb[1] + by) * G.nb[2] + bt];
-            float g = 0.0f;
-            if (kept && s >= 0)
-                g = dblocks[(int64_t)s * G.vblk +
-                            ((int64_t)(gx - bx * G.bf[0]) * G.bf[1] + (gy - by * G.bf[1])) * G.bf[2] +
-                            (gt - bt * G.bf[2])];
-            dval[o0 + k] = g;
+        const int bt0 = (f[2] + lane) / G.bf[2];
+        const int be0 = (bt0 + 1) * G.bf[2];
+        for (int r = wv; r < nrow && o0 + (int64_t)r * nt < o1; r += nw) {
+            const int ix = r / ny, iy = r - ix * ny;
+            const int gx = f[0] + ix, gy = f[1] + iy;
+            const int bx = gx / G.bf[0], by = gy / G.bf[1];
+            const int32_t* scol = slot + ((int64_t)bx * G.nb[1] + by) * G.nb[2];
+            const float* brow =
+                dblocks + ((int64_t)(gx - bx * G.bf[0]) * G.bf[1] + (gy - by * G.bf[1])) * G.bf[2];
+            float* drow = dval + o0 + (int64_t)r * nt;
+            int bt = bt0, be = be0;
+            for (int t = lane; t < nt; t += kWave) {
+                const int gt = f[2] + t;
+                while (gt >= be) {
+                    ++bt;
+                    be += G.bf[2];
+                }
+                if (o0 + (int64_t)r * nt + t >= o1) break;
+                const int s = scol[bt];
+                float g = 0.0f;
+                if (kept && s >= 0) g = brow[(int64_t)s * G.vblk + (gt - (be - G.bf[2]))];
+                drow[t] = g;
+            }
         }
     }
 }
