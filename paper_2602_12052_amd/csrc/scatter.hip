@@ -90,10 +90,10 @@ __global__ __launch_bounds__(1024) void k_compact_pix(ScatArgs S, int32_t* __res
 // One workgroup per pixel slot. Its threads walk the waveform in spans of 1024 ticks,
 // four ticks per thread, so the pixel's bin lookups are made once per span. Per
 // sample the covering bins are summed in (bx, by, bt) order. The loads carry no
-// branches, so a thread keeps the loads of every bin of a column in flight: each
-// block-output row is read through a buffer resource of its own length (ticks
-// outside it read zero), an inactive bin through an empty resource, and the bin
-// slots of a column are loaded once per wave (one per lane) and taken with readlane.
+// branches, so a thread keeps the loads of four bins in flight: each block-output row
+// is read through a buffer resource of its own length (ticks outside it read zero),
+// and the bin slots of a column are loaded once per wave (one per lane); the active
+// ones are found by a ballot and taken with readlane.
 constexpr int kGatherSpan = 1024;
 
 __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __restrict__ pix,
@@ -133,15 +133,17 @@ __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __res
                 for (int c0 = bt0; c0 <= bt1; c0 += kWave) {
                     const int nc = min(kWave, bt1 - c0 + 1);
                     const int vb = lane < nc ? bcol[c0 + lane] : -1;
-                    // four bins at a time: their loads in flight together, then the adds
-                    // in bin order
-                    for (int k0 = 0; k0 < nc; k0 += 4) {
+                    // the active bins of the column (lanes with a slot), in bt order, four
+                    // at a time: their loads in flight together, then the adds in bin order
+                    uint64_t live = __builtin_amdgcn_ballot_w64(vb >= 0);
+                    while (live != 0) {
                         float v[4][NJ];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            const int k = k0 + u;
-                            const int bl = __builtin_amdgcn_readlane(vb, min(k, nc - 1));
-                            const int b = k < nc ? bl : -1;
+                            const int k = live != 0 ? (int)__builtin_ctzll(live) : 0;
+                            const bool use = live != 0;
+                            live &= live - 1;   // (no-op once empty)
+                            const int b = use ? __builtin_amdgcn_readlane(vb, k) : -1;
                             const auto rr = buf_rsrc(outb + (int64_t)max(b, 0) * S.vout + qoff,
                                                      b < 0 ? 0u : rowb);
                             // tick within the row (negative ticks wrap past the end: zero)
