@@ -144,6 +144,13 @@ def test_footprints_bitexact_adversarial(T, orc):
                             n=15, seed=15), True),
     ("fs16-full-input", dict(npix=20, blk=(10, 10, 64), kpix=(5, 5), kticks=120,
                              fft=(16, 16, 256), n=15, seed=16), True),
+    # the remaining prime-factor instances: L inputs per axis at sizes 24 and 40, 2 L at 48
+    ("fs24-eight-inputs", dict(npix=12, blk=(6, 6, 64), kpix=(11, 11), kticks=120,
+                               fft=(24, 24, 256), n=15, seed=17), True),
+    ("fs40-eight-inputs", dict(npix=16, blk=(8, 8, 128), kpix=(21, 21), kticks=200,
+                               fft=(40, 40, 512), n=15, seed=18), True),
+    ("fs48-32-inputs", dict(npix=24, blk=(24, 24, 128), kpix=(15, 15), kticks=200,
+                            fft=(48, 48, 512), n=12, seed=19), True),
 ])
 def test_small_paths_match_oracle(T, orc, name, kw, mpcp):
     say(f"test_small_paths_match_oracle[{name}]")
