@@ -329,6 +329,13 @@ tred_status tred_scatter_waveforms_adjoint(const tred_conv_plan* plan, const int
 tred_status tred_block_conv_adjoint(const tred_conv_plan* plan, const int32_t* n_active,
                                     int32_t cap, const float* d_out_blocks, float* d_blocks,
                                     void* stream);
+/* tred_block_conv_adjoint_rows: as tred_block_conv_adjoint, writing only the rows of
+ * d_blocks marked in `rows` (row masks of tred_block_bin_rows; the other rows are left
+ * as they were). tred_block_bin_adjoint reads d_blocks at patch cells only, which lie
+ * in marked rows. */
+tred_status tred_block_conv_adjoint_rows(const tred_conv_plan* plan, const int32_t* n_active,
+                                         int32_t cap, const float* d_out_blocks,
+                                         const uint32_t* rows, float* d_blocks, void* stream);
 /* tred_block_bin_adjoint: d_blocks in, d_val [val_cap] out (each patch cell gets the
  *   gradient of its bin cell; zero for cells of bins beyond cap and for patches that
  *   end past val_cap). work: tred_block_bin_workspace() bytes (overwritten). */

@@ -1147,6 +1147,40 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     }
 }
 
+// Row groups of the time transforms that hold a marked row (its own or the mirror
+// row of the pair): tflag[bin][ch][p / kTile] = 1, else 0. Used by the transposed
+// convolution with row masks, whose outputs are needed on the marked rows only.
+__global__ __launch_bounds__(256) void k_group_need(ConvArgs A, int b0, int nb,
+                                                    const int32_t* __restrict__ n_active) {
+    const int ng = A.ppad / kTile;
+    const int64_t total = (int64_t)nb * A.nch * ng;
+    const int nact = min(*n_active, A.cap) - b0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(i % ng);
+        const int ch = (int)((i / ng) % A.nch);
+        const int bl = (int)(i / ((int64_t)ng * A.nch));
+        uint8_t need = 0;
+        if (bl < nact) {
+            const uint32_t* rw = A.rows + (int64_t)(b0 + bl) * A.nrw;
+            const int jx = ch / A.sy, jy = ch % A.sy;
+            const int jb = A.S - 1 - ch;
+            const bool pair = A.mpcp && jb != ch;
+            const int jbx = jb / A.sy, jby = jb % A.sy;
+            for (int w = 0; w < kTile; ++w) {
+                const int p = g * kTile + w;
+                if (p >= A.Bx * A.By) break;
+                const int px = p / A.By, py = p % A.By;
+                const int r0 = (px * A.sx + jx) * A.NYf + (py * A.sy + jy);
+                const int r1 = ((A.Bx - 1 - px) * A.sx + jbx) * A.NYf + ((A.By - 1 - py) * A.sy + jby);
+                if ((rw[r0 >> 5] >> (r0 & 31)) & 1u) need = 1;
+                if (pair && ((rw[r1 >> 5] >> (r1 & 31)) & 1u)) need = 1;
+            }
+        }
+        A.tflag[i] = need;
+    }
+}
+
 // k_tf_adj: per (half T tile, channel, bin); wave wv handles pixel p of the half tile.
 template <int FT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 ? 4 : 1))) void k_tf_adj(
@@ -1159,6 +1193,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     const int ch = blockIdx.y;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int pt = blockIdx.x / (kTileT / kTile), half = blockIdx.x % (kTileT / kTile);
+    // with row masks, groups without a marked row are not needed
+    if (A.rows && A.tflag[((int64_t)bl * A.nch + ch) * (A.ppad / kTile) + blockIdx.x] == 0) return;
     float2* twl = (float2*)(lds + tf_lds_floats<FT>());
     fft_tw_fill<FT>(twl, tw, threadIdx.x, blockDim.x);
     // stage the half tile [f][kTile] of T-layout gradients
@@ -1187,15 +1223,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     float* blk = dblocks + (int64_t)b * A.vblk;
     float* r0 = blk + ((int64_t)(px * A.sx + jx) * A.NYf + (py * A.sy + jy)) * A.Bt;
     const int jbx = jb / A.sy, jby = jb % A.sy;
-    float* r1 = blk + ((int64_t)((A.Bx - 1 - px) * A.sx + jbx) * A.NYf +
-                       ((A.By - 1 - py) * A.sy + jby)) * A.Bt;
+    const int q1 = ((A.Bx - 1 - px) * A.sx + jbx) * A.NYf + ((A.By - 1 - py) * A.sy + jby);
+    float* r1 = blk + (int64_t)q1 * A.Bt;
+    // with row masks only the marked rows are written
+    bool w0 = true, w1 = pair;
+    if (A.rows) {
+        const uint32_t* rw = A.rows + (int64_t)b * A.nrw;
+        const int q0 = (px * A.sx + jx) * A.NYf + (py * A.sy + jy);
+        w0 = (rw[q0 >> 5] >> (q0 & 31)) & 1u;
+        w1 = w1 && ((rw[q1 >> 5] >> (q1 & 31)) & 1u);
+    }
     const int mb = A.Bt / kWave;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         if (m < mb) {
             const float2 z = cconj(v[m]);
-            r0[lane + kWave * m] = z.x;
-            if (pair) r1[lane + kWave * m] = z.y;
+            if (w0) r0[lane + kWave * m] = z.x;
+            if (w1) r1[lane + kWave * m] = z.y;
         }
     }
 }
@@ -1351,8 +1395,17 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     // bin bl0 (the host keeps NB channels' worth of bins below 2^31 bytes)
     constexpr int IT5 = (NB * NF * NIN * NIN + NT - 1) / NT;
     int o_src[IT5];
-    uint32_t o_off[IT5];
+    uint32_t o_off[IT5], o_fo[IT5];
     bool o_ok[IT5];
+    // with row masks: the need flags of this workgroup's groups, [b][ch][group], in LDS;
+    // the stores of groups without a marked row go past the end of the buffer resource
+    // (dropped)
+    const int ng = A.ppad / kTile;
+    uint8_t* gflag = reinterpret_cast<uint8_t*>(sm + Ls.total);
+    if (A.rows) {
+        for (int i = tid; i < NB * A.nch * ng; i += NT)
+            gflag[i] = i < nbv * A.nch * ng ? A.tflag[(int64_t)bl0 * A.nch * ng + i] : 0;
+    }
     {
         const int npx = Bx * By;
 #pragma unroll
@@ -1367,6 +1420,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                                                   ((int64_t)(p / kTileT) * A.ft + f0 + fl2) * kTileT +
                                                   p % kTileT))
                                : 0u;
+            o_fo[k] = o_ok[k] ? (uint32_t)(b * A.nch * ng + p / kTile) : 0u;
         }
     }
     for (int ch = 0; ch < A.nch; ++ch) {
@@ -1486,8 +1540,10 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             const auto tr = buf_rsrc(dT + ((int64_t)bl0 * A.nch + ch) * tstride,
                                      (uint32_t)(((int64_t)nbv * A.nch - ch) * tstride * 8));
 #pragma unroll
-            for (int k = 0; k < IT5; ++k)
-                if (o_ok[k]) buf_st_f2(ob[o_src[k]], tr, o_off[k], 0u);
+            for (int k = 0; k < IT5; ++k) {
+                const bool need = !A.rows || gflag[o_fo[k] + ch * ng] != 0;
+                if (o_ok[k]) buf_st_f2(ob[o_src[k]], tr, need ? o_off[k] : 0xfffffff0u, 0u);
+            }
         }
         __syncthreads();
     }
@@ -1671,7 +1727,9 @@ tred_status launch_spp_adj(const ConvArgs& A, int b0, int nb, const int32_t* na,
                            const float2* rhat, const float2* tws, float2* dT, hipStream_t st) {
     using S = SppShape<FS, L, NIN, NB>;
     const auto Ls = spp_adj_lds<FS, L, NIN, NB, S::NF>(A.box, A.boy, A.Bx, A.By);
-    const size_t lds = (size_t)Ls.total * sizeof(float2);
+    // + the need flags of NB bins (row masks)
+    const size_t lds = (size_t)Ls.total * sizeof(float2) +
+                       (A.rows ? ((size_t)NB * A.nch * (A.ppad / kTile) + 15) / 16 * 16 : 0);
     if (lds > 160 * 1024)
         return tred_fail(TRED_EUNSUPPORTED, "adjoint spatial stage needs %zu B of LDS", lds);
     const int64_t tbytes = (int64_t)NB * A.nch * (A.ppad / kTileT) * A.ft * kTileT * 8;
@@ -1983,9 +2041,10 @@ extern "C" tred_status tred_block_conv_rows(const tred_conv_plan* P, const int32
     return block_conv(P, n_active, cap, blocks, rows, out_blocks, stream);
 }
 
-extern "C" tred_status tred_block_conv_adjoint(const tred_conv_plan* P, const int32_t* n_active,
-                                               int32_t cap, const float* d_out_blocks,
-                                               float* d_blocks, void* stream) {
+namespace {
+tred_status block_conv_adjoint(const tred_conv_plan* P, const int32_t* n_active, int32_t cap,
+                               const float* d_out_blocks, const uint32_t* rows, float* d_blocks,
+                               void* stream) {
     TRED_REQUIRE(P && n_active, "plan/n_active is NULL");
     TRED_REQUIRE(P->ready, "plan has no response (call tred_conv_plan_set_response)");
     TRED_REQUIRE(cap >= 0, "cap must be >= 0");
@@ -2000,9 +2059,16 @@ extern "C" tred_status tred_block_conv_adjoint(const tred_conv_plan* P, const in
     const float2* rhat = (const float2*)(ws + P->off_rhat);
     float2* T = (float2*)(ws + P->off_scratch_t);
     float2* U = (float2*)(ws + P->off_scratch_u);
+    A.rows = rows;
+    A.tflag = (uint8_t*)(ws + P->off_tflag);
     const int pass = std::min(P->batch, 65535);   // bins per pass (a grid dimension)
     for (int b0 = 0; b0 < cap; b0 += pass) {
         const int nb = std::min(pass, cap - b0);
+        if (rows) {
+            const int64_t ngr = (int64_t)nb * A.nch * (A.ppad / kTile);
+            hipLaunchKernelGGL(k_group_need, dim3((unsigned)std::min<int64_t>((ngr + 255) / 256, 8192)),
+                               dim3(256), 0, st, A, b0, nb, n_active);
+        }
         TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
             return launch_time_adj<decltype(ftc)::value>(A, b0, nb, n_active, d_out_blocks, twt, U,
                                                          T, d_blocks, 0, st);
@@ -2014,6 +2080,22 @@ extern "C" tred_status tred_block_conv_adjoint(const tred_conv_plan* P, const in
         }));
     }
     return TRED_OK;
+}
+}  // namespace
+
+extern "C" tred_status tred_block_conv_adjoint(const tred_conv_plan* P, const int32_t* n_active,
+                                               int32_t cap, const float* d_out_blocks,
+                                               float* d_blocks, void* stream) {
+    return block_conv_adjoint(P, n_active, cap, d_out_blocks, nullptr, d_blocks, stream);
+}
+
+extern "C" tred_status tred_block_conv_adjoint_rows(const tred_conv_plan* P,
+                                                    const int32_t* n_active, int32_t cap,
+                                                    const float* d_out_blocks, const uint32_t* rows,
+                                                    float* d_blocks, void* stream) {
+    TRED_REQUIRE(cap == 0 || rows, "rows is NULL");
+    TRED_REQUIRE(((uintptr_t)rows & 3) == 0, "rows must be 4-byte aligned");
+    return block_conv_adjoint(P, n_active, cap, d_out_blocks, rows, d_blocks, stream);
 }
 
 extern "C" tred_status tred_conv_plan_set_timing(tred_conv_plan* P, void* const* events) {

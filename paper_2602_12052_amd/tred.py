@@ -73,7 +73,7 @@ EXPORTS = [
     "tred_scatter_events_workspace", "tred_scatter_waveforms_events",
     "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint", "tred_block_bin_adjoint",
     "tred_effq_adjoint", "tred_block_row_words", "tred_block_bin_rows", "tred_block_conv_rows",
-    "tred_block_bin_events_rows",
+    "tred_block_bin_events_rows", "tred_block_conv_adjoint_rows",
 ]
 
 _lib = None
@@ -132,6 +132,7 @@ def lib():
     L.tred_block_conv_rows.argtypes = [P, P, I32, P, P, P, P]
     L.tred_block_bin_events_rows.argtypes = [P, P, I32, P, I64, P, P, P, I64, P, P, P, P, I32,
                                              P, P]
+    L.tred_block_conv_adjoint_rows.argtypes = [P, P, I32, P, P, P, P]
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
                  "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
@@ -140,7 +141,8 @@ def lib():
                  "tred_block_bin_events", "tred_scatter_waveforms_events",
                  "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint",
                  "tred_block_bin_adjoint", "tred_effq_adjoint", "tred_block_bin_rows",
-                 "tred_block_conv_rows", "tred_block_bin_events_rows"):
+                 "tred_block_conv_rows", "tred_block_bin_events_rows",
+                 "tred_block_conv_adjoint_rows"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -444,6 +446,19 @@ def tred_block_conv_adjoint(plan: ConvPlan, n_active, d_out_blocks, d_blocks, st
                                          _ptr(d_blocks), _stream(stream)))
 
 
+def tred_block_conv_adjoint_rows(plan: ConvPlan, n_active, d_out_blocks, rows, d_blocks,
+                                 stream=None):
+    """tred_block_conv_adjoint writing only the rows of d_blocks marked in `rows`."""
+    import torch
+    _dt(d_out_blocks, torch.float32, "d_out_blocks"), _dt(d_blocks, torch.float32, "d_blocks")
+    _dt(rows, torch.int32, "rows")
+    cap = d_blocks.shape[0]
+    if d_out_blocks.shape[0] < cap or rows.shape[0] < cap:
+        raise ValueError("d_out_blocks/rows have fewer rows than d_blocks")
+    _check(lib().tred_block_conv_adjoint_rows(plan.handle, _ptr(n_active), cap, _ptr(d_out_blocks),
+                                              _ptr(rows), _ptr(d_blocks), _stream(stream)))
+
+
 def tred_block_bin_adjoint(grid, blocking, fp, off, keys, n_active, d_blocks, d_val, work,
                            stream=None):
     import torch
@@ -553,7 +568,12 @@ class Pipeline:
             self.d_phys = torch.zeros(3, dtype=torch.float64, device="cuda")
         tred_scatter_waveforms_adjoint(self.plan, self.keys, self.n_active, self.pix, self.n_pix,
                                        d_wf, self.d_out_blocks, stream)
-        tred_block_conv_adjoint(self.plan, self.n_active, self.d_out_blocks, self.d_blocks, stream)
+        if self.rows is not None:
+            tred_block_conv_adjoint_rows(self.plan, self.n_active, self.d_out_blocks, self.rows,
+                                         self.d_blocks, stream)
+        else:
+            tred_block_conv_adjoint(self.plan, self.n_active, self.d_out_blocks, self.d_blocks,
+                                    stream)
         tred_block_bin_adjoint(self.grid, self.blocking, self.fp, self.off, self.keys,
                                self.n_active, self.d_blocks, self.d_val, self.bin_work, stream)
         self.d_phys.zero_()

@@ -125,6 +125,35 @@ def test_conv_transpose(T, name, kw, mpcp):
     assert abs(lhs - rhs) <= 1e-5 * scale
 
 
+@pytest.mark.parametrize("name,kw,mpcp", [CONV_CASES[0], CONV_CASES[1], CONV_CASES[5]])
+def test_conv_adjoint_rows_match_dense(T, name, kw, mpcp):
+    """The transposed convolution with row masks writes the marked rows exactly as the
+    dense transpose does and leaves the other rows untouched (here NaN)."""
+    import torch
+    say(f"test_conv_adjoint_rows_match_dense[{name}]")
+    g, ph, blk, kpix, kticks, fft, seg = grid_cfg_small(**kw)
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=11)
+    pl, sd = pipeline(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp)
+    torch.cuda.synchronize()
+    na = min(int(pl.n_active.item()), pl.keys.shape[0])
+    assert na > 0 and pl.rows is not None
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    Y = torch.randn(pl.out_blocks.shape, device="cuda", generator=gen)
+    dense = torch.empty_like(pl.blocks)
+    masked = torch.full_like(pl.blocks, float("nan"))
+    T.tred_block_conv_adjoint(pl.plan, pl.n_active, Y, dense)
+    T.tred_block_conv_adjoint_rows(pl.plan, pl.n_active, Y, pl.rows, masked)
+    torch.cuda.synchronize()
+    nrow = blk.blk_pix[0] * g.sub[0] * blk.blk_pix[1] * g.sub[1]
+    bits = pl.rows[:na].cpu().numpy().view(np.uint32)
+    marked = ((bits[:, np.arange(nrow) // 32] >> (np.arange(nrow) % 32).astype(np.uint32)) & 1) != 0
+    d = dense[:na].cpu().numpy().reshape(na, nrow, blk.blk_ticks)
+    m = masked[:na].cpu().numpy().reshape(na, nrow, blk.blk_ticks)
+    say(f"  {na} bins, marked rows {marked.mean():.3f}")
+    assert np.array_equal(m[marked], d[marked])
+    assert np.all(np.isnan(m[~marked]))
+
+
 def grid_cfg_small(npix=6, sub=3, nticks=200, blk=(2, 2, 64), kpix=(3, 5), kticks=100,
                    fft=(8, 8, 256), n=12, seed=1):
     h = W.PITCH / sub
