@@ -616,6 +616,7 @@ __device__ __forceinline__ Dual dsqrt(const Dual& a) {
     return dapply(a, r, 0.5f / r);
 }
 
+template <int NGL>
 __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
                                                   const float* __restrict__ seg,
                                                   const int32_t* __restrict__ fp,
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
     __shared__ float sdv[CAPA];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const tred_grid& g = P.g;
-    const int ngl = P.ph.n_gl;
+    constexpr int ngl = NGL;
     for (int64_t d = blockIdx.x; d < n_dep; d += gridDim.x) {
         const int32_t* f = fp + 6 * d;
         const int F0[3] = {f[0], f[1], f[2]}, F1[3] = {f[3], f[4], f[5]};
@@ -684,10 +685,11 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
 #pragma unroll
         for (int k = 0; k < NA; ++k) acc[k] = 0.0;
         const int64_t total = (int64_t)nn[0] * nn[1] * nn[2];
-        for (int64_t i = tid; i < total; i += NT) {
-            const int kt = (int)(i % nn[2]);
-            const int64_t r = i / nn[2];
-            const int ky = (int)(r % nn[1]), kx = (int)(r / nn[1]);
+        // node (kx, ky, kt) of the window, stepped by NT (32-bit components)
+        Idx3 itn;
+        itn.init(tid, NT, max(nn[1], 1), max(nn[2], 1));
+        for (int64_t i = tid; i < total; i += NT, itn.next()) {
+            const int kx = itn.i, ky = itn.j, kt = itn.k;
             const int cc[3] = {C0[0] + kx / ngl, C0[1] + ky / ngl, C0[2] + kt / ngl};
             const int ll[3] = {kx % ngl, ky % ngl, kt % ngl};
             // transposed spread: grid points c (1 - |xi| / 2) and c + sign(xi) (|xi| / 2)
@@ -874,8 +876,20 @@ extern "C" tred_status tred_effq_adjoint(const tred_grid* grid, const tred_physi
     for (int k = 0; k < 16; ++k) P.u[k] = 0.f;
     hipStream_t st = (hipStream_t)stream;
     const unsigned nb = (unsigned)std::min<int64_t>(n_dep, 1 << 20);
-    hipLaunchKernelGGL(k_effq_adj, dim3(nb), dim3(256), 0, st, P, n_dep, seg, fp, off, d_val,
-                       val_cap, d_seg, d_phys);
+    auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, st, P, n_dep, seg, fp, off, d_val, val_cap,
+                           d_seg, d_phys);
+    };
+    switch (n) {
+        case 1: launch(k_effq_adj<1>); break;
+        case 2: launch(k_effq_adj<2>); break;
+        case 3: launch(k_effq_adj<3>); break;
+        case 4: launch(k_effq_adj<4>); break;
+        case 5: launch(k_effq_adj<5>); break;
+        case 6: launch(k_effq_adj<6>); break;
+        case 7: launch(k_effq_adj<7>); break;
+        default: launch(k_effq_adj<8>); break;
+    }
     return tred_check_launch("tred_effq_adjoint");
 }
 
