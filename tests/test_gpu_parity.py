@@ -161,6 +161,42 @@ def test_small_paths_match_oracle(T, orc, name, kw, mpcp):
     compare_all(r, o)
 
 
+def random_config(seed):
+    """A valid small configuration drawn from a seeded generator: spatial size one of the
+    two smallest kernel sizes that hold block + response - 1 (blocks at most 2 L), time
+    size 256 or 512 with at most four response pieces."""
+    rng = np.random.default_rng(1000 + seed)
+    sub = int(rng.integers(2, 6))
+    bp = int(rng.integers(2, 17))
+    kp = int(rng.choice([3, 5, 7, 9, 11, 15, 21]))
+    need = bp + kp - 1
+    fits = [f for f in (8, 16, 24, 32, 40, 48, 64)
+            if f >= need and bp <= 2 * (16 if f in (16, 32, 48, 64) else 8)]
+    fs = int(fits[int(rng.integers(0, min(2, len(fits))))])
+    bt = int(rng.choice([64, 128]))
+    ft = int(rng.choice([256, 512]))
+    kticks = int(rng.integers(40, min(4 * (ft - bt), 600)))
+    npix = bp * int(rng.integers(2, 4))
+    nticks = int(rng.integers(3, 6)) * bt
+    return dict(npix=npix, sub=sub, nticks=nticks, blk=(bp, bp, bt), kpix=(kp, kp), kticks=kticks,
+                fft=(fs, fs, ft), n=int(rng.integers(5, 25)), seed=seed,
+                length=(0.01, float(rng.choice([0.1, 0.4])))), bool(rng.integers(0, 2)), \
+        int(rng.integers(1, 6))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_configs_match_oracle(T, orc, seed):
+    """Seeded sweep over sub-pixel counts, block and response sizes, FFT sizes, piece
+    counts, packing and conv pass sizes (row-mask path) against the oracle."""
+    kw, mpcp, batch = random_config(seed)
+    say(f"test_random_configs_match_oracle[{seed}] {kw} mpcp={mpcp} batch={batch}")
+    g, ph, blk, kpix, kticks, fft, seg = small_cfg(**kw)
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=11 + seed)
+    r = gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp=mpcp, batch=batch)
+    o = oracle_path(orc, g, ph, blk, kpix, kticks, resp, seg)
+    compare_all(r, o)
+
+
 def test_conv_delta_response_plain(T, orc):
     """A single unit entry in the response copies the charge to one offset (plain path)."""
     say("test_conv_delta_response_plain")
