@@ -154,6 +154,61 @@ def test_conv_adjoint_rows_match_dense(T, name, kw, mpcp):
     assert np.all(np.isnan(m[~marked]))
 
 
+def random_pfa_config(seed):
+    """A valid small configuration for the transposed convolution (prime-factor spatial
+    sizes 8, 16, 24, 40, 48) from a seeded generator."""
+    rng = np.random.default_rng(2000 + seed)
+    sub = int(rng.integers(2, 6))
+    bp = int(rng.integers(2, 17))
+    kp = int(rng.choice([3, 5, 7, 9, 11, 15]))
+    need = bp + kp - 1
+    fits = [f for f in (8, 16, 24, 40, 48) if f >= need and bp <= 2 * (16 if f in (16, 48) else 8)]
+    fs = int(fits[int(rng.integers(0, min(2, len(fits))))])
+    bt = int(rng.choice([64, 128]))
+    ft = int(rng.choice([256, 512]))
+    kticks = int(rng.integers(40, min(4 * (ft - bt), 500)))
+    return dict(npix=bp * int(rng.integers(2, 4)), sub=sub, nticks=int(rng.integers(3, 6)) * bt,
+                blk=(bp, bp, bt), kpix=(kp, kp), kticks=kticks, fft=(fs, fs, ft),
+                n=int(rng.integers(5, 20)), seed=seed), bool(rng.integers(0, 2))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_conv_transpose_random(T, seed):
+    """<conv(X), Y> = <X, conv^T(Y)> on seeded random configurations, and the transpose
+    with row masks equal to the dense one on the marked rows."""
+    import torch
+    kw, mpcp = random_pfa_config(seed)
+    say(f"test_conv_transpose_random[{seed}] {kw} mpcp={mpcp}")
+    g, ph, blk, kpix, kticks, fft, seg = grid_cfg_small(**kw)
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=31 + seed)
+    pl, sd = pipeline(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp, batch=3)
+    torch.cuda.synchronize()
+    na = min(int(pl.n_active.item()), pl.keys.shape[0])
+    assert na > 0
+    gen = torch.Generator(device="cuda").manual_seed(50 + seed)
+    X = torch.randn(pl.blocks.shape, device="cuda", generator=gen)
+    Y = torch.randn(pl.out_blocks.shape, device="cuda", generator=gen)
+    out = torch.empty_like(pl.out_blocks)
+    dX = torch.empty_like(pl.blocks)
+    dXr = torch.full_like(pl.blocks, float("nan"))
+    T.tred_block_conv(pl.plan, pl.n_active, X, out)
+    T.tred_block_conv_adjoint(pl.plan, pl.n_active, Y, dX)
+    T.tred_block_conv_adjoint_rows(pl.plan, pl.n_active, Y, pl.rows, dXr)
+    torch.cuda.synchronize()
+    lhs = dot(out[:na].cpu().numpy(), Y[:na].cpu().numpy())
+    rhs = dot(X[:na].cpu().numpy(), dX[:na].cpu().numpy())
+    scale = float(torch.linalg.norm(out[:na].double()) * torch.linalg.norm(Y[:na].double()))
+    say(f"  {na} bins: diff/scale {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-5 * scale
+    nrow = blk.blk_pix[0] * g.sub[0] * blk.blk_pix[1] * g.sub[1]
+    bits = pl.rows[:na].cpu().numpy().view(np.uint32)
+    marked = ((bits[:, np.arange(nrow) // 32] >> (np.arange(nrow) % 32).astype(np.uint32)) & 1) != 0
+    d = dX[:na].cpu().numpy().reshape(na, nrow, blk.blk_ticks)
+    m = dXr[:na].cpu().numpy().reshape(na, nrow, blk.blk_ticks)
+    assert np.array_equal(m[marked], d[marked])
+    assert np.all(np.isnan(m[~marked]))
+
+
 def grid_cfg_small(npix=6, sub=3, nticks=200, blk=(2, 2, 64), kpix=(3, 5), kticks=100,
                    fft=(8, 8, 256), n=12, seed=1):
     h = W.PITCH / sub
