@@ -10,7 +10,7 @@
 #define TRED_EFFQ_NT 512
 #endif
 #ifndef TRED_EFFQ_CAP
-#define TRED_EFFQ_CAP 16384
+#define TRED_EFFQ_CAP 20224   // 79 KiB: two workgroups per CU (160 KiB of LDS)
 #endif
 
 namespace {
