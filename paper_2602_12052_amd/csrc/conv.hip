@@ -344,6 +344,186 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
 }
 
 // ---------------------------------------------------------------------------
+// With row masks the live T tiles are known before the transforms: k_tf_tiles lists
+// the (bin, channel, tile) whose pixels read a marked row, with the bits of those rows
+// (bit half * kTile + wave for Q_j, 16 + that for the mirror row Q_j'), and writes
+// the group flags of both halves; k_tf_list transforms the listed tiles only. Row
+// groups without a marked row are zero, flagged 0 and never written. The list is in
+// no particular order: every tile is written independently of the others.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_count(int32_t* __restrict__ c) {
+    if (threadIdx.x == 0) c[0] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_tf_tiles(ConvArgs A, int b0, int nb,
+                                                  const int32_t* __restrict__ n_active,
+                                                  int2* __restrict__ list, int32_t* __restrict__ count) {
+    static_assert(kTileT == 2 * kTile && kTile == 8, "tile bits: two halves of 8 rows");
+    const int ntile = A.ppad / kTileT, ng = A.ppad / kTile;
+    const int64_t total = (int64_t)nb * A.nch * ntile;
+    const int nact = min(*n_active, A.cap) - b0;
+    const int lane = threadIdx.x & 63;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < total;
+         i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        uint32_t bits = 0;
+        if (i < total) {
+            const int pt = (int)(i % ntile);
+            const int ch = (int)((i / ntile) % A.nch);
+            const int bl = (int)(i / ((int64_t)ntile * A.nch));
+            if (bl < nact) {
+                const uint32_t* rw = A.rows + (int64_t)(b0 + bl) * A.nrw;
+                const int jx = ch / A.sy, jy = ch % A.sy;
+                const int jb = A.S - 1 - ch;
+                const bool pair = A.mpcp && jb != ch;
+                const int jbx = jb / A.sy, jby = jb % A.sy;
+                for (int k = 0; k < kTileT; ++k) {
+                    const int p = pt * kTileT + k;
+                    if (p >= A.Bx * A.By) break;
+                    const int px = p / A.By, py = p % A.By;
+                    const int r0 = (px * A.sx + jx) * A.NYf + (py * A.sy + jy);
+                    const int r1 = ((A.Bx - 1 - px) * A.sx + jbx) * A.NYf + ((A.By - 1 - py) * A.sy + jby);
+                    if ((rw[r0 >> 5] >> (r0 & 31)) & 1u) bits |= 1u << k;
+                    if (pair && ((rw[r1 >> 5] >> (r1 & 31)) & 1u)) bits |= 1u << (16 + k);
+                }
+            }
+            uint8_t* fl = A.tflag + ((int64_t)bl * A.nch + ch) * ng + 2 * pt;
+            fl[0] = (bits & 0x00ff00ffu) != 0;
+            fl[1] = (bits & 0xff00ff00u) != 0;
+        }
+        // one counter update per wave; lanes take consecutive slots in lane order
+        const bool live = bits != 0;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(live);
+        if (bal != 0) {
+            const int leader = __builtin_ctzll(bal);
+            int base = 0;
+            if (lane == leader) base = atomicAdd(count, __builtin_popcountll(bal));
+            base = __shfl(base, leader);
+            if (live) {
+                const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                list[base + r] = make_int2((int)i, (int)bits);
+            }
+        }
+    }
+}
+
+// k_tf_list: the time FFTs of the listed tiles. Iteration q covers half (q / 8) % 2 of
+// list entry (q / 16) * 8 + q % 8: the two halves of a tile (one 128-byte line of T per
+// frequency) are kXcd apart in q and, with the grid a multiple of 2 kXcd, land on one
+// XCD (one L2). Every iteration issues the same vector memory operations in the same
+// order (loads and stores it does not need address an empty buffer resource, which
+// reads zero and drops stores), so each wait waits for the operation it needs and not
+// for the stores still in flight: list entries are requested two iterations before
+// their transform and rows one iteration before; the loop starts two iterations early.
+template <int FT, bool HALF>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 ? 4 : 1))) void k_tf_list(
+    ConvArgs A, int b0, const int2* __restrict__ list, const int32_t* __restrict__ count, int32_t lcap,
+    const float* __restrict__ blocks, const float2* __restrict__ tw, float2* __restrict__ T) {
+    extern __shared__ float lds[];
+    constexpr int M = FT / kWave, MB = HALF ? M / 2 : M;
+    using u2 = __attribute__((ext_vector_type(2))) unsigned int;
+    const int n = min(*count, lcap);
+    if (n <= 0) return;
+    const int total = 2 * kTile * ((n + kTile - 1) / kTile);
+    const int G = (int)gridDim.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int mb = A.Bt / kWave;
+    const int ntile = A.ppad / kTileT;
+    const auto lr = buf_rsrc(list, (uint32_t)n * 8u);
+    // list entry of iteration q (q >= 0), requested now and used an iteration later
+    u2 en = {0u, 0u};
+    bool en_ok = false;
+    auto load_entry = [&](int q) {
+        const int t = (q >> 4) * kTile + (q & (kTile - 1));
+        en_ok = t < n;
+        en = __builtin_bit_cast(u2, __builtin_amdgcn_raw_buffer_load_b64(lr, 0u, (uint32_t)min(t, n - 1) * 8u, 0));
+    };
+    // rows of iteration q's pixel (this wave) of tile `tile` into (ra, rb): Q_j and,
+    // under mirror-pair packing, Q_j'; only rows whose bit is set are read (32-bit
+    // offsets within the bin: the host keeps a bin below 2^31 bytes)
+    float ra[MB], rb[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) ra[m] = rb[m] = 0.0f;
+    auto load = [&](int q, int tile, uint32_t bits) {
+        const int h = (q >> 3) & 1;
+        const int pt = tile % ntile, ch = (tile / ntile) % A.nch, bl = tile / (ntile * A.nch);
+        const int p = pt * kTileT + h * kTile + wv;
+        const bool la = (bits >> (h * kTile + wv)) & 1u;
+        const bool lb = (bits >> (16 + h * kTile + wv)) & 1u;
+        const int pc = min(p, A.Bx * A.By - 1);
+        const int px = pc / A.By, py = pc % A.By;
+        const int jx = ch / A.sy, jy = ch % A.sy;
+        const int jb = A.S - 1 - ch;
+        const int jbx = jb / A.sy, jby = jb % A.sy;
+        const int r0 = (px * A.sx + jx) * A.NYf + (py * A.sy + jy);
+        const int r1 = ((A.Bx - 1 - px) * A.sx + jbx) * A.NYf + ((A.By - 1 - py) * A.sy + jby);
+        const float* bb = blocks + (int64_t)(b0 + bl) * A.vblk;
+        const uint32_t vb = (uint32_t)(A.vblk * 4);
+        const auto bra = buf_rsrc(bb, la ? vb : 0u), brb = buf_rsrc(bb, lb ? vb : 0u);
+        const uint32_t o0 = 4u * (uint32_t)(r0 * A.Bt + lane);
+        const uint32_t o1 = 4u * (uint32_t)(r1 * A.Bt + lane);
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            // ticks past Bt belong to the next row: read tick block mb - 1 again, then zero
+            const uint32_t so = (uint32_t)(min(m, mb - 1) * kWave * 4);
+            const float xa = buf_f1(bra, o0, so), xb = buf_f1(brb, o1, so);
+            ra[m] = m < mb ? xa : 0.0f;
+            rb[m] = m < mb ? xb : 0.0f;
+        }
+    };
+    // twiddle table in LDS after the FFT scratch / staging region
+    float2* twl = (float2*)(lds + tf_lds_floats<FT>());
+    fft_tw_fill<FT>(twl, tw, threadIdx.x, blockDim.x);
+    __syncthreads();
+    int cur_tile = 0;          // entry of the group this iteration transforms
+    uint32_t cur_bits = 0u;
+    for (int q = (int)blockIdx.x - 2 * G; q < total; q += G) {
+        float2 v[M];
+        bool nz = false;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            v[m] = m < MB ? make_float2(ra[m], rb[m]) : make_float2(0.f, 0.f);
+            if (m < MB) nz = nz || ra[m] != 0.0f || rb[m] != 0.0f;
+        }
+        const int tile = cur_tile;
+        const uint32_t bits = cur_bits;
+        // the next group's rows, in flight during the transform
+        cur_tile = (int)__builtin_amdgcn_readfirstlane(en.x);
+        cur_bits = en_ok ? __builtin_amdgcn_readfirstlane(en.y) : 0u;
+        load(q + G, cur_tile, cur_bits);
+        load_entry(q + 2 * G);
+        // the transform of zeros is zero: such a wave keeps v
+        if (__builtin_amdgcn_ballot_w64(nz) != 0) wave_fft<FT, true, true>(v, lds + wv * kFftLds<FT>, twl, lane);
+        __syncthreads();   // the staging tile overlaps the other waves' FFT scratch
+        const int h = (q >> 3) & 1;
+        const bool wr = q >= 0 && ((bits >> (h * kTile)) & 0xffu | (bits >> (16 + h * kTile)) & 0xffu) != 0;
+        float2* stage = (float2*)lds;   // [f][kTile], columns swizzled
+        if (wr) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int f = lane + kWave * m;
+                stage[f * kTile + tf_col(f, wv)] = v[m];
+            }
+        }
+        __syncthreads();
+        const auto tr = buf_rsrc(T + (int64_t)tile * FT * kTileT,
+                                 wr ? (uint32_t)(FT * kTileT * sizeof(float2)) : 0u);
+        // thread t stores pixel c = t % kTile of rows f = t / kTile + (512 / kTile) k
+        // (as in k_tf)
+        {
+            const int f0 = (int)threadIdx.x / kTile, c = (int)threadIdx.x % kTile;
+            const float2* src = stage + f0 * kTile + tf_col(f0, c);
+            const uint32_t voff = (uint32_t)((f0 * kTileT + h * kTile + c) * 8);
+#pragma unroll
+            for (int k = 0; k < FT * kTile / 512; ++k)
+                buf_st_f2(src[512 * k], tr, voff, (uint32_t)(k * (512 / kTile) * kTileT * 8));
+        }
+        __syncthreads();   // the next FFT's scratch overlaps the staging tile
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_sp: spatial transforms and the spectral multiply-accumulate, per time frequency.
 // The fs-point transform along an axis with at most B <= 2L nonzero inputs
 // (L in {8, 16} divides fs) is split as k = r + RS m (RS = fs / L): for each r an
@@ -1639,12 +1819,35 @@ void allow_lds(K kernel, size_t bytes) {
         have = bytes;
 }
 
+// list: workspace for the live-tile list (row masks with skipped groups) or NULL
 template <int FT>
 tred_status launch_time_fwd(const ConvArgs& A, int b0, int nb, const int32_t* na, const float* blocks,
-                            const float2* tw, float2* T, hipStream_t st) {
+                            const float2* tw, float2* T, int2* list, int32_t* count, hipStream_t st) {
     const size_t lds = (size_t)tf_lds_floats<FT>() * sizeof(float) + (size_t)FT * sizeof(float2);
     if (A.vblk * 4 > INT32_MAX)
         return tred_fail(TRED_EUNSUPPORTED, "time forward: %lld B per bin", (long long)(A.vblk * 4));
+    if (list && A.rows && A.tskip) {
+        // live tiles listed first; the transforms run over the list
+        const int64_t tiles = (int64_t)(A.ppad / kTileT) * A.nch * nb;
+        if (tiles <= 0) return TRED_OK;
+        if (tiles > INT32_MAX / 2)
+            return tred_fail(TRED_EUNSUPPORTED, "time forward: %lld tiles per pass", (long long)tiles);
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, st, count);
+        hipLaunchKernelGGL(k_tf_tiles, dim3((unsigned)std::min<int64_t>((tiles + 255) / 256, 8192)), dim3(256),
+                           0, st, A, b0, nb, na, list, count);
+        const int64_t qs = 2 * tiles;
+        const int64_t G = std::min<int64_t>(TRED_TF_GRID, (qs + 2 * kXcd - 1) / (2 * kXcd) * (2 * kXcd));
+        if (2 * A.Bt <= FT) {
+            allow_lds(k_tf_list<FT, true>, lds);
+            hipLaunchKernelGGL((k_tf_list<FT, true>), dim3((unsigned)G), dim3(512), lds, st, A, b0, list, count,
+                               (int32_t)tiles, blocks, tw, T);
+        } else {
+            allow_lds(k_tf_list<FT, false>, lds);
+            hipLaunchKernelGGL((k_tf_list<FT, false>), dim3((unsigned)G), dim3(512), lds, st, A, b0, list, count,
+                               (int32_t)tiles, blocks, tw, T);
+        }
+        return tred_check_launch("tred_block_conv time forward (listed tiles)");
+    }
     // persistent workgroups: a multiple of 2 kXcd (tile halves on one XCD), a few per CU
     const int64_t groups = (int64_t)(A.ppad / kTile) * A.nch * nb;
     const int64_t cap = TRED_TF_GRID;
@@ -1905,6 +2108,10 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     o += scr;
     P->off_tflag = o;
     o = align256(o + (int64_t)batch * P->nch * (ppad / kTile));
+    P->off_tlist = o;   // live T tiles of a pass (row masks)
+    o = align256(o + (int64_t)batch * P->nch * (ppad / kTileT) * 8);
+    P->off_tcount = o;
+    o = align256(o + 4);
     P->ws_bytes = o;
     P->ws = nullptr;
     P->ready = 0;
@@ -2003,6 +2210,8 @@ tred_status block_conv(const tred_conv_plan* P, const int32_t* n_active, int32_t
     A.tskip = P->pfa;
     A.tflag = (uint8_t*)(ws + P->off_tflag);
     A.rows = rows;
+    int2* tlist = (int2*)(ws + P->off_tlist);
+    int32_t* tcount = (int32_t*)(ws + P->off_tcount);
     auto mark = [&](int b0, int k) {
         if (P->timing && b0 == 0) (void)hipEventRecord(P->ev[k], st);
     };
@@ -2011,7 +2220,7 @@ tred_status block_conv(const tred_conv_plan* P, const int32_t* n_active, int32_t
         const int nb = std::min(pass, cap - b0);
         mark(b0, 0);
         TRED_TRY(dispatch_ft(P->ft, [&](auto ftc) {
-            return launch_time_fwd<decltype(ftc)::value>(A, b0, nb, n_active, blocks, twt, T, st);
+            return launch_time_fwd<decltype(ftc)::value>(A, b0, nb, n_active, blocks, twt, T, tlist, tcount, st);
         }));
         mark(b0, 1);
         mark(b0, 2);

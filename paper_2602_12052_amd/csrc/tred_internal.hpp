@@ -448,6 +448,7 @@ struct tred_conv_plan {
     // workspace layout (byte offsets)
     int64_t off_tw_t, off_tw_s, off_rhat, off_chan, off_scratch_t, off_scratch_u;
     int64_t off_tflag;   // liveness of the time-FFT row groups (one byte each)
+    int64_t off_tlist, off_tcount;   // live T tiles of a pass (int2 each) and their count
     int64_t ws_bytes;
     void* ws;            // bound by set_response
     int ready;
