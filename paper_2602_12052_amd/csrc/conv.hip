@@ -851,6 +851,7 @@ __host__ __device__ inline SppLds spp_lds(int box, int boy) {
     if (a2 > a) a = a2;
     int b = s.ysz;
     if (RS > 1 && s.y2sz > b) b = s.y2sz;
+    if (s.zsz > b) b = s.zsz;   // B also holds the forward stage's second staging buffer
     s.A = even_up(a);
     s.B = even_up(b);
     s.total = s.tw + s.A + s.B;
@@ -897,7 +898,9 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     float2* twl = sm;                       // exp(-2 pi i k / fs)
     float2* regA = sm + Ls.tw;
     float2* regB = regA + Ls.A;
-    float2* zbuf = regA;                    // [NB][NF][NIN px][NIN py]
+    // staged time spectra [NB][NF][NIN px][NIN py] of channels ch (even, odd) in two
+    // buffers: the next channel's are staged while this one's are transformed
+    auto zbs = [&](int ch) { return (ch & 1) ? regB : regA; };
     float2* abuf = regA + Ls.zsz;           // [NB][NF][FS kx][P1 py]
     for (int i = tid; i < FS; i += NT) twl[i] = tws[i];
 
@@ -953,7 +956,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         for (int k = 0; k < ZPT; ++k)
             zpre[k] = buf_f2(tr, (zval[k] & (zfb[k] != 0u)) ? zoff[k] : kOob, 0u);
     };
-    auto store_T = [&]() {
+    auto store_T = [&](float2* zbuf) {
 #pragma unroll
         for (int k = 0; k < ZPT; ++k) {
             const int i = tid + k * NT;
@@ -975,7 +978,9 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     float2 wy[RS];   // W_RS^(j k2) of this thread's rows
 #pragma unroll
     for (int j = 0; j < RS; ++j) wy[j] = twl[((j * k2) % RS) * L];
-    store_T();
+    store_T(zbs(0));
+    load_T(min(1, A.nch - 1));
+    flags(min(2, A.nch - 1));
     __syncthreads();
     const int64_t rstride = (int64_t)A.nc * L * TPF;   // nc * fs * fs values per (ch, f)
     // response spectra of (ch, f0 .. f0 + NF - 1) as row pairs [c][m / 2][item][m % 2]
@@ -984,6 +989,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     static_assert(L % 2 == 0, "row pairs");
 
     for (int ch = 0; ch < A.nch; ++ch) {
+        const float2* zbuf = zbs(ch);
         // x pass: for each (bin, frequency, py, k2x) an L-point DFT over the gathered px
         for (int i = tid; i < NB * NF * NIN * RS; i += NT) {
             const int kk = i % RS;
@@ -1013,10 +1019,14 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         // y pass and multiply-accumulate with the response spectra of every piece. The
         // spectra of piece 0 are requested before the y pass and those of piece c + 1
         // before the multiply-adds of piece c (two register buffers), so L2 latency is
-        // covered by arithmetic; the next channel's time spectra are requested after
-        // piece 0's, so waits for the spectra never wait for them. Everything is
-        // unconditional: pieces past nc load piece nc - 1 again and accumulate into
-        // slots that are never read, the last channel prefetches itself again.
+        // covered by arithmetic. Vector loads complete in issue order, so a wait for
+        // response spectra also waits for every time-spectra load issued before them:
+        // the time spectra of channel ch + 2 are requested after the last piece's
+        // response spectra, which leaves the rest of this channel and the x and y passes
+        // of the next before any wait depends on them, and those of channel ch + 1 are
+        // staged after the y pass. Everything is unconditional: pieces past nc load
+        // piece nc - 1 again and accumulate into slots that are never read, the last
+        // channels request the last channel again.
         const auto rr = buf_rsrc(rhat + ((int64_t)ch * A.ft + f0) * rstride, rbytes);
         auto load_w = [&](float2* wv, int c) {
 #pragma unroll
@@ -1029,12 +1039,9 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         const int clast = A.nc - 1;
         float2 w[2][L];
         load_w(w[0], 0);
-        __builtin_amdgcn_sched_barrier(0);   // vector loads complete in issue order
-        load_T(min(ch + 1, A.nch - 1));
         __builtin_amdgcn_sched_barrier(0);
-        flags(min(ch + 2, A.nch - 1));
+        float2 s[NB][L];
         if (active) {
-            float2 s[NB][L];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const float4* ar4 = (const float4*)(abuf + ((b * NF + fl) * FS + kx) * P1);
@@ -1048,19 +1055,28 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 pfa_gather<L, RS, NIN>(x, wy, s[b]);
                 Dft<L>::run(s[b]);
             }
+        }
+        // channel ch + 1 into the other buffer (the x pass of ch - 1 that read it ended
+        // before this channel's x pass)
+        store_T(zbs(ch + 1));
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (c < NC - 1) load_w(w[(c + 1) & 1], min(c + 1, clast));
-                __builtin_amdgcn_sched_barrier(0);
+        for (int c = 0; c < NC; ++c) {
+            if (c < NC - 1) load_w(w[(c + 1) & 1], min(c + 1, clast));
+            if (c == NC - 2) {
+                __builtin_amdgcn_sched_barrier(0);   // vector loads complete in issue order
+                load_T(min(ch + 2, A.nch - 1));
+                flags(min(ch + 3, A.nch - 1));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (active) {
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
 #pragma unroll
                     for (int m = 0; m < L; ++m)
                         acc[b][c][m] = cfma(s[b][m], w[c & 1][m], acc[b][c][m]);
-                __builtin_amdgcn_sched_barrier(0);
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        store_T();
         __syncthreads();
     }
 
