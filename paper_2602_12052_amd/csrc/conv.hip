@@ -1037,8 +1037,12 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             }
         };
         const int clast = A.nc - 1;
-        float2 w[2][L];
+        // WB register buffers: piece c + WB - 1 is requested before the multiply-adds of
+        // c (three where the registers allow it)
+        constexpr int WB = (RS == 5 || FS == 8) ? 3 : 2;
+        float2 w[WB][L];
         load_w(w[0], 0);
+        if (WB == 3) load_w(w[1], min(1, clast));
         __builtin_amdgcn_sched_barrier(0);
         float2 s[NB][L];
         if (active) {
@@ -1061,8 +1065,8 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         store_T(zbs(ch + 1));
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            if (c < NC - 1) load_w(w[(c + 1) & 1], min(c + 1, clast));
-            if (c == NC - 2) {
+            if (c + WB - 1 < NC) load_w(w[(c + WB - 1) % WB], min(c + WB - 1, clast));
+            if (c == (NC > WB ? NC - WB : 0)) {   // after the last piece's request (and store_T)
                 __builtin_amdgcn_sched_barrier(0);   // vector loads complete in issue order
                 load_T(min(ch + 2, A.nch - 1));
                 flags(min(ch + 3, A.nch - 1));
@@ -1073,7 +1077,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 for (int b = 0; b < NB; ++b)
 #pragma unroll
                     for (int m = 0; m < L; ++m)
-                        acc[b][c][m] = cfma(s[b][m], w[c & 1][m], acc[b][c][m]);
+                        acc[b][c][m] = cfma(s[b][m], w[c % WB][m], acc[b][c][m]);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
