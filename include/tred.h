@@ -306,7 +306,7 @@ tred_status tred_block_conv_direct(const tred_direct_plan* plan, const int32_t* 
 void tred_direct_plan_destroy(tred_direct_plan* plan);
 
 /* ------------------------------------------------------------------------- */
-/* Gradients (Sec. V-A: the simulation is differentiable, e.g. to fit the electron
+/* Gradients (Sec. V-C: the simulation is differentiable, e.g. to fit the electron
  * lifetime). Each call is the transpose of the forward call of the same name for
  * the same inputs, plan, keys, pixel list and capacities: given dL/d(its outputs)
  * it returns dL/d(its inputs). Chained backwards they give dL/d(depositions) and

@@ -1297,7 +1297,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
 }
 
 // ===========================================================================
-// Transpose of the convolution (gradients, Sec. V-A). For one bin the forward map is
+// Transpose of the convolution (gradients, Sec. V-C). For one bin the forward map is
 //   out = OLA_c Re F_t^H Unpack Crop F_xy^H ( sum_ch Rhat[ch][c] F_xy F_t Pack(Q_ch) )
 // with F the unnormalised DFT (the 1/N factors live in Rhat). Its transpose (real
 // inner products) runs the same stages backwards:

@@ -545,7 +545,7 @@ void launch_effq(const EffqParams& P, int64_t n_dep, const float* seg, const int
 }
 
 // ---------------------------------------------------------------------------
-// Gradient of the effective charge (Sec. V-A). The node charge q = Qp g(r, D, sigma)
+// Gradient of the effective charge (Sec. V-C). The node charge q = Qp g(r, D, sigma)
 // is differentiated in forward mode with respect to the node offset r (3), the
 // segment vector D (3) and the widths sigma (3) (dual numbers, binary32); per node the
 // gradient of the loss with respect to its charge is the transposed trilinear spread

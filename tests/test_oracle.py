@@ -155,16 +155,149 @@ def test_point_switch_threshold(orc):
         assert ip == expect
 
 
-def test_transport_definition(orc):
-    ph = W.Physics()
-    seg = np.array([0.0, 0.0, 10.0, 0.1, 0.0, 30.0, 5.0e3], np.float32)
-    tr = orc.transport(ph, seg)
-    v = float(np.float32(0.16))
-    tm = 0.5 * (float(seg[2]) + float(seg[5])) / v
-    assert abs(tr[2] - tm) < 1e-12 * tm
-    assert abs(tr[3] - float(seg[6]) * math.exp(-tm / float(np.float32(2200.0)))) < 1e-9
-    assert abs(tr[4] - math.sqrt(2 * float(np.float32(8.8e-6)) * tm)) < 1e-14
-    assert abs(tr[6] - math.sqrt(2 * float(np.float32(4.0e-6)) * tm) / v) < 1e-12
+def _moments(fp, Q):
+    """Total, mean and variance (in cell-index units) of a patch along each axis."""
+    tot = Q.sum()
+    out = []
+    for a in range(3):
+        marg = Q.sum(axis=tuple(b for b in range(3) if b != a))
+        g = np.arange(fp[a], fp[3 + a] + 1, dtype=np.float64)
+        m = float((marg * g).sum() / tot)
+        out.append((m, float((marg * (g - m) ** 2).sum() / tot)))
+    return tot, out
+
+
+def _tent_variance(n):
+    """Mean over the n Gauss-Legendre nodes of f (1 - f), f = |xi| / 2: the variance the
+    trilinear spread adds (in cell units) to a density that is smooth on the cell scale.
+    A node at offset f from its cell's grid point pushes 1 - f there and f to the
+    neighbour, so its second moment grows by f (1 - f); summed over all cells of a density
+    whose width is several cells, each node offset samples the density's integral."""
+    X, Wt = np.polynomial.legendre.leggauss(n)
+    f = np.abs(X) / 2.0
+    return float(np.sum(Wt / 2.0 * f * (1.0 - f)))
+
+
+def _transport_probe(orc, seg, n_gl=2, sigma_min=None, npix=12, h=0.02, nticks=1200):
+    """Patch of one deposition on a fine grid (h = 0.02 cm) centred on it, with windows
+    of 8 widths so that the truncated tails are below 1e-14."""
+    zc = 0.5 * (float(seg[2]) + float(seg[5]))
+    t0 = zc / float(np.float32(0.16)) - nticks * 0.05 / 2
+    g = W.Grid(origin=(0.0, 0.0, float(np.float32(t0))), spacing=(h, h, 0.05), npix=(npix, npix),
+               sub=(10, 10), nticks=nticks)
+    smin = sigma_min or (0.1 * h, 0.1 * h, 0.1 * 0.05)
+    ph = W.Physics(sigma_min=smin, n_sigma=8.0, n_gl=n_gl)
+    s = np.asarray(seg, np.float32)
+    fp, off, ip = orc.footprints(g, ph, s)
+    N = g.nfine
+    assert (fp[0, :3] > 0).all() and (fp[0, 3:] < np.array(N) - 1).all(), "patch must be interior"
+    val, _ = orc.effq(g, ph, s, fp, off)
+    shape = tuple(int(fp[0, 3 + a] - fp[0, a] + 1) for a in range(3))
+    return g, ph, fp[0], val.reshape(shape), bool(ip[0])
+
+
+# Transport constants as the oracle receives them (binary32 inputs, exact in binary64).
+_V = float(np.float32(0.16))
+_TAU = float(np.float32(2200.0))
+_DT = float(np.float32(8.8e-6))
+_DL = float(np.float32(4.0e-6))
+
+
+@pytest.mark.parametrize("z,n_gl", [(20.0, 2), (40.0, 2), (32.0, 3)])
+def test_transport_point_moments(orc, z, n_gl):
+    """A point deposition after drift z (Sec. II-A): the effective charge carries the
+    surviving charge Q exp(-t/tau_e) and is a Gaussian of variance 2 D_T t (x, y, in
+    cm^2) and 2 D_L t / v^2 (t, in us^2) with t = z / v, plus the tent variance of the
+    trilinear spread. Read off the oracle's patch only (no call of its transport)."""
+    x, y = 1.2203, 1.1311
+    seg = np.array([x, y, z, x, y, z, 1.0e4], np.float32)
+    g, ph, fp, Q, ip = _transport_probe(orc, seg, n_gl=n_gl)
+    assert ip
+    t = float(np.float32(z)) / _V
+    tot, mom = _moments(fp, Q)
+    assert abs(tot / (1.0e4 * math.exp(-t / _TAU)) - 1.0) < 1e-10
+    c = _tent_variance(n_gl)
+    h = [float(np.float32(s)) for s in g.spacing]
+    exp_var = [2 * _DT * t, 2 * _DT * t, 2 * _DL * t / _V ** 2]
+    for a in range(3):
+        var = (mom[a][1] - c) * h[a] ** 2
+        assert abs(var / exp_var[a] - 1.0) < 1e-8, (a, var, exp_var[a])
+    # the centre sits at the deposition (grid point i at (i + 1/2) h, tick n at t0 + n tick)
+    assert abs(g.origin[0] + (mom[0][0] + 0.5) * h[0] - float(np.float32(x))) < 1e-9
+    assert abs(g.origin[1] + (mom[1][0] + 0.5) * h[1] - float(np.float32(y))) < 1e-9
+    assert abs(float(np.float32(g.origin[2])) + mom[2][0] * h[2] - t) < 1e-7
+
+
+def test_transport_attenuation_ratio(orc):
+    """Charge surviving two drift distances differs by exp(-dz / (v tau_e))."""
+    tots = []
+    for z in (12.0, 44.0):
+        seg = np.array([1.21, 1.23, z, 1.21, 1.23, z, 3.0e3], np.float32)
+        _, _, fp, Q, _ = _transport_probe(orc, seg)
+        tots.append(Q.sum())
+    assert abs(tots[1] / tots[0] / math.exp(-32.0 / (_V * _TAU)) - 1.0) < 1e-10
+
+
+def test_transport_line_along_drift_uses_mid_time(orc):
+    """A segment along the drift direction (Sec. II-C: one width per segment): the
+    transverse variance is 2 D_T t_mid at its mid drift time, the variance along t is
+    the segment's duration squared / 12 plus 2 D_L t_mid / v^2, and the surviving charge
+    is Q exp(-t_mid / tau_e)."""
+    x, y, z0, z1 = 1.1977, 1.2048, 19.0, 21.0
+    seg = np.array([x, y, z0, x, y, z1, 2.0e4], np.float32)
+    g, ph, fp, Q, ip = _transport_probe(orc, seg, nticks=1200)
+    assert not ip
+    t0, t1 = float(np.float32(z0)) / _V, float(np.float32(z1)) / _V
+    tm = 0.5 * (t0 + t1)
+    tot, mom = _moments(fp, Q)
+    assert abs(tot / (2.0e4 * math.exp(-tm / _TAU)) - 1.0) < 1e-10
+    c = _tent_variance(2)
+    h = [float(np.float32(s)) for s in g.spacing]
+    for a in range(2):
+        assert abs((mom[a][1] - c) * h[a] ** 2 / (2 * _DT * tm) - 1.0) < 1e-8
+    var_t = (mom[2][1] - c) * h[2] ** 2
+    assert abs(var_t / ((t1 - t0) ** 2 / 12.0 + 2 * _DL * tm / _V ** 2) - 1.0) < 1e-8
+
+
+def test_transport_width_floor(orc):
+    """Widths below the minimum diffusion scale are raised to it, per axis (x, y to
+    0.07 cm, t to 0.3 us here, both above the diffused widths at 20 cm)."""
+    seg = np.array([1.19, 1.22, 20.0, 1.19, 1.22, 20.0, 1.0e4], np.float32)
+    smin = (0.07, 0.07, 0.3)
+    g, ph, fp, Q, ip = _transport_probe(orc, seg, sigma_min=smin)
+    t = float(np.float32(20.0)) / _V
+    assert 2 * _DT * t < 0.07 ** 2 and 2 * _DL * t / _V ** 2 < 0.3 ** 2
+    tot, mom = _moments(fp, Q)
+    c = _tent_variance(2)
+    h = [float(np.float32(s)) for s in g.spacing]
+    for a in range(3):
+        var = (mom[a][1] - c) * h[a] ** 2
+        assert abs(var / float(np.float32(smin[a])) ** 2 - 1.0) < 1e-8, a
+    # the floor changes the shape only: the surviving charge is unchanged
+    assert abs(tot / (1.0e4 * math.exp(-t / _TAU)) - 1.0) < 1e-10
+
+
+def test_select_near_keeps_every_contributor(orc):
+    """The depositions select_near keeps for a set of samples give the same waveform
+    values there as all depositions, and each one it drops contributes exactly zero."""
+    g, ph, seg, fp, off, val = _small_event(orc, n=30, nticks=96)
+    K, kt = (3, 5), 24
+    R = np.abs(W.random_symmetric_response(K, g.sub, kt, seed=4)) + 0.1
+    rng = np.random.default_rng(3)
+    pts = np.stack([rng.integers(0, 6, 8), rng.integers(0, 6, 8), rng.integers(0, 96 + kt - 1, 8)], 1)
+    ids = np.stack([pts[:, 0] * g.npix[1] + pts[:, 1], pts[:, 2]], 1)
+    near = orc.select_near(fp, g.sub, K, kt, pts)
+    assert 0 < len(near) < fp.shape[0]
+    full = orc.waveform_points(g, K, kt, R, fp, off, val, ids)
+    vol = np.prod(np.maximum(fp[near, 3:] - fp[near, :3] + 1, 0), axis=1)
+    soff = np.concatenate([[0], np.cumsum(vol)]).astype(np.int64)
+    sval = np.concatenate([val[off[d]:off[d + 1]] for d in near])
+    part = orc.waveform_points(g, K, kt, R, fp[near], soff, sval, ids)
+    assert np.array_equal(part, full)
+    for d in sorted(set(range(fp.shape[0])) - set(near.tolist())):
+        one = orc.waveform_points(g, K, kt, R, fp[d:d + 1], np.array([0, off[d + 1] - off[d]]),
+                                  val[off[d]:off[d + 1]], ids)
+        assert not one.any(), d
 
 
 # ---------------------------------------------------------------------------
@@ -611,3 +744,89 @@ def test_accuracy_study_gl2_beats_grid_sampling(orc):
     devg = np.max(np.abs(acc["grid"] - acc[4]))
     assert dev2 < 0.2 * devg
     assert dev2 < 500.0
+
+
+# ---------------------------------------------------------------------------
+# Host sanitizer build of the oracle
+# ---------------------------------------------------------------------------
+
+
+def test_oracle_under_address_and_ub_sanitizers(orc, tmp_path):
+    """oracle.c built with the address and undefined-behaviour sanitizers (no OpenMP)
+    runs every entry point on a small event with a point-like deposition, one that
+    misses the region and ones cut by the region edges, without a report, and gives
+    the regular build's outputs."""
+    import shutil
+    import struct
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    here = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+    exe = str(tmp_path / "oracle_san")
+    subprocess.check_call([gcc, "-std=c11", "-D_DEFAULT_SOURCE", "-O1", "-g", "-ffp-contract=off",
+                           "-fno-fast-math", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-o", exe,
+                           os.path.join(here, "oracle.c"), os.path.join(here, "sanitize_main.c"),
+                           "-lm"])
+    g = tiny_grid(npix=6, sub=3, nticks=96, h=0.44 / 3)
+    ph = phys_for(g)
+    blk = W.Blocking((2, 4), 32)
+    K, kt = (3, 5), 24
+    seg = W.gen_uniform_segments(12, (6 * 0.44, 6 * 0.44), (0.1, 96 * 0.05 * 0.16 - 0.1), seed=2)
+    seg = np.concatenate([seg, np.array([
+        [1.0, 1.1, 0.4, 1.0, 1.1, 0.4, 5e3],           # point-like
+        [-3.0, 1.0, 0.3, -2.9, 1.0, 0.31, 5e3],        # outside the region
+        [0.01, 2.62, 0.02, 0.05, 2.60, 0.03, 5e3],      # x, y and t edges
+    ], np.float32)]).astype(np.float32)
+    R = W.random_symmetric_response(K, g.sub, kt, seed=4)
+    rng = np.random.default_rng(1)
+    pts = np.stack([rng.integers(0, 36, 20), rng.integers(0, 96 + kt - 1, 20)], 1).astype(np.int32)
+    og, oph, ob = orc.ogrid(g), orc.ophysics(ph), orc.oblocking(blk)
+    with open(tmp_path / "in.bin", "wb") as f:
+        f.write(bytes(og) + bytes(oph) + bytes(ob))
+        f.write(struct.pack("<iii", K[0], K[1], kt))
+        f.write(struct.pack("<q", seg.shape[0]) + seg.tobytes() + R.tobytes())
+        f.write(struct.pack("<q", pts.shape[0]) + pts.tobytes())
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    p = subprocess.run([exe, str(tmp_path / "in.bin"), str(tmp_path / "out.bin")], env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert p.returncode == 0, p.stderr[-4000:]
+    assert "runtime error" not in p.stderr and "AddressSanitizer" not in p.stderr, p.stderr[-4000:]
+    buf = (tmp_path / "out.bin").read_bytes()
+    pos = 0
+
+    def take(dtype, count):
+        nonlocal pos
+        a = np.frombuffer(buf, dtype=dtype, count=count, offset=pos)
+        pos += a.nbytes
+        return a
+
+    n = seg.shape[0]
+    nk = int(take(np.int64, 1)[0])
+    keys = take(np.int32, 3 * nk).reshape(nk, 3)
+    fp = take(np.int32, 6 * n).reshape(n, 6)
+    off = take(np.int64, n + 1)
+    ip = take(np.int32, n)
+    val = take(np.float64, int(off[-1]))
+    ns = take(np.float64, n)
+    vblk = 2 * 3 * 4 * 3 * 32
+    bv = take(np.float64, vblk * nk).reshape(nk, vblk)
+    npx = int(take(np.int64, 1)[0])
+    take(np.int32, npx)
+    wf = take(np.float64, npx * (96 + kt - 1)).reshape(npx, -1)
+    po = take(np.float64, pts.shape[0])
+    assert pos + 8 * (27 + 16 + 2) == len(buf)
+    ref = orc.simulate(g, ph, blk, K, kt, R, seg)
+    assert np.array_equal(fp, ref["fp"]) and np.array_equal(off, ref["off"])
+    assert np.array_equal(ip, ref["is_point"]) and ip[12] == 1 and off[14] == off[13]
+    assert np.array_equal(keys, ref["keys"])
+    close = lambda a, b: np.max(np.abs(a - b)) <= 1e-13 * max(np.abs(b).max(), 1e-300)
+    assert close(val, ref["val"]) and close(ns, ref["node_sums"])
+    allpix = np.arange(36, dtype=np.int32)
+    assert close(wf, orc.waveforms(g, K, kt, R, ref["fp"], ref["off"], ref["val"], allpix))
+    assert close(po, orc.waveform_points(g, K, kt, R, ref["fp"], ref["off"], ref["val"], pts))
+    for k in range(nk):
+        assert close(bv[k], orc.block_values(g, blk, ref["fp"], ref["off"], ref["val"],
+                                              keys[k]).ravel())
