@@ -133,7 +133,21 @@ def cpu_baseline(cfg, seg, resp, n_sample, seed=0):
     dt = time.perf_counter() - t
     return dict(value=n_sample / dt, unit="depositions/s", cores=oracle.num_threads(), kind="oracle",
                 sample=f"{n_sample} random depositions of the same event (seed {seed}), whole path "
-                       f"(effective charge, binning, direct convolution, waveforms): {dt:.1f} s")
+                       f"(effective charge, binning, direct convolution, waveforms): {dt:.1f} s",
+                host_cpu=host_cpu_model(), nproc=os.cpu_count(),
+                affinity=len(os.sched_getaffinity(0)))
+
+
+def host_cpu_model():
+    """Model name of the host CPU (from /proc/cpuinfo, as lscpu prints it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_direct(args, split):
@@ -242,14 +256,14 @@ def bench_adjoint(args):
         ev.record(0, stream)
         pl.run(sd)
         ev.record(1, stream)
-        n = pl.n_pix                          # device scalar; rows past it stay zero
+        n = pl.n_pix                          # device scalar; wf rows past it are zero
         rows = torch.arange(pl.pix.shape[0], device="cuda")
         live = rows < n
         j = torch.searchsorted(tpix, pl.pix).clamp_(max=max(nt - 1, 0))
         hit = live & (tpix[j] == pl.pix) if nt > 0 else torch.zeros_like(live)
         target = torch.where(hit[:, None], twf[j], torch.zeros((), device="cuda"))
         torch.sub(pl.wf, target, out=d_wf)
-        d_wf.mul_(live[:, None])
+        d_wf.masked_fill_(~live[:, None], 0.0)
         loss.copy_(0.5 * (d_wf.double() ** 2).sum())
         pl.backward(sd, d_wf)
         ev.record(2, stream)

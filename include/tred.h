@@ -49,6 +49,10 @@ const char* tred_status_string(int status);
 /* Detail of the last non-OK status returned on the calling host thread ("" if none). */
 const char* tred_last_error(void);
 int tred_abi_version(void);
+/* Identity of the build: the hex SHA-256 of the sources (every file of csrc/ and
+ * this header), compiler flags and defines it was compiled from ("unversioned"
+ * when built without one). A binding compares it with its source tree. */
+const char* tred_build_id(void);
 
 /* Fine sampling grid of the field response (Sec. II-B, II-C): each pixel of
  * pitch a is divided into sub[0] x sub[1] impact cells of size
@@ -229,7 +233,8 @@ tred_status tred_block_conv_rows(const tred_conv_plan* plan, const int32_t* n_ac
  * sum of all block outputs covering it.
  * pix [pix_cap] out: pixel ids px * npix[1] + py, ascending; n_pix out (device).
  * wf  [pix_cap][nticks + kticks - 1] out: current waveform of pix[i], tick 0 first
- *     (ticks past the end of the readout window carry the response tail).
+ *     (ticks past the end of the readout window carry the response tail); rows
+ *     i >= *n_pix are set to zero, so every row of wf is defined after the call.
  * work: device workspace of tred_scatter_workspace() bytes. */
 int64_t tred_scatter_workspace(const tred_conv_plan* plan);
 tred_status tred_scatter_waveforms(const tred_conv_plan* plan, const int32_t* keys,

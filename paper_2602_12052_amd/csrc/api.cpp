@@ -35,3 +35,9 @@ extern "C" const char* tred_status_string(int s) {
 extern "C" const char* tred_last_error(void) { return g_err; }
 
 extern "C" int tred_abi_version(void) { return TRED_ABI_VERSION; }
+
+#ifndef TRED_BUILD_ID
+#define TRED_BUILD_ID "unversioned"
+#endif
+
+extern "C" const char* tred_build_id(void) { return TRED_BUILD_ID; }

@@ -87,8 +87,9 @@ __global__ __launch_bounds__(1024) void k_compact_pix(ScatArgs S, int32_t* __res
     if (tid == 0) *n_pix = carry;
 }
 
-// One workgroup per pixel slot. Its threads walk the waveform in spans of 1024 ticks,
-// four ticks per thread, so the pixel's bin lookups are made once per span. Per
+// One workgroup per pixel slot (slots at or past n_pix get a zero waveform). Its threads
+// walk the waveform in spans of 1024 ticks, four ticks per thread, so the pixel's bin
+// lookups are made once per span. Per
 // sample the covering bins are summed in (bx, by, bt) order. The loads carry no
 // branches, so a thread keeps the loads of four bins in flight: each block-output row
 // is read through a buffer resource of its own length (ticks outside it read zero),
@@ -102,7 +103,12 @@ __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __res
                                                 const float* __restrict__ outb,
                                                 float* __restrict__ wf) {
     const int slot = blockIdx.x;
-    if (slot >= min(*n_pix, S.pix_cap)) return;
+    if (slot >= min(*n_pix, S.pix_cap)) {
+        // slots without a pixel hold a zero waveform, so every row of wf is defined
+        float* zrow = wf + (int64_t)slot * S.lwf;
+        for (int T = threadIdx.x; T < S.lwf; T += 256) zrow[T] = 0.0f;
+        return;
+    }
     const int64_t npix = (int64_t)S.npx * S.npy;
     const int e = (int)(pix[slot] / npix);
     const int p = (int)(pix[slot] % npix);

@@ -13,8 +13,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# TRED_LIBRARY selects another build of the same library (A/B comparisons of kernels)
-LIB_PATH = os.environ.get("TRED_LIBRARY") or os.path.join(_HERE, "libtred.so")
+LIB_PATH = os.path.join(_HERE, "libtred.so")
 
 TRED_OK, TRED_EINVAL, TRED_ECAPACITY, TRED_EDEVICE, TRED_EUNSUPPORTED = range(5)
 TRED_CONV_MPCP = 1
@@ -63,7 +62,8 @@ def blocking_struct(b) -> Blocking:
 
 
 EXPORTS = [
-    "tred_status_string", "tred_last_error", "tred_abi_version", "tred_effq_windows", "tred_effq",
+    "tred_status_string", "tred_last_error", "tred_abi_version", "tred_build_id",
+    "tred_effq_windows", "tred_effq",
     "tred_block_count", "tred_block_bin_workspace", "tred_block_bin", "tred_conv_plan_create",
     "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
@@ -80,14 +80,21 @@ _lib = None
 
 
 def lib():
-    """Load libtred.so; raises if it has not been built."""
+    """Load libtred.so; raises if it has not been built, or if it was built from
+    other sources than the tree's (its tred_build_id() differs)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2602_12052_amd.build.build()")
+    from . import build as _build
     L = C.CDLL(LIB_PATH)
     P, I32, I64, U32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+    L.tred_build_id.restype = C.c_char_p
+    want, got = _build.source_id(), L.tred_build_id().decode()
+    if got != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (build id {got[:16]}, "
+                          f"tree {want[:16]}): rebuild it with paper_2602_12052_amd.build.build()")
     L.tred_status_string.argtypes = [C.c_int]
     L.tred_status_string.restype = C.c_char_p
     L.tred_last_error.restype = C.c_char_p
@@ -581,10 +588,20 @@ class Pipeline:
                           self.d_phys, stream)
         return self.d_seg, self.d_phys
 
+    def check_capacity(self, n_dep=None):
+        """Raise TredError(TRED_ECAPACITY) if the last run overflowed a capacity (the
+        patch length off[n], the active-bin count or the pixel count exceeds the
+        buffer it was given, so part of the event was dropped). Synchronises."""
+        n = self.n_dep if n_dep is None else int(n_dep)
+        _check_counts(int(self.off[n].item()), self.val.numel(), int(self.n_active.item()),
+                      self.keys.shape[0], int(self.n_pix.item()), self.pix.shape[0])
+
     def results(self):
-        """Host copies of the outputs (synchronises)."""
+        """Host copies of the outputs (synchronises); raises TredError if the run
+        overflowed a capacity."""
         import torch
         torch.cuda.synchronize()
+        self.check_capacity()
         na = int(self.n_active.item())
         npx = int(self.n_pix.item())
         nval = int(self.off[-1].item())
@@ -594,6 +611,18 @@ class Pipeline:
                     keys=self.keys[:min(na, self.keys.shape[0])].cpu().numpy(), n_pix=npx,
                     pix=self.pix[:min(npx, self.pix.shape[0])].cpu().numpy(),
                     wf=self.wf[:min(npx, self.pix.shape[0])].cpu().numpy())
+
+
+def _check_counts(nval, val_cap, na, block_cap, npx, pix_cap):
+    over = []
+    if nval > val_cap:
+        over.append(f"patch cells {nval} > val capacity {val_cap}")
+    if na > block_cap:
+        over.append(f"active bins {na} > bin capacity {block_cap}")
+    if npx > pix_cap:
+        over.append(f"pixels {npx} > pixel capacity {pix_cap}")
+    if over:
+        raise TredError(TRED_ECAPACITY, "run truncated: " + "; ".join(over))
 
 
 def tred_block_bin_events_rows(grid, blocking, ev_off, fp, off, val, keys, n_active, blocks, rows,
@@ -685,12 +714,18 @@ class BatchPipeline:
                                       self.pix, self.n_pix, self.wf, self.scat_work, stream)
 
     def results(self, n_dep=None):
-        """Host copies of the outputs of the last run (synchronises)."""
+        """Host copies of the outputs of the last run (synchronises); n_dep: depositions
+        of that run. Raises TredError if the run overflowed a capacity."""
         import torch
         torch.cuda.synchronize()
         n = self.n_dep_max if n_dep is None else int(n_dep)
         na = int(self.n_active.item())
         npx = int(self.n_pix.item())
+        if n_dep is not None:
+            _check_counts(int(self.off[n].item()), self.val.numel(), na, self.keys.shape[0],
+                          npx, self.pix.shape[0])
+        else:
+            _check_counts(0, 0, na, self.keys.shape[0], npx, self.pix.shape[0])
         return dict(fp=self.fp[:n].cpu().numpy(), off=self.off[:n + 1].cpu().numpy(),
                     n_active=na, keys=self.keys[:min(na, self.keys.shape[0])].cpu().numpy(),
                     n_pix=npx, pix=self.pix[:min(npx, self.pix.shape[0])].cpu().numpy(),
@@ -783,8 +818,12 @@ def simulate(seg, resp, grid, phys, blocking, kpix, kticks, fft=None, mpcp=True,
 class Simulate:
     """torch.autograd.Function over a Pipeline: waveforms of the depositions seg
     (float32 [n][7] on the GPU, requires_grad for d/d(end points, charge)). The pixel
-    list of the forward pass fixes the waveform rows; backward returns dL/dseg and
-    accumulates dL/d(diff_T, diff_L, lifetime) into pipeline.d_phys."""
+    list of the forward pass fixes the waveform rows (pipeline.pix[:n_pix]); rows at
+    or past n_pix are zero and carry no gradient. backward returns dL/dseg and
+    writes dL/d(diff_T, diff_L, lifetime) into pipeline.d_phys. The forward pass
+    synchronises once to check the capacities: a run that would drop part of the
+    event (depositions moved outside the sizes the pipeline was built for) raises
+    TredError instead of returning truncated waveforms."""
 
     @staticmethod
     def apply(pipeline, seg):
@@ -794,6 +833,7 @@ class Simulate:
             @staticmethod
             def forward(ctx, s):
                 pipeline.run(s)
+                pipeline.check_capacity()
                 ctx.save_for_backward(s)
                 return pipeline.wf.clone()
 

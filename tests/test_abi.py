@@ -33,6 +33,17 @@ def test_exports_every_declared_symbol(T):
     assert set(names) == set(T.EXPORTS)
 
 
+def test_build_id_matches_tree(T):
+    """The loaded library was compiled from the tree's sources and flags: its
+    tred_build_id() equals the hash of csrc/ and include/tred.h computed here."""
+    from paper_2602_12052_amd import build as B
+    got = T.lib().tred_build_id().decode()
+    assert got == B.source_id()
+    assert len(got) == 64
+    # a variant build (other defines) carries another id and would be refused
+    assert B.source_id(("TRED_SOME_SWITCH=1",)) != got
+
+
 def test_abi_version_and_status_strings(T):
     L = T.lib()
     assert L.tred_abi_version() == 1
@@ -209,3 +220,4 @@ def test_direct_conv_requires_response(T):
     assert T.lib().tred_block_conv_direct(h, na, 4, na, na, None) == T.TRED_EINVAL
     assert b"set_response" in T.lib().tred_last_error()
     T.lib().tred_direct_plan_destroy(h)
+

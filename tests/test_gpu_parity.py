@@ -475,3 +475,82 @@ def test_module_sampled_waveforms(module_run, orc):
     e = rel_l2(got, ref)
     say(f"  rel-L2 sampled waveforms {e:.2e} (|ref| max {np.abs(ref).max():.3e})")
     assert e < TOL
+
+
+def test_module_whole_waveforms(module_run, orc):
+    """Whole waveforms (all nticks + Kt - 1 = 8,297 ticks) of 16 pixels of the module
+    event against the oracle's direct sum over every deposition that reaches them:
+    four region-edge pixels, four in the output footprint of the last active bin (the
+    last key, so the tail workgroup of the paired spatial stage), four holding charge
+    in the partial last time bin (ticks 6,144-6,249) and four drawn at random. Every
+    pixel holds charge directly (a footprint covers it); pixels whose oracle sum
+    would exceed about 1.5e6 reaching cells (3e6 for the late ones) are passed over
+    to bound the oracle's time."""
+    say("test_module_whole_waveforms")
+    cfg, seg, resp, r = module_run
+    g, blk = cfg.grid, cfg.blocking
+    ofp, ooff, _ = orc.footprints(g, cfg.physics, seg)
+    pix = r["pix"]
+    npy = g.npix[1]
+    L = g.nticks + cfg.kticks - 1
+    hx, hy = (cfg.kpix[0] - 1) // 2, (cfg.kpix[1] - 1) // 2
+    vol = np.prod(np.maximum(ofp[:, 3:] - ofp[:, :3] + 1, 0), axis=1)
+    px0, px1 = ofp[:, 0] // g.sub[0], ofp[:, 3] // g.sub[0]
+    py0, py1 = ofp[:, 1] // g.sub[1], ofp[:, 4] // g.sub[1]
+    direct = np.zeros(g.npix, bool)
+    late = np.zeros(g.npix, bool)
+    last_bin = g.nticks // blk.blk_ticks * blk.blk_ticks
+    for d in np.nonzero(vol > 0)[0]:
+        direct[px0[d]:px1[d] + 1, py0[d]:py1[d] + 1] = True
+        if ofp[d, 5] >= last_bin:
+            late[px0[d]:px1[d] + 1, py0[d]:py1[d] + 1] = True
+    px, py = pix // npy, pix % npy
+
+    def cost(i):
+        x, y = px[i], py[i]
+        m = (px0 <= x + hx) & (px1 >= x - hx) & (py0 <= y + hy) & (py1 >= y - hy)
+        return int(vol[m].sum())
+
+    rng = np.random.default_rng(4)
+    sel = []
+
+    def pick(cands, k, cap=1.5e6):
+        got = 0
+        for i in rng.permutation(cands):
+            if got == k:
+                break
+            if i in sel or not direct[px[i], py[i]] or cost(i) > cap:
+                continue
+            sel.append(int(i))
+            got += 1
+        assert got == k
+
+    pick(np.nonzero((px == 0) | (py == 0) | (px == g.npix[0] - 1) | (py == npy - 1))[0], 4)
+    kb = r["keys"][-1]
+    x0, x1 = kb[0] * blk.blk_pix[0] - hx, kb[0] * blk.blk_pix[0] + blk.blk_pix[0] - 1 + hx
+    y0, y1 = kb[1] * blk.blk_pix[1] - hy, kb[1] * blk.blk_pix[1] + blk.blk_pix[1] - 1 + hy
+    pick(np.nonzero((px >= x0) & (px <= x1) & (py >= y0) & (py <= y1))[0], 4)
+    pick(np.nonzero(late[px, py])[0], 4, cap=3e6)
+    pick(np.arange(len(pix)), 4)
+    ids = pix[sel]
+    near = orc.select_near(ofp, g.sub, cfg.kpix, L,
+                           np.stack([ids // npy, ids % npy, np.full(len(ids), L - 1)], 1))
+    sfp = ofp[near]
+    svol = np.prod(np.maximum(sfp[:, 3:] - sfp[:, :3] + 1, 0), axis=1)
+    soff = np.concatenate([[0], np.cumsum(svol)]).astype(np.int64)
+    sval, _ = orc.effq(g, cfg.physics, seg[near], sfp, soff)
+    ref = orc.waveforms(g, cfg.kpix, cfg.kticks, resp, sfp, soff, sval, ids)
+    got = r["wf"][sel]
+    assert got.shape == ref.shape == (16, L)
+    per = [rel_l2(got[i], ref[i]) for i in range(16)]
+    say(f"  {len(near)} depositions reach the 16 pixels; per-pixel rel-L2 "
+        + " ".join(f"{e:.1e}" for e in per))
+    for name, rows in (("region edge", slice(0, 4)), ("last bin", slice(4, 8)),
+                       ("late ticks", slice(8, 12)), ("random", slice(12, 16))):
+        e = rel_l2(got[rows], ref[rows])
+        say(f"  {name}: rel-L2 {e:.2e}")
+        assert e < TOL, name
+    e_late = rel_l2(got[8:12, last_bin:], ref[8:12, last_bin:])
+    say(f"  ticks >= {last_bin} of the late pixels: rel-L2 {e_late:.2e}")
+    assert e_late < TOL
+    assert rel_l2(got, ref) < TOL

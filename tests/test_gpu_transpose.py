@@ -397,3 +397,43 @@ def test_autograd_function(T):
     ref, _ = pl.backward(sd, c)
     torch.cuda.synchronize()
     assert torch.allclose(x.grad, ref, rtol=1e-6, atol=0)
+
+
+def test_simulate_whole_output_and_capacity(T):
+    """Simulate's output is defined on every row: with the waveform buffer pre-filled
+    with NaN, a loss over the whole output (rows past n_pix included, with nonzero
+    weights) is finite, those rows are zero, and the gradient equals the one of the
+    loss over the n_pix live rows. A pipeline whose patch capacity is too small for
+    the depositions raises a capacity error instead of returning truncated output."""
+    import torch
+    say("test_simulate_whole_output_and_capacity")
+    g, ph, blk, kpix, kticks, fft, seg = grad_cfg()
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=11)
+    sd = dev(seg)
+    val_cap, bcap, pix_cap = T.size_event(g, ph, blk, kpix, sd)
+    pl = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap, bcap,
+                    pix_cap + 7, fft, True, 8)
+    pl.wf.fill_(float("nan"))
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    c = torch.randn(pl.wf.shape, device="cuda", generator=gen)
+    x = sd.clone().requires_grad_(True)
+    wf = T.Simulate.apply(pl, x)
+    npx = int(pl.n_pix.item())
+    assert npx < wf.shape[0]
+    assert torch.isfinite(wf).all() and (wf[npx:] == 0).all()
+    loss = (wf * c).sum()
+    assert torch.isfinite(loss)
+    loss.backward()
+    c_live = c.clone()
+    c_live[npx:] = 0
+    ref, _ = pl.backward(sd, c_live)
+    torch.cuda.synchronize()
+    assert torch.isfinite(x.grad).all()
+    assert torch.allclose(x.grad, ref, rtol=1e-6, atol=0)
+    small = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap // 2, bcap,
+                       pix_cap, fft, True, 8)
+    with pytest.raises(T.TredError) as e:
+        T.Simulate.apply(small, sd.clone().requires_grad_(True))
+    assert e.value.status == T.TRED_ECAPACITY
+    with pytest.raises(T.TredError):
+        small.results()
