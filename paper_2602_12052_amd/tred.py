@@ -596,12 +596,14 @@ class Pipeline:
         _check_counts(int(self.off[n].item()), self.val.numel(), int(self.n_active.item()),
                       self.keys.shape[0], int(self.n_pix.item()), self.pix.shape[0])
 
-    def results(self):
+    def results(self, check=True):
         """Host copies of the outputs (synchronises); raises TredError if the run
-        overflowed a capacity."""
+        overflowed a capacity, unless `check` is False (then the truncated outputs
+        are returned: the first capacity-many bins and pixels in key order)."""
         import torch
         torch.cuda.synchronize()
-        self.check_capacity()
+        if check:
+            self.check_capacity()
         na = int(self.n_active.item())
         npx = int(self.n_pix.item())
         nval = int(self.off[-1].item())

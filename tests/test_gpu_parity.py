@@ -59,7 +59,8 @@ def small_cfg(npix=6, sub=3, nticks=200, blk=(2, 2, 64), kpix=(3, 5), kticks=100
     return g, ph, W.Blocking(blk[:2], blk[2]), kpix, kticks, fft, seg
 
 
-def gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp=True, batch=8, block_cap=None):
+def gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp=True, batch=8, block_cap=None,
+             check=True):
     say(f"  gpu path: npix={g.npix} sub={g.sub} nticks={g.nticks} blk={blk.blk_pix}x{blk.blk_ticks}"
         f" K={kpix}x{kticks} fft={fft} n={seg.shape[0]} mpcp={mpcp}")
     sd = dev(seg)
@@ -67,7 +68,10 @@ def gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp=True, batch=8, bl
     pl = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap,
                     block_cap or bcap, pix_cap, fft, mpcp, batch)
     pl.run(sd)
-    return pl.results()
+    if not check:
+        with pytest.raises(T.TredError, match="active bins"):
+            pl.results()
+    return pl.results(check=check)
 
 
 def oracle_path(orc, g, ph, blk, kpix, kticks, resp, seg):
@@ -377,14 +381,15 @@ def test_empty_and_outside_events(T, orc):
 
 
 def test_block_capacity_truncation(T, orc):
-    """With fewer block slots than active bins the count reports the full number and
-    only the first `cap` bins (in key order) are produced."""
+    """With fewer block slots than active bins the count reports the full number, the
+    binding raises on the overflow, and only the first `cap` bins (in key order) are
+    produced."""
     say("test_block_capacity_truncation")
     g, ph, blk, kpix, kticks, fft, seg = small_cfg(n=30, seed=9)
     resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=11)
     o = oracle_path(orc, g, ph, blk, kpix, kticks, resp, seg)
     cap = max(1, len(o["keys"]) // 2)
-    r = gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, block_cap=cap)
+    r = gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, block_cap=cap, check=False)
     assert r["n_active"] == len(o["keys"])
     assert np.array_equal(r["keys"], o["keys"][:cap])
     pix = orc.pix_set(g, blk, kpix, o["keys"][:cap])
