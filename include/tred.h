@@ -165,6 +165,23 @@ tred_status tred_block_bin_rows(const tred_grid* grid, const tred_blocking* bloc
                                 int32_t* n_active, float* blocks, uint32_t* rows, int32_t cap,
                                 void* work, void* stream);
 
+/* tred_block_bin_rows for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * outputs as tred_block_bin_rows, with the workspace replaced by a static array in the
+ * library's device memory (1 MiB, one copy per device, held until the process ends;
+ * found on a device's first call, which must have that device current). The call
+ * allocates nothing and frees nothing.
+ * Returns TRED_ECAPACITY if tred_block_count() exceeds 262,144 bins (the array's
+ * size); use tred_block_bin_rows with a workspace then.
+ * Every call on one device shares that device's array: calls that overlap on one
+ * device (other streams, other host threads) race and give undefined outputs; calls
+ * ordered on one stream are safe (each call clears the array before using it). */
+tred_status tred_block_bin_rows_noalloc(const tred_grid* grid, const tred_blocking* blocking,
+                                        int64_t n_dep, const int32_t* fp, const int64_t* off,
+                                        const float* val, int64_t val_cap, int32_t* keys,
+                                        int32_t* n_active, float* blocks, uint32_t* rows,
+                                        int32_t cap, void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Interlaced convolution with the field response (Sec. II-D, eq. interlaced),
  * evaluated per active bin by FFT with the channel sum in the frequency domain

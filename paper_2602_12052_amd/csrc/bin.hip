@@ -2,10 +2,45 @@
 // charge of each active bin, reduced over overlapping deposition patches. A batch
 // of events shares one binned tensor: the event index leads the bin key, so the
 // (event, bin) pairs of all events form one list of independent blocks.
+#include <mutex>
+
 #include "tred_internal.hpp"
 #include "validate.hpp"
 
+// Bin -> slot map of tred_block_bin_rows_noalloc: a fixed array in device memory (one
+// copy per device, held until the process ends) instead of a caller workspace. Host
+// code never passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): it looks the address up once per device and passes that.
+constexpr int64_t kNoallocMaxBins = 1 << 18;  // 1 MiB of int32 slots
+static __device__ __align__(256) int32_t scratch[kNoallocMaxBins];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+
+// device address of `scratch` on the current device (looked up on a device's first call)
+tred_status noalloc_scratch(int32_t** out) {
+    static std::mutex mu;
+    static int32_t* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return tred_fail(TRED_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return tred_fail(TRED_EUNSUPPORTED, "device %d beyond the %d the library tracks", dev,
+                         kMaxDevices);
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return tred_fail(TRED_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                             hipGetErrorString(e));
+        addr[dev] = (int32_t*)p;
+    }
+    *out = addr[dev];
+    return TRED_OK;
+}
 
 struct BinGeom {
     int32_t bf[3];   // bin extent in fine cells
@@ -390,6 +425,31 @@ extern "C" tred_status tred_block_bin_rows(const tred_grid* grid, const tred_blo
                                            int32_t cap, void* work, void* stream) {
     TRED_REQUIRE(cap == 0 || rows, "rows is NULL");
     TRED_REQUIRE(((uintptr_t)rows & 3) == 0, "rows must be 4-byte aligned");
+    return block_bin(grid, blocking, 1, nullptr, n_dep, fp, off, val, val_cap, keys, n_active,
+                     blocks, rows, cap, work, stream);
+}
+
+extern "C" tred_status tred_block_bin_rows_noalloc(const tred_grid* grid,
+                                                   const tred_blocking* blocking, int64_t n_dep,
+                                                   const int32_t* fp, const int64_t* off,
+                                                   const float* val, int64_t val_cap,
+                                                   int32_t* keys, int32_t* n_active,
+                                                   float* blocks, uint32_t* rows, int32_t cap,
+                                                   void* stream) {
+    TRED_TRY(validate_grid(grid));
+    TRED_TRY(validate_blocking(blocking));
+    const int32_t nb = tred_block_count(grid, blocking);
+    if (nb < 0 || nb > kNoallocMaxBins)
+        return tred_fail(TRED_ECAPACITY,
+                         "tred_block_bin_rows_noalloc: %d bins exceed the static scratch of %lld "
+                         "bins; use tred_block_bin_rows with a workspace",
+                         (int)nb, (long long)kNoallocMaxBins);
+    TRED_REQUIRE(cap == 0 || rows, "rows is NULL");
+    TRED_REQUIRE(((uintptr_t)rows & 3) == 0, "rows must be 4-byte aligned");
+    int32_t* work = nullptr;
+    TRED_TRY(noalloc_scratch(&work));
+    // block_bin clears the map with a fill kernel first, so the previous call's contents
+    // do not matter
     return block_bin(grid, blocking, 1, nullptr, n_dep, fp, off, val, val_cap, keys, n_active,
                      blocks, rows, cap, work, stream);
 }

@@ -73,7 +73,7 @@ EXPORTS = [
     "tred_scatter_events_workspace", "tred_scatter_waveforms_events",
     "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint", "tred_block_bin_adjoint",
     "tred_effq_adjoint", "tred_block_row_words", "tred_block_bin_rows", "tred_block_conv_rows",
-    "tred_block_bin_events_rows", "tred_block_conv_adjoint_rows",
+    "tred_block_bin_events_rows", "tred_block_conv_adjoint_rows", "tred_block_bin_rows_noalloc",
 ]
 
 _lib = None
@@ -140,6 +140,7 @@ def lib():
     L.tred_block_bin_events_rows.argtypes = [P, P, I32, P, I64, P, P, P, I64, P, P, P, P, I32,
                                              P, P]
     L.tred_block_conv_adjoint_rows.argtypes = [P, P, I32, P, P, P, P]
+    L.tred_block_bin_rows_noalloc.argtypes = [P, P, I64, P, P, P, I64, P, P, P, P, I32, P]
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
                  "tred_conv_plan_set_response", "tred_conv_plan_info", "tred_conv_plan_set_timing",
     "tred_block_conv",
@@ -149,7 +150,7 @@ def lib():
                  "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint",
                  "tred_block_bin_adjoint", "tred_effq_adjoint", "tred_block_bin_rows",
                  "tred_block_conv_rows", "tred_block_bin_events_rows",
-                 "tred_block_conv_adjoint_rows"):
+                 "tred_block_conv_adjoint_rows", "tred_block_bin_rows_noalloc"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -341,6 +342,25 @@ def tred_block_bin_rows(grid, blocking, fp, off, val, keys, n_active, blocks, ro
     _check(lib().tred_block_bin_rows(C.byref(g), C.byref(b), n, _ptr(fp), _ptr(off), _ptr(val),
                                      val.numel(), _ptr(keys), _ptr(n_active), _ptr(blocks),
                                      _ptr(rows), cap, _ptr(work), _stream(stream)))
+
+
+def tred_block_bin_rows_noalloc(grid, blocking, fp, off, val, keys, n_active, blocks, rows,
+                                stream=None):
+    """tred_block_bin_rows without a workspace (the library's static per-device scratch;
+    calls that overlap on one device race)."""
+    import torch
+    _dt(keys, torch.int32, "keys"), _dt(n_active, torch.int32, "n_active")
+    _dt(blocks, torch.float32, "blocks"), _dt(rows, torch.int32, "rows")
+    g, b = grid_struct(grid), blocking_struct(blocking)
+    n = fp.shape[0]
+    cap = keys.shape[0]
+    if blocks.shape[0] < cap or rows.shape[0] < cap:
+        raise ValueError("blocks/rows have fewer rows than keys")
+    if rows.shape[1] != tred_block_row_words(grid, blocking):
+        raise ValueError("rows must have tred_block_row_words() columns")
+    _check(lib().tred_block_bin_rows_noalloc(C.byref(g), C.byref(b), n, _ptr(fp), _ptr(off),
+                                             _ptr(val), val.numel(), _ptr(keys), _ptr(n_active),
+                                             _ptr(blocks), _ptr(rows), cap, _stream(stream)))
 
 
 def tred_block_conv_rows(plan: ConvPlan, n_active, blocks, rows, out_blocks, stream=None):

@@ -178,6 +178,9 @@ def test_row_mask_calls_reject(T):
                                  C.c_void_p(0x1002), 4, p, None) == T.TRED_EINVAL
     assert L.tred_block_bin_events_rows(C.byref(g), C.byref(b), 2, p, 1, p, p, p, 10, p, p, p, None,
                                         4, p, None) == T.TRED_EINVAL
+    assert L.tred_block_bin_rows_noalloc(C.byref(g), C.byref(b), 1, p, p, p, 10, p, p, p, None, 4,
+                                         None) == T.TRED_EINVAL
+    assert b"rows" in L.tred_last_error()
     st, h, ws = _plan(T, cfg, fft=(8, 8, 256))
     assert L.tred_block_conv_rows(h, p, 4, p, None, p, None) == T.TRED_EINVAL
     assert b"rows" in L.tred_last_error()
@@ -221,3 +224,18 @@ def test_direct_conv_requires_response(T):
     assert b"set_response" in T.lib().tred_last_error()
     T.lib().tred_direct_plan_destroy(h)
 
+
+
+def test_noalloc_binning_rejects_grids_beyond_its_scratch(T):
+    """The binning call without a workspace holds at most 2^18 bins in its static
+    scratch; a larger grid is refused on the host, before any device call."""
+    L = T.lib()
+    g = W.Grid(origin=(0.0, 0.0, 0.0), spacing=(0.044, 0.044, W.TICK), npix=(1024, 1024),
+               sub=(1, 1), nticks=64 * 64)
+    b = W.Blocking((1, 1), 64)
+    assert T.tred_block_count(g, b) == 1024 * 1024 * 64
+    gs, bs = T.grid_struct(g), T.blocking_struct(b)
+    p = C.c_void_p(0x1000)  # never dereferenced
+    assert L.tred_block_bin_rows_noalloc(C.byref(gs), C.byref(bs), 1, p, p, p, 10, p, p, p, p, 4,
+                                         None) == T.TRED_ECAPACITY
+    assert b"static scratch" in L.tred_last_error()
