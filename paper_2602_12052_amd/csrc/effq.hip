@@ -7,10 +7,10 @@
 
 // threads per deposition and LDS floats of a tile of the effective-charge kernel
 #ifndef TRED_EFFQ_NT
-#define TRED_EFFQ_NT 512
+#define TRED_EFFQ_NT 128
 #endif
 #ifndef TRED_EFFQ_CAP
-#define TRED_EFFQ_CAP 20224   // 79 KiB: two workgroups per CU (160 KiB of LDS)
+#define TRED_EFFQ_CAP 4864   // 19 KiB: eight workgroups per CU (160 KiB of LDS)
 #endif
 
 namespace {
@@ -222,19 +222,16 @@ struct Idx3 {
     }
 };
 
-// One workgroup of NT threads per deposition (grid-stride over depositions). The
-// footprint is cut into tiles; for a tile of cells [X0, X1] x [Y0, Y1] x [Z0, Z1]
-// the node charges w * q of the cells one beyond the tile on every side (zero for
-// cells outside the quadrature window) are held in LDS, so that the spread stencil
-// of every output cell (the S = NGL + 2 (NGL / 2) nodes per axis of cells g-1, g, g+1
-// that reach g) lies inside the tile and the 3-D gather is fully unrolled. Tiles
-// follow each other along t; a ring of cell slots along t keeps the two cells that
-// consecutive tiles share, so every node is evaluated once per x-y column of tiles,
-// and only the cells inside the window are evaluated (the other slots are zeroed
-// once per column). Along t (the axis consecutive lanes walk) the nodes are stored
-// in planes of equal local index, V[..][l][slot], so the lanes' stencil reads are
-// unit-stride (no LDS bank conflicts); along x and y they are interleaved,
-// V[cell * NGL + l].
+// One workgroup of NT threads per deposition (grid-stride over depositions). Every
+// Gauss-Legendre node of the window cells is evaluated once, by the thread that owns
+// its (x-node, y-node) column: the thread walks the column along t and applies the t
+// part of the trilinear spread in registers (the nodes of cells g-1, g and g+1 reach
+// grid point g), writing A[column][t]; the x and y parts follow in one pass in which
+// every footprint cell gathers the S x S columns of its stencil from LDS. The
+// footprint is cut into tiles (the whole x-y extent when it fits, as many ticks as
+// fit); between t tiles a column's sliding state (the node charges of the two cells
+// the next tile still needs) is kept in LDS, so no node is evaluated twice along t.
+// Only columns of window cells are stored; the gather gives the others weight zero.
 template <int NGL, int CAP, int NT>
 __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                                              const float* __restrict__ seg,
@@ -242,11 +239,11 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                                              const int64_t* __restrict__ off,
                                              float* __restrict__ val, int64_t val_cap,
                                              double* __restrict__ charge_sum) {
-    constexpr int N3 = NGL * NGL * NGL;
     constexpr int NPOS = NGL / 2;                 // nodes with xi > 0 in a cell
     constexpr int S = NGL + 2 * NPOS;             // stencil nodes per axis
+    constexpr int NST = NPOS + NGL;               // sliding state of a column
     constexpr int NW = NT / kWave;
-    __shared__ __align__(16) float V[CAP];
+    __shared__ __align__(16) float sm[CAP];
     __shared__ double red[NW];
     __shared__ float sxi[8], sw[8];
     const int tid = threadIdx.x;
@@ -297,9 +294,12 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
             fh[a] = (float)h[a];
             fd[a] = (float)D[a];
             isg2[a] = (float)(1.0 / (sg[a] * sg[a]));
+            gvec[a] = 0.f;
         }
+        // the rule's Jacobian h_x h_y tick / 8 is folded into the prefactor
+        const double jac = h[0] * h[1] * h[2] / 8.0;
         if (point) {
-            pref = (float)(Qp * pow(2.0 * M_PI, -1.5) / (sg[0] * sg[1] * sg[2]));
+            pref = (float)(jac * Qp * pow(2.0 * M_PI, -1.5) / (sg[0] * sg[1] * sg[2]));
         } else {
             double alpha = 0.0;
 #pragma unroll
@@ -310,9 +310,8 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
             inv_alpha = (float)(1.0 / alpha);
             kq = (float)sqrt(0.5 * alpha);
             // Q / (4 pi Delta) with Delta = sigma_x sigma_y sigma_t sqrt(alpha)
-            pref = (float)(Qp / (4.0 * M_PI * sg[0] * sg[1] * sg[2] * sqrt(alpha)));
+            pref = (float)(jac * Qp / (4.0 * M_PI * sg[0] * sg[1] * sg[2] * sqrt(alpha)));
         }
-        const float jac = (float)(h[0] * h[1] * h[2] / 8.0);
 
         // cells whose nodes are evaluated: the quadrature window (intersected with F +- 1)
         int C0[3], C1[3], Fs[3];
@@ -322,162 +321,168 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
             C1[a] = min(W.hi[a], F1[a] + 1);
             Fs[a] = F1[a] - F0[a] + 1;
         }
-        // tile: whole footprint in x, y when it fits, as many ticks as fit
+        // tiles: LDS holds A (window columns x PA ticks, PA odd) and the columns' state
+        const int nwx = C1[0] - C0[0] + 1, nwy = C1[1] - C0[1] + 1;
+        auto ncols = [&](int t, int nw) { return max(0, min(t + 2, nw)) * NGL; };
         int T[3] = {Fs[0], Fs[1], Fs[2]};
-        while (N3 * (T[0] + 2) * (T[1] + 2) * 3 > CAP && (T[0] > 1 || T[1] > 1)) {
-            if (T[0] >= T[1]) T[0] = (T[0] + 1) / 2;
-            else T[1] = (T[1] + 1) / 2;
-        }
         {
-            const int per = N3 * (T[0] + 2) * (T[1] + 2);
-            int tt = 1;
-            while (tt < Fs[2] && per * (tt + 3) <= CAP) ++tt;
-            T[2] = tt;
+            const int tmin = min(Fs[2], 5) | 1;
+            while (ncols(T[0], nwx) * ncols(T[1], nwy) * (tmin + NST) > CAP && (T[0] > 1 || T[1] > 1)) {
+                if (T[0] >= T[1]) T[0] = (T[0] + 1) / 2;
+                else T[1] = (T[1] + 1) / 2;
+            }
+            const int nc = ncols(T[0], nwx) * ncols(T[1], nwy);
+            if (nc > 0) {
+                const int room = CAP / nc - NST;          // >= 1 (CAP >= (3 NGL)^2 (1 + NST))
+                const int tmax = (room & 1) ? room : room - 1;
+                T[2] = max(1, min(Fs[2], tmax));
+            }
         }
+        const int PA = T[2] | 1;   // odd row pitch: the columns' rows start in distinct banks
         const int64_t FY = Fs[1], FT = Fs[2];
         double nsum = 0.0;
 
-        // node charge w * q of node (lx, ly, lt) of cell (cx, cy, ct), inside the window
-        auto node_charge = [&](int cx, int lx, int cy, int ly, int ct, int lt) -> float {
-            float xx, xy, xt, wt;
-            if constexpr (NGL == 2) {
-                // nodes -+1/sqrt(3), weights 1
-                constexpr float xi2 = 0.57735026918962576f;
-                xx = lx ? xi2 : -xi2;
-                xy = ly ? xi2 : -xi2;
-                xt = lt ? xi2 : -xi2;
-                wt = 1.0f;
-            } else {
-                xx = sxi[lx];
-                xy = sxi[ly];
-                xt = sxi[lt];
-                wt = sw[lx] * sw[ly] * sw[lt];
-            }
-            const float rx = fb[0] + ((float)(cx - W.lo[0]) + 0.5f * xx) * fh[0];
-            const float ry = fb[1] + ((float)(cy - W.lo[1]) + 0.5f * xy) * fh[1];
-            const float rt = fb[2] + ((float)(ct - W.lo[2]) + 0.5f * xt) * fh[2];
-            float q;
-            if (point) {
-                const float e = rx * rx * isg2[0] + ry * ry * isg2[1] + rt * rt * isg2[2];
-                q = pref * exp_neg_half(e);
-            } else {
-                const float beta = rx * gvec[0] + ry * gvec[1] + rt * gvec[2];
-                const float sst = beta * inv_alpha;       // closest point on the line
-                const float px = rx - sst * fd[0], py = ry - sst * fd[1], pt = rt - sst * fd[2];
-                const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
-                q = pref * exp_neg_half(e) * erf_diff(kq * (1.0f - sst), -kq * sst);
-            }
-            return wt * jac * q;
-        };
-
-        // Along t a tile holds cells Z0-1 .. Z1+1 at slots 0 .. Z1-Z0+2 of a row of
-        // R = T[2] + 2; the two cells that consecutive tiles share are copied down from
-        // slots R-2, R-1 instead of evaluated again.
-        const int R = T[2] + 2;
         for (int X0 = F0[0]; X0 <= F1[0]; X0 += T[0])
             for (int Y0 = F0[1]; Y0 <= F1[1]; Y0 += T[1]) {
                 const int X1 = min(X0 + T[0] - 1, F1[0]);
                 const int Y1 = min(Y0 + T[1] - 1, F1[1]);
-                const int nn0 = (X1 - X0 + 3) * NGL, nn1 = (Y1 - Y0 + 3) * NGL, nn2 = NGL * R;
-                const int sxs = nn1 * nn2;
-                // cells of the window among x in X0-1 .. X1+1, y in Y0-1 .. Y1+1; the node
-                // slots of the other cells stay zero
+                // window cells among x in X0-1 .. X1+1, y in Y0-1 .. Y1+1
                 const int ex0 = max(X0 - 1, C0[0]), ex1 = min(X1 + 1, C1[0]);
                 const int ey0 = max(Y0 - 1, C0[1]), ey1 = min(Y1 + 1, C1[1]);
-                // cells whose nodes this column counts in the charge sum (x, y tiles share
-                // their edge cells; along t every cell is evaluated once)
+                const int ncx = max(0, ex1 - ex0 + 1) * NGL, ncy = max(0, ey1 - ey0 + 1) * NGL;
+                const int ncw = ncx * ncy;
+                // cells whose nodes this x-y tile counts in the charge sum (x, y tiles share
+                // their edge cells; along t every cell is counted once)
                 const int ox0 = max(X0 == F0[0] ? X0 - 1 : X0, C0[0]);
                 const int ox1 = min(X1 == F1[0] ? X1 + 1 : X1, C1[0]);
                 const int oy0 = max(Y0 == F0[1] ? Y0 - 1 : Y0, C0[1]);
                 const int oy1 = min(Y1 == F1[1] ? Y1 + 1 : Y1, C1[1]);
-                {
-                    const int n4 = (nn0 * sxs + 3) / 4;   // <= CAP / 4
-                    float4* V4 = reinterpret_cast<float4*>(V);
-                    for (int i = tid; i < n4; i += NT) V4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                __syncthreads();
+                float* A = sm;                          // [ncw][PA]
+                float* ST = sm + ncw * PA;              // [ncw][NST]
+                const int nx = X1 - X0 + 1, ny = Y1 - Y0 + 1;
                 for (int Z0 = F0[2]; Z0 <= F1[2]; Z0 += T[2]) {
                     const int Z1 = min(Z0 + T[2] - 1, F1[2]);
-                    const bool first = Z0 == F0[2];
-                    const bool xy = ex0 <= ex1 && ey0 <= ey1;
-                    const int mx = (ex1 - ex0 + 1) * NGL, my = (ey1 - ey0 + 1) * NGL;
-                    const int xo = (ex0 - X0 + 1) * NGL, yo = (ey0 - Y0 + 1) * NGL;
-                    if (!first) {
-                        // cells Z0-1, Z0 were the previous (full) tile's slots R-2, R-1
-                        if (xy) {
-                            const int rows = mx * my * NGL;
-                            for (int r = tid; r < rows; r += NT) {
-                                const int lt = r % NGL, q = r / NGL;
-                                const int j = q % my, i = q / my;
-                                float* row = V + (xo + i) * sxs + (yo + j) * nn2 + lt * R;
-                                const float v0 = row[R - 2], v1 = row[R - 1];
-                                row[0] = v0;
-                                row[1] = v1;
-                            }
+                    const int nz = Z1 - Z0 + 1;
+                    const bool first = Z0 == F0[2], last = Z1 == F1[2];
+                    // 1) columns: node charges along t, t part of the spread
+                    for (int c = tid; c < ncw; c += NT) {
+                        const int xn = c / ncy, yn = c - xn * ncy;
+                        const int cx = ex0 + xn / NGL, lx = xn % NGL;
+                        const int cy = ey0 + yn / NGL, ly = yn % NGL;
+                        float xx, xy, wxy;
+                        if constexpr (NGL == 2) {
+                            constexpr float xi2 = 0.57735026918962576f;   // nodes -+1/sqrt(3)
+                            xx = lx ? xi2 : -xi2;
+                            xy = ly ? xi2 : -xi2;
+                            wxy = 1.0f;
+                        } else {
+                            xx = sxi[lx];
+                            xy = sxi[ly];
+                            wxy = sw[lx] * sw[ly];
                         }
-                        __syncthreads();
-                    }
-                    // 1) node charges of the cells new to the tile: Z0-1 .. Z1+1 for the
-                    //    first tile, Z0+1 .. Z1+1 after it (zero outside the window)
-                    const int cs = first ? Z0 - 1 : Z0 + 1;
-                    const int ntn = Z1 + 2 - cs;
-                    const int kb = cs - (Z0 - 1);   // slot of cell cs
-                    if (xy) {
-                        const int mt = ntn * NGL;
-                        const int total = mx * my * mt;
-                        Idx3 it;
-                        it.init(tid, NT, my, mt);
-                        for (int i = tid; i < total; i += NT, it.next()) {
-                            const int cx = ex0 + it.i / NGL, lx = it.i % NGL;
-                            const int cy = ey0 + it.j / NGL, ly = it.j % NGL;
-                            int lt;
-                            if constexpr (NGL == 2) lt = it.k >= ntn ? 1 : 0;
-                            else lt = it.k / ntn;
-                            const int d = it.k - lt * ntn;
-                            const int ct = cs + d;
-                            float vq = 0.0f;
-                            if (ct >= C0[2] && ct <= C1[2]) {
-                                vq = node_charge(cx, lx, cy, ly, ct, lt);
-                                if (cx >= ox0 && cx <= ox1 && cy >= oy0 && cy <= oy1) nsum += (double)vq;
+                        const float rx = fb[0] + ((float)(cx - W.lo[0]) + 0.5f * xx) * fh[0];
+                        const float ry = fb[1] + ((float)(cy - W.lo[1]) + 0.5f * xy) * fh[1];
+                        const bool cnt = cx >= ox0 && cx <= ox1 && cy >= oy0 && cy <= oy1;
+                        const float bxy = rx * gvec[0] + ry * gvec[1];
+                        const float exy = rx * rx * isg2[0] + ry * ry * isg2[1];
+                        // w * q of the NGL nodes of cell ct (zero outside the window)
+                        auto cell = [&](int ct, float* q) {
+                            const bool in = ct >= C0[2] && ct <= C1[2];
+                            const float ctf = (float)(ct - W.lo[2]);
+#pragma unroll
+                            for (int l = 0; l < NGL; ++l) {
+                                float xt, wt;
+                                if constexpr (NGL == 2) {
+                                    constexpr float xi2 = 0.57735026918962576f;
+                                    xt = l ? xi2 : -xi2;
+                                    wt = wxy;
+                                } else {
+                                    xt = sxi[l];
+                                    wt = wxy * sw[l];
+                                }
+                                const float rt = fb[2] + (ctf + 0.5f * xt) * fh[2];
+                                float v;
+                                if (point) {
+                                    v = pref * exp_neg_half(fmaf(rt * isg2[2], rt, exy));
+                                } else {
+                                    const float sst = fmaf(rt, gvec[2], bxy) * inv_alpha;   // closest point on the line
+                                    const float px = rx - sst * fd[0], py = ry - sst * fd[1], pt = rt - sst * fd[2];
+                                    const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
+                                    v = pref * exp_neg_half(e) * erf_diff(kq * (1.0f - sst), -kq * sst);
+                                }
+                                q[l] = in ? wt * v : 0.0f;
+                                if (cnt) nsum += (double)q[l];
                             }
-                            // (indices below 2^24: full-rate 24-bit products)
-                            V[__mul24(xo + it.i, sxs) + __mul24(yo + it.j, nn2) + lt * R + kb + d] = vq;
+                        };
+                        float hold[NPOS > 0 ? NPOS : 1], cur[NGL], nxt[NGL];
+                        float* stc = ST + c * NST;
+                        if (first) {
+                            // cells F0t - 1 and F0t: every node counted once
+                            cell(Z0 - 1, nxt);
+#pragma unroll
+                            for (int k = 0; k < NPOS; ++k) hold[k] = nxt[NGL - NPOS + k];
+                            cell(Z0, cur);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < NPOS; ++k) hold[k] = stc[k];
+#pragma unroll
+                            for (int k = 0; k < NGL; ++k) cur[k] = stc[NPOS + k];
+                        }
+                        float* arow = A + c * PA;
+                        for (int j = 0; j < nz; ++j) {
+                            cell(Z0 + j + 1, nxt);
+                            float a = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < NPOS; ++k) a = fmaf(su[k], hold[k], a);
+#pragma unroll
+                            for (int k = 0; k < NGL; ++k) a = fmaf(su[NPOS + k], cur[k], a);
+#pragma unroll
+                            for (int k = 0; k < NPOS; ++k) a = fmaf(su[NPOS + NGL + k], nxt[k], a);
+                            arow[j] = a;
+#pragma unroll
+                            for (int k = 0; k < NPOS; ++k) hold[k] = cur[NGL - NPOS + k];
+#pragma unroll
+                            for (int k = 0; k < NGL; ++k) cur[k] = nxt[k];
+                        }
+                        if (!last) {
+#pragma unroll
+                            for (int k = 0; k < NPOS; ++k) stc[k] = hold[k];
+#pragma unroll
+                            for (int k = 0; k < NGL; ++k) stc[NPOS + k] = cur[k];
                         }
                     }
                     __syncthreads();
-                    // 2) each footprint cell gathers the spread of its stencil nodes
+                    // 2) x and y parts of the spread: each footprint cell of the tile sums the
+                    //    S x S columns of its stencil (columns outside the window weigh zero)
                     {
-                        const int nx = X1 - X0 + 1, ny = Y1 - Y0 + 1, nz = Z1 - Z0 + 1;
                         const int count = nx * ny * nz;
-                        // t stencil: nodes NGL-NPOS.. of cell g-1, all of g, ..NPOS-1 of g+1,
-                        // at plane l, cell offset -1 / 0 / +1 from g
-                        int offt[S];
-#pragma unroll
-                        for (int c = 0; c < S; ++c) {
-                            const int l = c < NPOS ? NGL - NPOS + c : (c < NPOS + NGL ? c - NPOS : c - NPOS - NGL);
-                            const int dc = c < NPOS ? -1 : (c < NPOS + NGL ? 0 : 1);
-                            offt[c] = l * R + dc;
-                        }
                         Idx3 it;
                         it.init(tid, NT, ny, nz);
                         for (int k = tid; k < count; k += NT, it.next()) {
-                            // first x/y stencil node of cell g: node NGL - NPOS of cell g - 1;
-                            // along t cell g sits at slot it.k + 1
-                            const float* vb = V + (it.i * NGL + (NGL - NPOS)) * sxs +
-                                              (it.j * NGL + (NGL - NPOS)) * nn2 + it.k + 1;
                             float acc = 0.0f;
-#pragma unroll
-                            for (int a = 0; a < S; ++a) {
-                                float ay = 0.0f;
+                            if (ncw > 0) {
+                                // first stencil node of cell g: node NGL - NPOS of cell g - 1
+                                const int xn0 = (X0 + it.i - 1 - ex0) * NGL + (NGL - NPOS);
+                                const int yn0 = (Y0 + it.j - 1 - ey0) * NGL + (NGL - NPOS);
+                                int ib[S];
+                                float wb[S];
 #pragma unroll
                                 for (int b = 0; b < S; ++b) {
-                                    const float* vr = vb + a * sxs + b * nn2;
-                                    float az = 0.0f;
-#pragma unroll
-                                    for (int c = 0; c < S; ++c) az = fmaf(su[c], vr[offt[c]], az);
-                                    ay = fmaf(su[b], az, ay);
+                                    const int yn = yn0 + b;
+                                    const bool ok = yn >= 0 && yn < ncy;
+                                    ib[b] = (ok ? yn : 0) * PA;
+                                    wb[b] = ok ? su[b] : 0.0f;
                                 }
-                                acc = fmaf(su[a], ay, acc);
+#pragma unroll
+                                for (int a = 0; a < S; ++a) {
+                                    const int xn = xn0 + a;
+                                    const bool ok = xn >= 0 && xn < ncx;
+                                    const float* ar = A + (ok ? xn : 0) * ncy * PA + it.k;
+                                    float ay = 0.0f;
+#pragma unroll
+                                    for (int b = 0; b < S; ++b) ay = fmaf(wb[b], ar[ib[b]], ay);
+                                    acc = fmaf(ok ? su[a] : 0.0f, ay, acc);
+                                }
                             }
                             val[o0 + ((int64_t)(X0 + it.i - F0[0]) * FY + (Y0 + it.j - F0[1])) * FT +
                                 (Z0 + it.k - F0[2])] = acc;
@@ -536,8 +541,10 @@ void gl_rule(int n, double* xi, double* w) {
 template <int NGL>
 void launch_effq(const EffqParams& P, int64_t n_dep, const float* seg, const int32_t* fp,
                  const int64_t* off, float* val, int64_t val_cap, double* cs, hipStream_t st) {
-    // node charges of one tile (floats of LDS): at least one cell and its neighbours
-    constexpr int CAP = TRED_EFFQ_CAP > 27 * NGL * NGL * NGL ? TRED_EFFQ_CAP : 27 * NGL * NGL * NGL;
+    // LDS floats of a tile: at least the window columns of one x-y cell and its
+    // neighbours, one tick each, and their sliding state
+    constexpr int CMIN = 9 * NGL * NGL * (1 + NGL + NGL / 2);
+    constexpr int CAP = TRED_EFFQ_CAP > CMIN ? TRED_EFFQ_CAP : CMIN;
     constexpr int NT = TRED_EFFQ_NT;
     int64_t grid = n_dep < (1 << 20) ? n_dep : (1 << 20);
     hipLaunchKernelGGL((k_effq<NGL, CAP, NT>), dim3((unsigned)grid), dim3(NT), 0, st, P, n_dep, seg,
