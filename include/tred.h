@@ -125,7 +125,8 @@ tred_status tred_effq_windows(const tred_grid* grid, const tred_physics* phys, i
  * the cells of fp[d] (x-major, then y, t fastest), summed over that deposition
  * only. Grid points outside the region are dropped.
  * val_cap: length of val; depositions whose patch would end past val_cap are
- * skipped (the caller detects this from off[n_dep] > val_cap).
+ * skipped (the caller detects this from off[n_dep] > val_cap), and so are patches of
+ * 2^31 cells or more (off[d+1] - off[d] > INT32_MAX; their values are not written).
  * charge_sum (may be NULL): binary64 sum over all evaluated nodes of w * q,
  * accumulated (not overwritten) by this call. */
 tred_status tred_effq(const tred_grid* grid, const tred_physics* phys, int64_t n_dep,

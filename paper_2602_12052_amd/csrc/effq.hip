@@ -7,10 +7,10 @@
 
 // threads per deposition and LDS floats of a tile of the effective-charge kernel
 #ifndef TRED_EFFQ_NT
-#define TRED_EFFQ_NT 128
+#define TRED_EFFQ_NT 256
 #endif
 #ifndef TRED_EFFQ_CAP
-#define TRED_EFFQ_CAP 4864   // 19 KiB: eight workgroups per CU (160 KiB of LDS)
+#define TRED_EFFQ_CAP 9984   // 39 KiB: four workgroups per CU (160 KiB of LDS)
 #endif
 
 namespace {
@@ -226,14 +226,18 @@ struct Idx3 {
 // Gauss-Legendre node of the window cells is evaluated once, by the thread that owns
 // its (x-node, y-node) column: the thread walks the column along t and applies the t
 // part of the trilinear spread in registers (the nodes of cells g-1, g and g+1 reach
-// grid point g), writing A[column][t]; the x and y parts follow in one pass in which
-// every footprint cell gathers the S x S columns of its stencil from LDS. The
-// footprint is cut into tiles (the whole x-y extent when it fits, as many ticks as
-// fit); between t tiles a column's sliding state (the node charges of the two cells
-// the next tile still needs) is kept in LDS, so no node is evaluated twice along t.
-// Only columns of window cells are stored; the gather gives the others weight zero.
+// grid point g), writing A[y-node][t][x-node]; the x and y parts follow in one pass in
+// which every footprint cell sums the S x S stencil columns from LDS (per y node, the
+// S x nodes are consecutive and read in pairs). The footprint is cut into tiles (the
+// whole x-y extent when it fits, as many ticks as fit); between t tiles a column's
+// sliding state (the node charges of the two cells the next tile still needs) is kept
+// in LDS, so no node is evaluated twice along t. Only columns of window cells are
+// stored; per-tile tables give every footprint cell's stencil its weights, zero for
+// nodes outside the window (those reads land on other finite values of the tile).
+// (four waves per SIMD for the 2-point rule: four 256-thread workgroups per CU)
 template <int NGL, int CAP, int NT>
-__global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4 : 1))) void k_effq(
+    EffqParams P, int64_t n_dep,
                                              const float* __restrict__ seg,
                                              const int32_t* __restrict__ fp,
                                              const int64_t* __restrict__ off,
@@ -242,6 +246,8 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
     constexpr int NPOS = NGL / 2;                 // nodes with xi > 0 in a cell
     constexpr int S = NGL + 2 * NPOS;             // stencil nodes per axis
     constexpr int NST = NPOS + NGL;               // sliding state of a column
+    constexpr int TX = (S + 1 + 3) / 4 * 4;       // x table row: first node, S weights
+    constexpr int TY = 2 * S;                     // y table row: S offsets, S weights
     constexpr int NW = NT / kWave;
     __shared__ __align__(16) float sm[CAP];
     __shared__ double red[NW];
@@ -255,6 +261,9 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
     float su[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) su[k] = P.u[k];
+    // every float of the tile memory holds a finite value from here on (the gather reads
+    // a few floats beyond a row with weight zero)
+    for (int i = tid; i < CAP; i += NT) sm[i] = 0.0f;
     __syncthreads();
 
     for (int64_t d = blockIdx.x; d < n_dep; d += gridDim.x) {
@@ -262,7 +271,8 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
         int F0[3] = {f[0], f[1], f[2]}, F1[3] = {f[3], f[4], f[5]};
         if (F1[0] < F0[0] || F1[1] < F0[1] || F1[2] < F0[2]) continue;
         const int64_t o0 = off[d], o1 = off[d + 1];
-        if (o1 > val_cap) continue;
+        // patches past val_cap, or of 2^31 cells or more (32-bit offsets), are skipped
+        if (o1 > val_cap || o1 - o0 > INT32_MAX) continue;
         float s[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) s[k] = seg[7 * d + k];
@@ -321,25 +331,30 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
             C1[a] = min(W.hi[a], F1[a] + 1);
             Fs[a] = F1[a] - F0[a] + 1;
         }
-        // tiles: LDS holds A (window columns x PA ticks, PA odd) and the columns' state
+        // tiles. LDS: the stencil tables of the tile's x and y cells, A[y node][t][x node]
+        // (window columns; rows of PX = ncx | 1 floats, odd so that the columns' rows
+        // start in distinct banks) between two guard bands of S floats, and the
+        // columns' sliding state
         const int nwx = C1[0] - C0[0] + 1, nwy = C1[1] - C0[1] + 1;
         auto ncols = [&](int t, int nw) { return max(0, min(t + 2, nw)) * NGL; };
+        auto fixed = [&](int t0, int t1) {   // floats besides the ticks of A
+            const int cx = ncols(t0, nwx), cy = ncols(t1, nwy);
+            return t0 * TX + t1 * TY + 2 * S + cx * cy * NST;
+        };
+        auto per_tick = [&](int t0, int t1) { return ncols(t1, nwy) * (ncols(t0, nwx) | 1); };
         int T[3] = {Fs[0], Fs[1], Fs[2]};
         {
-            const int tmin = min(Fs[2], 5) | 1;
-            while (ncols(T[0], nwx) * ncols(T[1], nwy) * (tmin + NST) > CAP && (T[0] > 1 || T[1] > 1)) {
+            const int tmin = min(Fs[2], 5);
+            while (fixed(T[0], T[1]) + tmin * per_tick(T[0], T[1]) > CAP && (T[0] > 1 || T[1] > 1)) {
                 if (T[0] >= T[1]) T[0] = (T[0] + 1) / 2;
                 else T[1] = (T[1] + 1) / 2;
             }
-            const int nc = ncols(T[0], nwx) * ncols(T[1], nwy);
-            if (nc > 0) {
-                const int room = CAP / nc - NST;          // >= 1 (CAP >= (3 NGL)^2 (1 + NST))
-                const int tmax = (room & 1) ? room : room - 1;
-                T[2] = max(1, min(Fs[2], tmax));
-            }
+            const int pt = per_tick(T[0], T[1]);
+            if (pt > 0) T[2] = max(1, min(Fs[2], (CAP - fixed(T[0], T[1])) / pt));
         }
-        const int PA = T[2] | 1;   // odd row pitch: the columns' rows start in distinct banks
-        const int64_t FY = Fs[1], FT = Fs[2];
+        // patch of this deposition (its cell count, FX FY FT, is below 2^31: 32-bit offsets)
+        const int FY = Fs[1], FT = Fs[2];
+        float* vd = val + o0;
         double nsum = 0.0;
 
         for (int X0 = F0[0]; X0 <= F1[0]; X0 += T[0])
@@ -351,22 +366,45 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                 const int ey0 = max(Y0 - 1, C0[1]), ey1 = min(Y1 + 1, C1[1]);
                 const int ncx = max(0, ex1 - ex0 + 1) * NGL, ncy = max(0, ey1 - ey0 + 1) * NGL;
                 const int ncw = ncx * ncy;
+                const int PX = ncx | 1, PY = T[2] * PX;
                 // cells whose nodes this x-y tile counts in the charge sum (x, y tiles share
                 // their edge cells; along t every cell is counted once)
                 const int ox0 = max(X0 == F0[0] ? X0 - 1 : X0, C0[0]);
                 const int ox1 = min(X1 == F1[0] ? X1 + 1 : X1, C1[0]);
                 const int oy0 = max(Y0 == F0[1] ? Y0 - 1 : Y0, C0[1]);
                 const int oy1 = min(Y1 == F1[1] ? Y1 + 1 : Y1, C1[1]);
-                float* A = sm;                          // [ncw][PA]
-                float* ST = sm + ncw * PA;              // [ncw][NST]
                 const int nx = X1 - X0 + 1, ny = Y1 - Y0 + 1;
+                float* tabx = sm;                               // [nx][TX]: x0 node, S weights
+                float* taby = sm + T[0] * TX;                   // [ny][TY]: S offsets, S weights
+                float* A = taby + T[1] * TY + S;                // [ncy][T2][PX]
+                float* ST = A + ncy * PY + S;                   // [ncw][NST]
+                // stencil tables: cell g of the tile gathers nodes x0 .. x0 + S - 1 (node
+                // NGL - NPOS of cell g - 1 onwards); those outside the window weigh zero
+                for (int i = tid; i < nx + ny; i += NT) {
+                    if (i < nx) {
+                        const int x0 = (X0 + i - 1 - ex0) * NGL + (NGL - NPOS);
+                        tabx[i * TX] = __int_as_float(x0);
+#pragma unroll
+                        for (int a = 0; a < S; ++a)
+                            tabx[i * TX + 1 + a] = (x0 + a >= 0 && x0 + a < ncx) ? su[a] : 0.0f;
+                    } else {
+                        const int y = i - nx;
+                        const int y0 = (Y0 + y - 1 - ey0) * NGL + (NGL - NPOS);
+#pragma unroll
+                        for (int b = 0; b < S; ++b) {
+                            const bool ok = y0 + b >= 0 && y0 + b < ncy;
+                            taby[y * TY + b] = __int_as_float((ok ? y0 + b : 0) * PY);
+                            taby[y * TY + S + b] = ok ? su[b] : 0.0f;
+                        }
+                    }
+                }
                 for (int Z0 = F0[2]; Z0 <= F1[2]; Z0 += T[2]) {
                     const int Z1 = min(Z0 + T[2] - 1, F1[2]);
                     const int nz = Z1 - Z0 + 1;
                     const bool first = Z0 == F0[2], last = Z1 == F1[2];
                     // 1) columns: node charges along t, t part of the spread
                     for (int c = tid; c < ncw; c += NT) {
-                        const int xn = c / ncy, yn = c - xn * ncy;
+                        const int yn = c / ncx, xn = c - yn * ncx;
                         const int cx = ex0 + xn / NGL, lx = xn % NGL;
                         const int cy = ey0 + yn / NGL, ly = yn % NGL;
                         float xx, xy, wxy;
@@ -428,7 +466,7 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
 #pragma unroll
                             for (int k = 0; k < NGL; ++k) cur[k] = stc[NPOS + k];
                         }
-                        float* arow = A + c * PA;
+                        float* arow = A + yn * PY + xn;
                         for (int j = 0; j < nz; ++j) {
                             cell(Z0 + j + 1, nxt);
                             float a = 0.0f;
@@ -438,7 +476,7 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                             for (int k = 0; k < NGL; ++k) a = fmaf(su[NPOS + k], cur[k], a);
 #pragma unroll
                             for (int k = 0; k < NPOS; ++k) a = fmaf(su[NPOS + NGL + k], nxt[k], a);
-                            arow[j] = a;
+                            arow[j * PX] = a;
 #pragma unroll
                             for (int k = 0; k < NPOS; ++k) hold[k] = cur[NGL - NPOS + k];
 #pragma unroll
@@ -453,39 +491,25 @@ __global__ __launch_bounds__(NT) void k_effq(EffqParams P, int64_t n_dep,
                     }
                     __syncthreads();
                     // 2) x and y parts of the spread: each footprint cell of the tile sums the
-                    //    S x S columns of its stencil (columns outside the window weigh zero)
+                    //    S x S stencil columns with the tables' weights
                     {
                         const int count = nx * ny * nz;
                         Idx3 it;
                         it.init(tid, NT, ny, nz);
                         for (int k = tid; k < count; k += NT, it.next()) {
+                            const float* tx = tabx + it.i * TX;
+                            const float* ty = taby + it.j * TY;
+                            const float* ab = A + it.k * PX + __float_as_int(tx[0]);
                             float acc = 0.0f;
-                            if (ncw > 0) {
-                                // first stencil node of cell g: node NGL - NPOS of cell g - 1
-                                const int xn0 = (X0 + it.i - 1 - ex0) * NGL + (NGL - NPOS);
-                                const int yn0 = (Y0 + it.j - 1 - ey0) * NGL + (NGL - NPOS);
-                                int ib[S];
-                                float wb[S];
 #pragma unroll
-                                for (int b = 0; b < S; ++b) {
-                                    const int yn = yn0 + b;
-                                    const bool ok = yn >= 0 && yn < ncy;
-                                    ib[b] = (ok ? yn : 0) * PA;
-                                    wb[b] = ok ? su[b] : 0.0f;
-                                }
+                            for (int b = 0; b < S; ++b) {
+                                const float* r = ab + __float_as_int(ty[b]);
+                                float ax = 0.0f;
 #pragma unroll
-                                for (int a = 0; a < S; ++a) {
-                                    const int xn = xn0 + a;
-                                    const bool ok = xn >= 0 && xn < ncx;
-                                    const float* ar = A + (ok ? xn : 0) * ncy * PA + it.k;
-                                    float ay = 0.0f;
-#pragma unroll
-                                    for (int b = 0; b < S; ++b) ay = fmaf(wb[b], ar[ib[b]], ay);
-                                    acc = fmaf(ok ? su[a] : 0.0f, ay, acc);
-                                }
+                                for (int a = 0; a < S; ++a) ax = fmaf(tx[1 + a], r[a], ax);
+                                acc = fmaf(ty[S + b], ax, acc);
                             }
-                            val[o0 + ((int64_t)(X0 + it.i - F0[0]) * FY + (Y0 + it.j - F0[1])) * FT +
-                                (Z0 + it.k - F0[2])] = acc;
+                            vd[((X0 + it.i - F0[0]) * FY + (Y0 + it.j - F0[1])) * FT + (Z0 + it.k - F0[2])] = acc;
                         }
                     }
                     __syncthreads();
@@ -541,9 +565,11 @@ void gl_rule(int n, double* xi, double* w) {
 template <int NGL>
 void launch_effq(const EffqParams& P, int64_t n_dep, const float* seg, const int32_t* fp,
                  const int64_t* off, float* val, int64_t val_cap, double* cs, hipStream_t st) {
-    // LDS floats of a tile: at least the window columns of one x-y cell and its
-    // neighbours, one tick each, and their sliding state
-    constexpr int CMIN = 9 * NGL * NGL * (1 + NGL + NGL / 2);
+    // LDS floats of a tile: at least the tables and window columns of one x-y cell and
+    // its neighbours, one tick each, and their sliding state
+    constexpr int S = NGL + 2 * (NGL / 2);
+    constexpr int CMIN = 9 * NGL * NGL * (NGL + NGL / 2) + 3 * NGL * (3 * NGL + 1) +
+                         (S + 4) / 4 * 4 + 4 * S;
     constexpr int CAP = TRED_EFFQ_CAP > CMIN ? TRED_EFFQ_CAP : CMIN;
     constexpr int NT = TRED_EFFQ_NT;
     int64_t grid = n_dep < (1 << 20) ? n_dep : (1 << 20);
