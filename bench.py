@@ -305,9 +305,10 @@ def bench_adjoint(args):
 
 def bench_batched(args):
     """Batched events: n_ev module-scale events of log-uniform size in [1e3, 2e5]. The
-    autotuner picks the bin shape and FFT sizes on the median event; events are grouped
-    into chunks whose (event, bin) pairs fit a memory budget; each chunk's whole path
-    (effq, binning with the event in the key, one convolution queue over all its
+    autotuner picks the bin shape and FFT sizes on three events (the quartile sizes);
+    events are taken smallest first (by active bins) and grouped into chunks of at most
+    --chunk-bins (event, bin) pairs that also fit a memory budget; each chunk's whole
+    path (effq, binning with the event in the key, one convolution queue over all its
     bins, per-event overlap-add) is captured once in a HIP graph, and the graphs are
     replayed back to back. Reports throughput and the per-event completion latency
     (time from the batch start until the event's chunk is done). One JSON line."""
@@ -321,8 +322,10 @@ def bench_batched(args):
     resp = W.synthetic_response(cfg.kpix, g.sub, cfg.kticks)
     dresp = torch.from_numpy(resp).cuda()
     log = lambda m: print("# " + m, file=sys.stderr, flush=True)
-    med = int(np.argsort(sizes)[len(sizes) // 2])
-    tune = autotune.tune(g, ph, cfg.kpix, cfg.kticks, dresp, torch.from_numpy(evs[med]).cuda(),
+    order = np.argsort(sizes, kind="stable")
+    picks = [int(order[int(q * (len(sizes) - 1))]) for q in (0.25, 0.5, 0.75)]
+    tune = autotune.tune(g, ph, cfg.kpix, cfg.kticks, dresp,
+                         [torch.from_numpy(evs[e]).cuda() for e in picks],
                          make_blocking=lambda bp, bt: W.Blocking((bp, bp), bt), log=log)
     best = tune.best
     blk = W.Blocking((best.blk_pix, best.blk_pix), best.blk_ticks)
@@ -331,9 +334,12 @@ def bench_batched(args):
     bins = np.array([c[1] for c in caps])
     fixed, scratch = autotune._bytes_per_bin(g, blk, cfg.kpix, cfg.kticks, fft, True)
     pass_bins = max(1, int(args.pass_gb * 1e9 // scratch))
-    chunk_bins = max(int(bins.max()), int((args.budget_gb * 1e9 - pass_bins * scratch) // fixed))
+    chunk_bins = max(int(bins.max()), min(args.chunk_bins,
+                                          int((args.budget_gb * 1e9 - pass_bins * scratch) // fixed)))
+    # smallest events first: the median event completes after a small share of the work
     chunks, cur, nb = [], [], 0
-    for e in range(len(evs)):
+    for e in np.argsort(bins, kind="stable"):
+        e = int(e)
         if cur and nb + bins[e] > chunk_bins:
             chunks.append(cur)
             cur, nb = [], 0
@@ -391,7 +397,8 @@ def bench_batched(args):
         "config": {"workload": f"{len(evs)} module-scale events, deposition counts log-uniform in "
                                f"[1e3, 2e5], per-event track/blob mix",
                    "n_dep": int(sizes.sum()), "active_event_bins": int(bins.sum()),
-                   "chunks": len(chunks), "bins_per_pass": min(pass_bins, max(c[1] for c in ccap)),
+                   "chunks": len(chunks), "chunk_bins": chunk_bins, "order": "smallest first",
+                   "bins_per_pass": min(pass_bins, max(c[1] for c in ccap)),
                    "blocking": [best.blk_pix, best.blk_pix, best.blk_ticks], "fft": list(fft)},
         "event_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "autotune": [{"blk": [t.blk_pix, t.blk_pix, t.blk_ticks], "fft": list(t.fft), "ms": t.ms,
@@ -417,6 +424,8 @@ def main():
                     help="module: the benchmark event; plain-small: the 1,000-segment event")
     ap.add_argument("--events", type=int, default=64, help="events of the batched form")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="device memory of a chunk")
+    ap.add_argument("--chunk-bins", type=int, default=1024,
+                    help="(event, bin) pairs per chunk of the batched form (at least one event)")
     ap.add_argument("--pass-gb", type=float, default=60.0, help="convolution scratch per pass")
     ap.add_argument("--form", default="fft",
                     choices=["fft", "direct-split", "direct-bf16", "batched", "adjoint"],

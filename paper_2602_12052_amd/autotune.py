@@ -16,14 +16,20 @@ from typing import List, Optional, Sequence, Tuple
 
 from . import tred
 
-# (blk_pix, blk_ticks, fft) candidates; fft = (fs, fs, ft)
+# (blk_pix, blk_ticks, fft) candidates; fft = (fs, fs, ft). Spatial sizes 32, 40 and 48
+# (the smallest that hold blk_pix + kpix - 1 for a 21-pixel response, and one larger),
+# bins of 8 to 28 pixels and of 256, 512 and 1024 ticks with time transforms of 1024 or
+# 2048 points.
 DEFAULT_CANDIDATES: Tuple[Tuple[int, int, Tuple[int, int, int]], ...] = (
     (16, 512, (40, 40, 1024)),
-    (16, 512, (40, 40, 2048)),
+    (16, 512, (48, 48, 1024)),
     (16, 256, (40, 40, 1024)),
-    (16, 256, (40, 40, 2048)),
-    (8, 512, (40, 40, 1024)),
+    (16, 1024, (40, 40, 2048)),
+    (8, 512, (32, 32, 1024)),
     (8, 256, (40, 40, 1024)),
+    (24, 512, (48, 48, 1024)),
+    (28, 512, (48, 48, 1024)),
+    (24, 1024, (48, 48, 2048)),
 )
 
 
@@ -59,37 +65,43 @@ def _bytes_per_bin(grid, blocking, kpix, kticks, fft, mpcp):
 def tune(grid, phys, kpix, kticks, resp, seg, mpcp: bool = True,
          candidates: Sequence = DEFAULT_CANDIDATES, budget_bytes: float = 200e9,
          reps: int = 2, make_blocking=None, log=None) -> TuneResult:
-    """Time each candidate on the sample event `seg` (device tensor) and return the
-    fastest. make_blocking(blk_pix, blk_ticks) builds a blocking object."""
+    """Time each candidate on the sample events `seg` (one device tensor, or a list of
+    them: the score is the sum of the events' median times) and return the fastest.
+    make_blocking(blk_pix, blk_ticks) builds a blocking object."""
     import torch
+    samples = list(seg) if isinstance(seg, (list, tuple)) else [seg]
     trials = []
     for bp, bt, fft in candidates:
         tr = Trial(bp, bt, tuple(fft))
         trials.append(tr)
         blk = make_blocking(bp, bt)
         try:
-            val_cap, bcap, pix_cap = tred.size_event(grid, phys, blk, kpix, seg)
-            fixed, scratch = _bytes_per_bin(grid, blk, kpix, kticks, fft, mpcp)
-            nb = tred.conv_batch(grid, blk, kpix, kticks, fft, mpcp, bcap,
-                                 max(scratch, budget_bytes - fixed * bcap))
-            tr.bins = bcap
-            tr.bytes = fixed * bcap + scratch * nb
-            if fixed * bcap + scratch > budget_bytes:
-                tr.note = "over the memory budget"
-                continue
-            pl = tred.Pipeline(grid, phys, blk, kpix, kticks, resp, seg.shape[0], val_cap, bcap,
-                               pix_cap, fft, mpcp, nb)
-            pl.run(seg)
-            torch.cuda.synchronize()
-            ts = []
-            for _ in range(reps):
-                t0 = time.perf_counter()
-                pl.run(seg)
+            total, nbins, nbytes = 0.0, 0, 0
+            for sd in samples:
+                val_cap, bcap, pix_cap = tred.size_event(grid, phys, blk, kpix, sd)
+                fixed, scratch = _bytes_per_bin(grid, blk, kpix, kticks, fft, mpcp)
+                nb = tred.conv_batch(grid, blk, kpix, kticks, fft, mpcp, bcap,
+                                     max(scratch, budget_bytes - fixed * bcap))
+                nbins += bcap
+                nbytes = max(nbytes, fixed * bcap + scratch * nb)
+                if fixed * bcap + scratch > budget_bytes:
+                    raise MemoryError
+                pl = tred.Pipeline(grid, phys, blk, kpix, kticks, resp, sd.shape[0], val_cap, bcap,
+                                   pix_cap, fft, mpcp, nb)
+                pl.run(sd)
                 torch.cuda.synchronize()
-                ts.append(1e3 * (time.perf_counter() - t0))
-            tr.ms = sorted(ts)[len(ts) // 2]
-            del pl
-            torch.cuda.empty_cache()
+                ts = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    pl.run(sd)
+                    torch.cuda.synchronize()
+                    ts.append(1e3 * (time.perf_counter() - t0))
+                total += sorted(ts)[len(ts) // 2]
+                del pl
+                torch.cuda.empty_cache()
+            tr.ms, tr.bins, tr.bytes = total, nbins, nbytes
+        except MemoryError:
+            tr.note = "over the memory budget"
         except tred.TredError as e:
             tr.note = f"unsupported: {e}"
         if log:
