@@ -33,7 +33,12 @@ struct tred_direct_plan {
 
 namespace {
 
-constexpr int kPad = 32;    // zero ticks on each side of a bin in Qt (>= MFMA rows - 1)
+constexpr int kPad = 32;    // zero ticks on each side of a bin in Qt (>= 2 TT - 2)
+#ifndef TRED_DIRECT_TT
+#define TRED_DIRECT_TT 16
+#endif
+constexpr int kDirTT = TRED_DIRECT_TT;   // output ticks per wave of the matrix-core kernel
+static_assert(2 * kDirTT - 2 <= kPad, "charge margin");
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -112,69 +117,116 @@ __global__ void k_direct_zero(DirArgs A, int b0, int nb, const int32_t* __restri
         o[i] = 0.0f;
 }
 
-__device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {
-    const uint4 v = *(const uint4*)p;
-    return __builtin_bit_cast(bf16x8, v);
+__device__ __forceinline__ bf16x8 ld8(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0u, 0));
 }
 
-// One wave per 32 x 32 output tile: rows (p, t' = t0 .. t0 + 31), columns k0 .. k0 + 31.
-// Workgroup = 4 waves on consecutive tick tiles of one (bin, pixel, column tile).
-// Lane l holds A[row l % 32][8 (l / 32) .. + 7] and B[8 (l / 32) .. + 7][col l % 32] of
-// each 32 x 16 x 32 step, and accumulator element i of C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
-template <bool SPLIT>
-__global__ __launch_bounds__(256) void k_direct_mma(DirArgs A, int b0, int nb,
-                                                    const int32_t* __restrict__ n_active,
-                                                    const uint16_t* __restrict__ qhi,
-                                                    const uint16_t* __restrict__ qlo,
-                                                    const uint16_t* __restrict__ rhi,
-                                                    const uint16_t* __restrict__ rlo,
-                                                    float* __restrict__ out) {
+// One wave per tile of 32 pixels p (rows) x 32 response offsets k (columns) x TT output
+// ticks t' (one accumulator tile per tick); a workgroup holds 2 x 2 such tiles (two
+// pixel tiles, two offset tiles) at the same ticks. For response tick tau and impact
+// positions j = 16 s .. 16 s + 15 the product is A[p][j] = Q_j[p][t' - tau] times
+// B[j][k] = R_j[k][tau]: a charge fragment (tick u = t' - tau) serves the TT output
+// ticks at TT consecutive tau, so the tau loop is unrolled by TT and the fragments sit in
+// a ring of TT registers (slot u mod TT, with tau walked in groups aligned to t0), one new
+// fragment and one response fragment per tau (one wave per SIMD, the accumulators in
+// the AGPRs). Loads go through buffer resources: ticks
+// before 0 or past the response, and pixels past the bin, read zero. Lane l holds
+// A[row l % 32][8 (l / 32) .. + 7] and B[8 (l / 32) .. + 7][col l % 32] of each
+// 32 x 16 x 32 step, and accumulator element i of C[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+template <bool SPLIT, int TT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1))) void k_direct_mma(
+    DirArgs A, int b0, int nb, const int32_t* __restrict__ n_active,
+    const uint16_t* __restrict__ qhi, const uint16_t* __restrict__ qlo,
+    const uint16_t* __restrict__ rhi, const uint16_t* __restrict__ rlo, float* __restrict__ out) {
     const int na = min(*n_active, A.cap);
-    const int bl = blockIdx.y;
-    if (b0 + bl >= na || bl >= nb) return;
-    const int ntg = (A.bot + 127) / 128;          // groups of 4 tick tiles
-    const int nkt = A.kpad / 32;
-    int r = blockIdx.x;
-    const int kt0 = r % nkt;
-    r /= nkt;
-    const int tg = r % ntg;
-    const int p = r / ntg;
+    const int npt = (A.npix + 31) / 32, nkt = A.kpad / 32;
+    const int cpx = (npt + 1) / 2, ckx = (nkt + 1) / 2;
+    static_assert((TT & (TT - 1)) == 0, "ticks per wave: a power of two");
+    // bins vary fastest: workgroups running together share the response slab of their
+    // ticks and offsets
+    int64_t w = blockIdx.x;
+    const int bl = (int)(w % nb);
+    w /= nb;
+    const int pc = (int)(w % cpx);
+    w /= cpx;
+    const int kc = (int)(w % ckx);
+    const int tt = (int)(w / ckx);
+    if (b0 + bl >= na) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int t0 = (tg * 4 + wv) * 32;
-    if (t0 >= A.bot) return;
+    const int pt = 2 * pc + (wv & 1), kt = 2 * kc + (wv >> 1);
+    if (pt >= npt || kt >= nkt) return;
     const int row = lane & 31, half = lane >> 5;
-    const int k0 = kt0 * 32;
-    // ticks tau with some row t' - tau inside the bin: t0 - (Bt - 1) <= tau <= t0 + 31
-    const int tau0 = max(0, t0 - (A.Bt - 1));
-    const int tau1 = min(A.kt - 1, t0 + 31);
-    const int64_t qrow = ((int64_t)bl * A.npix + p) * A.tq;
+    const int p0 = pt * 32, k0 = kt * 32, t0 = tt * TT;
+    // response ticks that reach some output tick of the tile from inside the bin
+    const int tlo = max(0, t0 - (A.Bt - 1)), thi = min(A.kt - 1, t0 + TT - 1);
+    if (tlo > thi) return;
+    const int tb0 = t0 - TT * ((t0 - tlo + TT - 1) / TT);   // <= tlo, congruent to t0 mod TT
+    const int jb = A.jpad * 2;                      // bytes per (pixel, tick) or (tau, k) row
+    const uint32_t qbytes = (uint32_t)((int64_t)A.npix * A.tq * jb);
+    const uint32_t rbytes = (uint32_t)((int64_t)A.kt * A.kpad * jb);
+    const int64_t qbin = (int64_t)bl * A.npix * A.tq * A.jpad;
+    const auto qh = buf_rsrc(qhi + qbin, qbytes), rh = buf_rsrc(rhi, rbytes);
+    const auto ql = buf_rsrc(qlo + qbin, qbytes), rl = buf_rsrc(rlo, rbytes);
+    // byte offsets: A(u) = Q[p0 + row][u] at qa + u * jb (margin kPad ticks before the bin);
+    // B(tau) = R[tau][k0 + row] at ra + tau * kpad * jb (negative tau wraps past the range)
+    const int qa = ((p0 + row) * A.tq + kPad) * jb + 16 * half;
+    const int ra = (k0 + row) * jb + 16 * half;
+    const int rstep = A.kpad * jb;
     const int jsteps = A.jpad / 16;
-    f32x16 acc = {};
-    for (int tau = tau0; tau <= tau1; ++tau) {
-        const int64_t qoff = (qrow + (t0 + row - tau + kPad)) * A.jpad + 8 * half;
-        const int64_t roff = ((int64_t)tau * A.kpad + k0 + row) * A.jpad + 8 * half;
-        for (int s = 0; s < jsteps; ++s) {
-            const bf16x8 ah = ld8(qhi + qoff + 16 * s);
-            const bf16x8 bh = ld8(rhi + roff + 16 * s);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-            if constexpr (SPLIT) {
-                const bf16x8 al = ld8(qlo + qoff + 16 * s);
-                const bf16x8 blo = ld8(rlo + roff + 16 * s);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blo, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+    constexpr int M = TT - 1;
+    f32x16 acc[TT];
+#pragma unroll
+    for (int i = 0; i < TT; ++i) acc[i] = (f32x16){};
+    for (int s = 0; s < jsteps; ++s) {
+        // hi (and lo) fragments; each tau's charge and response fragments are requested
+        // just before their multiplies, which the TT (x 3 with the split) products cover
+        bf16x8 fh[TT], fl[SPLIT ? TT : 1];
+#pragma unroll
+        for (int i = 1; i < TT; ++i) {
+            const uint32_t o = (uint32_t)(qa + (t0 - tb0 + i) * jb + 32 * s);
+            fh[i] = ld8(qh, o);
+            if constexpr (SPLIT) fl[i] = ld8(ql, o);
+        }
+        for (int tb = tb0; tb <= thi; tb += TT) {
+#pragma unroll
+            for (int d = 0; d < TT; ++d) {
+                const int tau = tb + d;
+                const int sl = (TT - d) & M;
+                const uint32_t oq = (uint32_t)(qa + (t0 - tau) * jb + 32 * s);
+                const uint32_t orr = (uint32_t)(ra + tau * rstep + 32 * s);
+                fh[sl] = ld8(qh, oq);
+                const bf16x8 bh = ld8(rh, orr);
+                bf16x8 blo;
+                if constexpr (SPLIT) {
+                    fl[sl] = ld8(ql, oq);
+                    blo = ld8(rl, orr);
+                }
+#pragma unroll
+                for (int i = 0; i < TT; ++i) {
+                    const int q = (i - d) & M;
+                    acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[q], bh, acc[i], 0, 0, 0);
+                    if constexpr (SPLIT) {
+                        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[q], blo, acc[i], 0, 0, 0);
+                        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[q], bh, acc[i], 0, 0, 0);
+                    }
+                }
             }
         }
     }
-    // scatter-add C[(p, t')][k] into out[p + k][t']
+    // scatter-add C[p][k] of tick t' into out[p + k][t']
     const int k = k0 + row;
     if (k >= A.nk) return;
-    const int px = p / A.By, py = p % A.By;
     const int kx = k / A.Ky, ky = k % A.Ky;
-    float* o = out + (int64_t)(b0 + bl) * A.vout + ((int64_t)(px + kx) * A.boy + (py + ky)) * A.bot;
+    float* ob = out + (int64_t)(b0 + bl) * A.vout;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int t = t0 + 8 * (i / 4) + 4 * half + (i % 4);
-        if (t < A.bot) atomicAdd(o + t, acc[i]);
+    for (int e = 0; e < 16; ++e) {
+        const int p = p0 + 8 * (e / 4) + 4 * half + (e % 4);
+        if (p >= A.npix) continue;
+        const int px = p / A.By, py = p % A.By;
+        float* o = ob + ((int64_t)(px + kx) * A.boy + (py + ky)) * A.bot + t0;
+#pragma unroll
+        for (int i = 0; i < TT; ++i)
+            if (t0 + i < A.bot) atomicAdd(o + i, acc[i][e]);
     }
 }
 
@@ -289,9 +341,11 @@ extern "C" tred_status tred_block_conv_direct(const tred_direct_plan* P, const i
     const uint16_t* rlo = (const uint16_t*)(ws + P->off_rlo);
     uint16_t* qhi = (uint16_t*)(ws + P->off_qhi);
     uint16_t* qlo = (uint16_t*)(ws + P->off_qlo);
-    const int ntg = (A.bot + 127) / 128;
-    const int64_t tiles = (int64_t)A.npix * ntg * (A.kpad / 32);
-    if (tiles > 0x7fffffff) return tred_fail(TRED_EUNSUPPORTED, "bin too large for the direct path");
+    const int npt = (A.npix + 31) / 32, nkt = A.kpad / 32;
+    const int64_t combos = (int64_t)((npt + 1) / 2) * ((nkt + 1) / 2) * ((A.bot + kDirTT - 1) / kDirTT);
+    if (combos * P->batch > 0x7fffffff || (int64_t)A.npix * A.tq * A.jpad * 2 > 0x7fffffff ||
+        (int64_t)A.kt * A.kpad * A.jpad * 2 > 0x7fffffff)
+        return tred_fail(TRED_EUNSUPPORTED, "bin too large for the direct path");
     for (int b0 = 0; b0 < cap; b0 += P->batch) {
         const int nb = std::min(P->batch, cap - b0);
         const int64_t nq = (int64_t)nb * A.npix * A.tq * A.jpad;
@@ -299,11 +353,12 @@ extern "C" tred_status tred_block_conv_direct(const tred_direct_plan* P, const i
                            blocks, qhi, qlo);
         hipLaunchKernelGGL(k_direct_zero, dim3(grid_for((int64_t)nb * A.vout)), dim3(256), 0, st, A, b0,
                            nb, n_active, out_blocks);
+        const unsigned nwg = (unsigned)(combos * nb);
         if (P->split)
-            hipLaunchKernelGGL(k_direct_mma<true>, dim3((unsigned)tiles, nb), dim3(256), 0, st, A, b0, nb,
+            hipLaunchKernelGGL((k_direct_mma<true, kDirTT>), dim3(nwg), dim3(256), 0, st, A, b0, nb,
                                n_active, qhi, qlo, rhi, rlo, out_blocks);
         else
-            hipLaunchKernelGGL(k_direct_mma<false>, dim3((unsigned)tiles, nb), dim3(256), 0, st, A, b0, nb,
+            hipLaunchKernelGGL((k_direct_mma<false, kDirTT>), dim3(nwg), dim3(256), 0, st, A, b0, nb,
                                n_active, qhi, qlo, rhi, rlo, out_blocks);
         TRED_TRY(tred_check_launch("tred_block_conv_direct"));
     }
