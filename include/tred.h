@@ -197,14 +197,15 @@ tred_status tred_block_bin_rows_noalloc(const tred_grid* grid, const tred_blocki
  * bt*blk_ticks + t'.
  *
  * fft: FFT sizes (x, y, t). Spatial sizes must be equal, taken from
- * {8,16,24,32,40,48,64}, with fft[a] >= blk_pix[a] + kpix[a] - 1 (0 selects the
- * smallest). The
+ * {8,16,24,32,36,40,48,64}, with fft[a] >= blk_pix[a] + kpix[a] - 1 (0 selects the
+ * smallest of {8,16,24,32,40,48,64}). The
  * time size is a power of two in [256, 2048] with fft[2] >= blk_ticks + 64 (0 selects
  * the smallest power of two >= blk_ticks + kticks - 1); when fft[2] is shorter
  * than blk_ticks + kticks - 1 the response is split into ceil(kticks /
  * (fft[2] - blk_ticks)) <= 4 consecutive pieces whose outputs are overlap-added.
  * Kernel limits (TRED_EUNSUPPORTED otherwise): blk_pix[a] <= 2 L with L = 8 for
- * spatial sizes 8, 24, 40 and L = 16 for 16, 32, 48, 64; blk_ticks a multiple of 64;
+ * spatial sizes 8, 24, 40 and L = 16 for 16, 32, 48, 64, blk_pix[a] <= 16 for size 36
+ * (the gradient calls do not take size 36); blk_ticks a multiple of 64;
  * kpix must be odd (TRED_EINVAL).
  * flags: TRED_CONV_MPCP pairs impact channels j and its mirror (sub-1-j) into one
  * complex transform (Sec. III-A, eq. multch); it requires the exact point symmetry

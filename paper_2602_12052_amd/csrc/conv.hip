@@ -157,12 +157,13 @@ __global__ void k_rhat_x(ConvArgs A, int Kx, int Ky, const double2* __restrict__
 // so that the nc * L values a thread needs at one frequency lie at fixed offsets.
 // With rpair the rows m of one (ch, f, c) are stored in pairs, [m / 2][item][m % 2],
 // so that a thread reads two rows with one 16-byte load and a wave's loads are
-// contiguous.
+// contiguous; an odd L is padded with one row (m = L, never read by the kernels).
 __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2* __restrict__ twd,
                          const double2* __restrict__ PB, float2* __restrict__ rhat) {
     const int RS = A.fs / L;
     const int TPF = A.fs * RS;
-    const int64_t n = (int64_t)A.nch * A.nc * L * A.ft * TPF;
+    const int LP = A.rpair ? (L + 1) / 2 * 2 : L;   // rows stored per (ch, f, c)
+    const int64_t n = (int64_t)A.nch * A.nc * LP * A.ft * TPF;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = i;
@@ -170,7 +171,7 @@ __global__ void k_rhat_y(ConvArgs A, int Ky, int L, double scale, const double2*
         if (A.rpair) {
             const int e = (int)(r % 2); r /= 2;
             item = (int)(r % TPF); r /= TPF;
-            m = 2 * (int)(r % (L / 2)) + e; r /= L / 2;
+            m = 2 * (int)(r % (LP / 2)) + e; r /= LP / 2;
         } else {
             item = (int)(r % TPF); r /= TPF;
             m = (int)(r % L); r /= L;
@@ -860,7 +861,7 @@ __host__ __device__ inline SppLds spp_lds(int box, int boy) {
 
 // NC: response pieces the accumulators hold (the plan's piece count rounded up to 2 or 4)
 template <int FS, int L, int NIN, int NB, int NC>
-__global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdgpu_waves_per_eu(2))) void k_spp(
+__global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdgpu_waves_per_eu(FS == 36 ? 3 : 2))) void k_spp(
     ConvArgs A, int b0, int nbp, const int32_t* __restrict__ n_active,
     const float2* __restrict__ T, const float2* __restrict__ rhat,
     const float2* __restrict__ tws, float2* __restrict__ U) {
@@ -982,11 +983,11 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     load_T(min(1, A.nch - 1));
     flags(min(2, A.nch - 1));
     __syncthreads();
-    const int64_t rstride = (int64_t)A.nc * L * TPF;   // nc * fs * fs values per (ch, f)
+    constexpr int LP = (L + 1) / 2 * 2;                 // rows stored (odd L: one pad row)
+    const int64_t rstride = (int64_t)A.nc * LP * TPF;   // nc * LP * TPF values per (ch, f)
     // response spectra of (ch, f0 .. f0 + NF - 1) as row pairs [c][m / 2][item][m % 2]
     const uint32_t rbytes = (uint32_t)(NF * rstride * 8);
     const uint32_t rvoff = (uint32_t)(fl * rstride * 8 + item * 16);
-    static_assert(L % 2 == 0, "row pairs");
 
     for (int ch = 0; ch < A.nch; ++ch) {
         const float2* zbuf = zbs(ch);
@@ -1030,8 +1031,8 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         const auto rr = buf_rsrc(rhat + ((int64_t)ch * A.ft + f0) * rstride, rbytes);
         auto load_w = [&](float2* wv, int c) {
 #pragma unroll
-            for (int mp = 0; mp < L / 2; ++mp) {
-                const float4 v = buf_f4(rr, rvoff, (uint32_t)((c * L + 2 * mp) * TPF * 8));
+            for (int mp = 0; mp < LP / 2; ++mp) {
+                const float4 v = buf_f4(rr, rvoff, (uint32_t)((c * LP + 2 * mp) * TPF * 8));
                 wv[2 * mp] = make_float2(v.x, v.y);
                 wv[2 * mp + 1] = make_float2(v.z, v.w);
             }
@@ -1040,7 +1041,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         // WB register buffers: piece c + WB - 1 is requested before the multiply-adds of
         // c (three where the registers allow it)
         constexpr int WB = (RS == 5 || FS == 8) ? 3 : 2;
-        float2 w[WB][L];
+        float2 w[WB][LP];
         load_w(w[0], 0);
         if (WB == 3) load_w(w[1], min(1, clast));
         __builtin_amdgcn_sched_barrier(0);
@@ -1762,6 +1763,7 @@ int spatial_sub_length(int fs) {
     switch (fs) {
         case 8: case 24: case 40: return 8;
         case 16: case 32: case 48: case 64: return 16;
+        case 36: return 9;
         default: return 0;
     }
 }
@@ -1808,7 +1810,7 @@ ConvArgs make_args(const tred_conv_plan* P) {
             if ((L * x) % RS == 1 % RS) { li = x; break; }
         A.e1 = (RS * rsi) % P->fs;
         A.e2 = RS > 1 ? (L * li) % P->fs : 0;
-        A.rpair = 1;   // k_spp reads rows in pairs (L is 8 or 16)
+        A.rpair = 1;   // k_spp reads rows in pairs (an odd L is padded with one row)
     } else {
         A.e1 = RS;
         A.e2 = 1;
@@ -2022,6 +2024,9 @@ tred_status launch_space_any(const tred_conv_plan* P, const ConvArgs& A, int b0,
             case 24:
                 return two ? launch_spp<24, 8, 16, NB8>(A, b0, nb, na, T, rhat, tws, U, st)
                            : launch_spp<24, 8, 8, NB8>(A, b0, nb, na, T, rhat, tws, U, st);
+            case 36:
+                return P->nin == 16 ? launch_spp<36, 9, 16, 1>(A, b0, nb, na, T, rhat, tws, U, st)
+                                    : launch_spp<36, 9, 8, 1>(A, b0, nb, na, T, rhat, tws, U, st);
             case 40:
                 return two ? launch_spp<40, 8, 16, NB8>(A, b0, nb, na, T, rhat, tws, U, st)
                            : launch_spp<40, 8, 8, NB8>(A, b0, nb, na, T, rhat, tws, U, st);
@@ -2086,18 +2091,25 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     if (fsx < P->bo[0] || fsy < P->bo[1])
         return bad(TRED_EINVAL, "spatial FFT sizes must be >= blk_pix + kpix - 1");
     if (fsx != fsy || spatial_sub_length(fsx) == 0)
-        return bad(TRED_EUNSUPPORTED, "spatial FFT sizes must be equal and in {8,16,24,32,40,48,64}");
+        return bad(TRED_EUNSUPPORTED,
+                   "spatial FFT sizes must be equal and in {8,16,24,32,36,40,48,64}");
     const int L = spatial_sub_length(fsx);
-    if (Bx > 2 * L || By > 2 * L) return bad(TRED_EUNSUPPORTED, "blk_pix too large for this FFT size");
+    // inputs per axis of the prime-factor stage: L / 2 (sizes 8 and 16 only), L or 2 L;
+    // size 36 (L = 9) takes 8 or 16 (an even count)
+    const int nin = fsx == 36 ? (std::max(Bx, By) <= 8 ? 8 : 16)
+                              : (fsx <= 16 && std::max(Bx, By) <= L / 2)
+                                    ? L / 2
+                                    : (std::max(Bx, By) <= L ? L : 2 * L);
+    if (Bx > nin || By > nin || Bx > 2 * L || By > 2 * L)
+        return bad(TRED_EUNSUPPORTED, "blk_pix too large for this FFT size");
     if (Bt % 64 != 0) return bad(TRED_EUNSUPPORTED, "blk_ticks must be a multiple of 64");
     if (!is_pow2(ft)) return bad(TRED_EINVAL, "time FFT size must be a power of two");
     if (ft < 256 || ft > 2048) return bad(TRED_EUNSUPPORTED, "time FFT size must be in [256, 2048]");
     if (ft < Bt + 64) return bad(TRED_EINVAL, "time FFT size must be >= blk_ticks + 64");
     P->fs = fsx;
     P->ls = L;
-    P->pfa = (fsx % 32) != 0;   // 8, 16, 24, 40, 48: fs / L is 1 or odd, coprime to L
-    // inputs per axis of the prime-factor stage: L / 2 (sizes 8 and 16 only), L or 2 L
-    P->nin = (fsx <= 16 && std::max(Bx, By) <= L / 2) ? L / 2 : (std::max(Bx, By) <= L ? L : 2 * L);
+    P->pfa = (fsx % 32) != 0;   // 8, 16, 24, 36, 40, 48: L and fs / L coprime
+    P->nin = nin;
     P->spp_nb = L == 8 ? TRED_SPP_NB8 : 1;
     P->ft = ft;
     P->ct = ft - Bt;
@@ -2115,7 +2127,10 @@ extern "C" tred_status tred_conv_plan_create(const tred_grid* grid, const tred_b
     o = align256(o + (int64_t)P->fs * 8);
     P->off_chan = o;
     P->off_rhat = o;
-    o = align256(o + (int64_t)P->nch * P->nc * P->fs * P->fs * ft * 8);
+    // response spectra: fs * fs values per (ch, c, f), or (L + 1) * fs * fs / L with the
+    // pad row of an odd L
+    const int64_t rsp = (int64_t)(L + (L & 1)) * (P->fs / L) * P->fs;
+    o = align256(o + (int64_t)P->nch * P->nc * rsp * ft * 8);
     P->off_scratch_t = o;
     const int64_t tbytes = align256((int64_t)batch * P->nch * ppad * ft * 8);
     const int64_t ubytes = align256((int64_t)batch * P->nc * P->qpad * ft * 8);

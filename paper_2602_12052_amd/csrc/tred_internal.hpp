@@ -111,6 +111,12 @@ constexpr float c51 = 0.30901699437494742f;  // cos(2 pi / 5)
 constexpr float c52 = -0.80901699437494742f; // cos(4 pi / 5)
 constexpr float s51 = 0.95105651629515357f;  // sin(2 pi / 5)
 constexpr float s52 = 0.58778525229247313f;  // sin(4 pi / 5)
+constexpr float c91 = 0.76604444311897801f;  // cos(2 pi / 9)
+constexpr float s91 = 0.64278760968653925f;  // sin(2 pi / 9)
+constexpr float c92 = 0.17364817766693041f;  // cos(4 pi / 9)
+constexpr float s92 = 0.98480775301220802f;  // sin(4 pi / 9)
+constexpr float c94 = -0.93969262078590832f; // cos(8 pi / 9)
+constexpr float s94 = 0.34202014332566888f;  // sin(8 pi / 9)
 }  // namespace cst
 
 template <>
@@ -142,6 +148,33 @@ struct Dft<5> {
         x[4] = csub(r1, cmul_mi(q1));
         x[2] = cadd(r2, cmul_mi(q2));
         x[3] = csub(r2, cmul_mi(q2));
+    }
+};
+
+// 9-point DFT as 3 x 3: n = 3 n1 + n2, k = k1 + 3 k2; 3-point DFTs over n1, the
+// twiddles W9^(n2 k1), 3-point DFTs over n2.
+template <>
+struct Dft<9> {
+    __device__ __forceinline__ static void run(float2* x) {
+        float2 y[3][3];
+#pragma unroll
+        for (int n2 = 0; n2 < 3; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 3; ++n1) y[n2][n1] = x[3 * n1 + n2];
+            Dft<3>::run(y[n2]);
+        }
+        // exp(-2 pi i k / 9) for k = n2 k1 in {1, 2, 4}
+        y[1][1] = cmul(y[1][1], make_float2(cst::c91, -cst::s91));
+        y[1][2] = cmul(y[1][2], make_float2(cst::c92, -cst::s92));
+        y[2][1] = cmul(y[2][1], make_float2(cst::c92, -cst::s92));
+        y[2][2] = cmul(y[2][2], make_float2(cst::c94, -cst::s94));
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+            float2 z[3] = {y[0][k1], y[1][k1], y[2][k1]};
+            Dft<3>::run(z);
+#pragma unroll
+            for (int k2 = 0; k2 < 3; ++k2) x[k1 + 3 * k2] = z[k2];
+        }
     }
 };
 

@@ -155,6 +155,14 @@ def test_footprints_bitexact_adversarial(T, orc):
                                fft=(40, 40, 512), n=15, seed=18), True),
     ("fs48-32-inputs", dict(npix=24, blk=(24, 24, 128), kpix=(15, 15), kticks=200,
                             fft=(48, 48, 512), n=12, seed=19), True),
+    # the 36-point spatial stage (9-point sub-DFTs, a pad row in the response spectra):
+    # exactly blk + kpix - 1 = 36, sixteen and eight inputs per axis, four pieces, plain
+    ("fs36-module-shape", dict(npix=32, nticks=1100, blk=(16, 16, 512), kpix=(21, 21),
+                               kticks=1800, fft=(36, 36, 1024), n=20, seed=22), True),
+    ("fs36-plain", dict(npix=32, nticks=1100, blk=(16, 16, 512), kpix=(21, 21), kticks=600,
+                        fft=(36, 36, 1024), n=20, seed=23), False),
+    ("fs36-eight-inputs", dict(npix=16, blk=(8, 8, 128), kpix=(25, 25), kticks=200,
+                               fft=(36, 36, 512), n=15, seed=24), True),
 ])
 def test_small_paths_match_oracle(T, orc, name, kw, mpcp):
     say(f"test_small_paths_match_oracle[{name}]")
