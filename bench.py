@@ -326,7 +326,8 @@ def bench_batched(args):
     picks = [int(order[int(q * (len(sizes) - 1))]) for q in (0.25, 0.5, 0.75)]
     tune = autotune.tune(g, ph, cfg.kpix, cfg.kticks, dresp,
                          [torch.from_numpy(evs[e]).cuda() for e in picks],
-                         make_blocking=lambda bp, bt: W.Blocking((bp, bp), bt), log=log)
+                         make_blocking=lambda bp, bt: W.Blocking((bp, bp), bt), log=log,
+                         fused=not args.unfused)
     best = tune.best
     blk = W.Blocking((best.blk_pix, best.blk_pix), best.blk_ticks)
     fft = best.fft
@@ -351,7 +352,7 @@ def bench_batched(args):
     bp = tred.BatchPipeline(g, ph, blk, cfg.kpix, cfg.kticks, dresp, max(len(c) for c in chunks),
                             max(c[3] for c in ccap), max(c[0] for c in ccap),
                             max(c[1] for c in ccap), max(c[2] for c in ccap), fft, True,
-                            min(pass_bins, max(c[1] for c in ccap)))
+                            min(pass_bins, max(c[1] for c in ccap)), fused=not args.unfused)
     segs, offs = [], []
     for c in chunks:
         segs.append(torch.from_numpy(np.concatenate([evs[e] for e in c])).cuda())
@@ -398,6 +399,7 @@ def bench_batched(args):
                                f"[1e3, 2e5], per-event track/blob mix",
                    "n_dep": int(sizes.sum()), "active_event_bins": int(bins.sum()),
                    "chunks": len(chunks), "chunk_bins": chunk_bins, "order": "smallest first",
+                   "effective_charge": "patches" if args.unfused else "into the bins",
                    "bins_per_pass": min(pass_bins, max(c[1] for c in ccap)),
                    "blocking": [best.blk_pix, best.blk_pix, best.blk_ticks], "fft": list(fft)},
         "event_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -416,6 +418,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=40)
     ap.add_argument("--plain", action="store_true", help="complex-of-real packing instead of MPCP")
+    ap.add_argument("--unfused", action="store_true",
+                    help="effective charge as patches (tred_effq), then tred_block_bin_rows, "
+                         "instead of straight into the bins (tred_effq_bin)")
     ap.add_argument("--scratch-gb", type=float, default=None,
                     help="bound on the convolution scratch (sets the bins per pass)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -483,8 +488,10 @@ def main():
     box, boy = Bx + cfg.kpix[0] - 1, By + cfg.kpix[1] - 1
     batch = tred.conv_batch(cfg.grid, cfg.blocking, cfg.kpix, cfg.kticks, cfg.fft, mpcp, block_cap,
                             args.scratch_gb * 1e9)
+    fused = not args.unfused
     pl = tred.Pipeline(cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, dev_resp,
-                       seg.shape[0], val_cap, block_cap, pix_cap, cfg.fft, mpcp, batch)
+                       seg.shape[0], val_cap, block_cap, pix_cap, cfg.fft, mpcp, batch,
+                       fused=fused)
     stream = torch.cuda.current_stream().cuda_stream
     ev = HipEvents(12)
     pl.plan.set_timing(ev.handles(range(6, 12)))
@@ -497,11 +504,17 @@ def main():
             ev.record(0, stream)
         tred.tred_effq_windows(pl.grid, pl.phys, dev_seg, pl.fp, pl.off, stream)
         pl.charge_sum.zero_()
-        tred.tred_effq(pl.grid, pl.phys, dev_seg, pl.fp, pl.off, pl.val, pl.charge_sum, stream)
-        if record:
-            ev.record(1, stream)
-        tred.tred_block_bin_rows(pl.grid, pl.blocking, pl.fp, pl.off, pl.val, pl.keys,
-                                 pl.n_active, pl.blocks, pl.rows, pl.bin_work, stream)
+        if fused:
+            if record:
+                ev.record(1, stream)
+            tred.tred_effq_bin(pl.grid, pl.phys, pl.blocking, dev_seg, pl.fp, pl.keys, pl.n_active,
+                               pl.blocks, pl.rows, pl.bin_work, pl.charge_sum, stream)
+        else:
+            tred.tred_effq(pl.grid, pl.phys, dev_seg, pl.fp, pl.off, pl.val, pl.charge_sum, stream)
+            if record:
+                ev.record(1, stream)
+            tred.tred_block_bin_rows(pl.grid, pl.blocking, pl.fp, pl.off, pl.val, pl.keys,
+                                     pl.n_active, pl.blocks, pl.rows, pl.bin_work, stream)
         if record:
             ev.record(2, stream)
         tred.tred_block_conv_rows(pl.plan, pl.n_active, pl.blocks, pl.rows, pl.out_blocks, stream)
@@ -570,9 +583,12 @@ def main():
             "active_fraction": n_act / n_bins_total, "pixels": n_pix,
             "fft": list(cfg.fft), "response_pieces": nc,
             "packing": "mirror-pair" if mpcp else "complex-of-real", "bins_per_conv_pass": batch,
+            "effective_charge": "into the bins (tred_effq_bin)" if fused else
+                                "patches (tred_effq), then tred_block_bin_rows",
         },
         "step_ms": {"p50": float(np.median(per_step)), "p99": float(np.percentile(per_step, 99))},
-        "stage_ms": {"effq_windows+effq": float(stages[:, 0].mean()), "block_bin": float(stages[:, 1].mean()),
+        "stage_ms": {("effq_windows" if fused else "effq_windows+effq"): float(stages[:, 0].mean()),
+                     ("effq_bin" if fused else "block_bin"): float(stages[:, 1].mean()),
                      "block_conv": float(stages[:, 2].mean()), "scatter": float(stages[:, 3].mean()),
                      "conv_time_fwd": float(conv_stages[:, 0].mean()),
                      "conv_space_mac": float(conv_stages[:, 1].mean()),

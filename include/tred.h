@@ -183,6 +183,23 @@ tred_status tred_block_bin_rows_noalloc(const tred_grid* grid, const tred_blocki
                                         int32_t* n_active, float* blocks, uint32_t* rows,
                                         int32_t cap, void* stream);
 
+/* Effective charge straight into the bins (Sec. II-C eq. eff_q, Sec. III-B): the
+ * outputs of tred_effq followed by tred_block_bin_rows (rows non-NULL) or
+ * tred_block_bin (rows NULL), without the patches. The bins are laid out from the
+ * footprints fp of tred_effq_windows (keys, n_active, rows, zeroed rows or bins),
+ * then the effective-charge kernel adds every footprint cell of every deposition
+ * into its bin with an FP32 atomic, so no patch buffer is written or read. Blocks
+ * equal those of the two-call path up to the order of the FP32 additions; cells of
+ * bins beyond cap are dropped as there. charge_sum (may be NULL) accumulates the
+ * node sum of tred_effq. The patch-size limits of tred_effq do not apply.
+ * Requires physics.point_frac > 0 and fewer than 2^31 cells per bin (TRED_EINVAL).
+ * work: tred_block_bin_workspace() bytes. */
+tred_status tred_effq_bin(const tred_grid* grid, const tred_physics* phys,
+                          const tred_blocking* blocking, int64_t n_dep, const float* seg,
+                          const int32_t* fp, int32_t* keys, int32_t* n_active, float* blocks,
+                          uint32_t* rows, int32_t cap, double* charge_sum, void* work,
+                          void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Interlaced convolution with the field response (Sec. II-D, eq. interlaced),
  * evaluated per active bin by FFT with the channel sum in the frequency domain
@@ -290,6 +307,14 @@ tred_status tred_block_bin_events_rows(const tred_grid* grid, const tred_blockin
                                        int64_t val_cap, int32_t* keys, int32_t* n_active,
                                        float* blocks, uint32_t* rows, int32_t cap, void* work,
                                        void* stream);
+/* tred_effq_bin over a batch of events (keys [cap][4] as tred_block_bin_events;
+ * work: tred_block_bin_events_workspace() bytes). */
+tred_status tred_effq_bin_events(const tred_grid* grid, const tred_physics* phys,
+                                 const tred_blocking* blocking, int32_t n_ev,
+                                 const int64_t* ev_off, int64_t n_dep, const float* seg,
+                                 const int32_t* fp, int32_t* keys, int32_t* n_active,
+                                 float* blocks, uint32_t* rows, int32_t cap, double* charge_sum,
+                                 void* work, void* stream);
 int64_t tred_scatter_events_workspace(const tred_conv_plan* plan, int32_t n_ev);
 tred_status tred_scatter_waveforms_events(const tred_conv_plan* plan, int32_t n_ev,
                                           const int32_t* keys, const int32_t* n_active,

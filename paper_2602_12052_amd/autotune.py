@@ -64,10 +64,11 @@ def _bytes_per_bin(grid, blocking, kpix, kticks, fft, mpcp):
 
 def tune(grid, phys, kpix, kticks, resp, seg, mpcp: bool = True,
          candidates: Sequence = DEFAULT_CANDIDATES, budget_bytes: float = 200e9,
-         reps: int = 2, make_blocking=None, log=None) -> TuneResult:
+         reps: int = 2, make_blocking=None, log=None, fused: bool = True) -> TuneResult:
     """Time each candidate on the sample events `seg` (one device tensor, or a list of
     them: the score is the sum of the events' median times) and return the fastest.
-    make_blocking(blk_pix, blk_ticks) builds a blocking object."""
+    make_blocking(blk_pix, blk_ticks) builds a blocking object; fused: time the path
+    with the effective charge added straight into the bins."""
     import torch
     samples = list(seg) if isinstance(seg, (list, tuple)) else [seg]
     trials = []
@@ -87,7 +88,7 @@ def tune(grid, phys, kpix, kticks, resp, seg, mpcp: bool = True,
                 if fixed * bcap + scratch > budget_bytes:
                     raise MemoryError
                 pl = tred.Pipeline(grid, phys, blk, kpix, kticks, resp, sd.shape[0], val_cap, bcap,
-                                   pix_cap, fft, mpcp, nb)
+                                   pix_cap, fft, mpcp, nb, fused=fused)
                 pl.run(sd)
                 torch.cuda.synchronize()
                 ts = []

@@ -51,18 +51,6 @@ struct BinGeom {
     int64_t nbins;   // bins per event
 };
 
-// event of deposition d: ev_off[e] <= d < ev_off[e + 1] (ev_off NULL: one event)
-__device__ __forceinline__ int event_of(int64_t d, const int64_t* __restrict__ ev_off, int nev) {
-    if (ev_off == nullptr) return 0;
-    int lo = 0, hi = nev - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ev_off[mid] <= d) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -336,19 +324,38 @@ BinGeom geom(const tred_grid* g, const tred_blocking* b, int nev, int kst) {
     return G;
 }
 
+// The effective charge computed inside the binning (instead of patches off/val)
+struct FusedEffq {
+    const tred_physics* phys;
+    const float* seg;
+    double* charge_sum;
+};
+
 // rows NULL: every bin is zeroed whole; otherwise the row masks are written and only
-// the marked rows of each bin are zeroed (the other rows are left as they were)
+// the marked rows of each bin are zeroed (the other rows are left as they were).
+// fz non-NULL: the effective charge of the depositions is added into the bins by the
+// effective-charge kernel itself (off, val and val_cap are not used).
 tred_status block_bin(const tred_grid* grid, const tred_blocking* blocking, int32_t n_ev,
                       const int64_t* ev_off, int64_t n_dep, const int32_t* fp, const int64_t* off,
                       const float* val, int64_t val_cap, int32_t* keys, int32_t* n_active,
-                      float* blocks, uint32_t* rows, int32_t cap, void* work, void* stream) {
+                      float* blocks, uint32_t* rows, int32_t cap, void* work, void* stream,
+                      const FusedEffq* fz = nullptr) {
     TRED_TRY(validate_grid(grid));
     TRED_TRY(validate_blocking(blocking));
     TRED_REQUIRE(n_dep >= 0, "n_dep must be >= 0");
     TRED_REQUIRE(cap >= 0, "cap must be >= 0");
     TRED_REQUIRE(n_active && work, "n_active/work is NULL");
     TRED_REQUIRE(cap == 0 || (keys && blocks), "keys/blocks is NULL");
-    TRED_REQUIRE(n_dep == 0 || (fp && off && val), "fp/off/val is NULL");
+    if (fz) {
+        TRED_TRY(validate_physics(fz->phys));
+        TRED_REQUIRE(fz->phys->point_frac > 0.0f, "physics.point_frac must be > 0 for the line form");
+        TRED_REQUIRE(n_dep == 0 || (fp && fz->seg), "seg/fp is NULL");
+        TRED_REQUIRE((int64_t)blocking->blk_pix[0] * grid->sub[0] * blocking->blk_pix[1] * grid->sub[1] *
+                             blocking->blk_ticks <= INT32_MAX,
+                     "cells per bin must be below 2^31");
+    } else {
+        TRED_REQUIRE(n_dep == 0 || (fp && off && val), "fp/off/val is NULL");
+    }
     TRED_REQUIRE(tred_block_count(grid, blocking) > 0, "too many bins");
     TRED_REQUIRE((int64_t)n_ev * tred_block_count(grid, blocking) < INT32_MAX,
                  "too many (event, bin) pairs");
@@ -380,13 +387,29 @@ tred_status block_bin(const tred_grid* grid, const tred_blocking* blocking, int3
                                cap, G.vblk);
             hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(4), 0, st, blocks, n_active, cap, G.vblk);
         }
-        if (n_dep > 0) {
+        if (n_dep > 0 && fz == nullptr) {
             unsigned nb = (unsigned)std::min<int64_t>(n_dep, 1 << 20);
             hipLaunchKernelGGL(k_accum, dim3(nb), dim3(256), 0, st, G, n_dep, fp, off, val, val_cap,
                                ev_off, flag, blocks);
         }
     }
-    return tred_check_launch("tred_block_bin");
+    TRED_TRY(tred_check_launch("tred_block_bin"));
+    if (fz && n_dep > 0) {   // (with cap 0 every slot is -1: only the charge sum)
+        EffqBins B;
+        B.blocks = blocks;
+        B.slot = flag;
+        B.ev_off = ev_off;
+        B.nbins = G.nbins;
+        B.vblk = G.vblk;
+        for (int a = 0; a < 3; ++a) {
+            B.bf[a] = G.bf[a];
+            B.nb[a] = G.nb[a];
+        }
+        B.nev = G.nev;
+        B.inv_bf2 = 1.0f / (float)G.bf[2];
+        TRED_TRY(effq_into_bins(grid, fz->phys, n_dep, fz->seg, fp, B, fz->charge_sum, st));
+    }
+    return TRED_OK;
 }
 
 }  // namespace
@@ -452,6 +475,31 @@ extern "C" tred_status tred_block_bin_rows_noalloc(const tred_grid* grid,
     // do not matter
     return block_bin(grid, blocking, 1, nullptr, n_dep, fp, off, val, val_cap, keys, n_active,
                      blocks, rows, cap, work, stream);
+}
+
+extern "C" tred_status tred_effq_bin(const tred_grid* grid, const tred_physics* phys,
+                                     const tred_blocking* blocking, int64_t n_dep,
+                                     const float* seg, const int32_t* fp, int32_t* keys,
+                                     int32_t* n_active, float* blocks, uint32_t* rows, int32_t cap,
+                                     double* charge_sum, void* work, void* stream) {
+    TRED_REQUIRE(((uintptr_t)rows & 3) == 0, "rows must be 4-byte aligned");
+    const FusedEffq fz{phys, seg, charge_sum};
+    return block_bin(grid, blocking, 1, nullptr, n_dep, fp, nullptr, nullptr, 0, keys, n_active,
+                     blocks, rows, cap, work, stream, &fz);
+}
+
+extern "C" tred_status tred_effq_bin_events(const tred_grid* grid, const tred_physics* phys,
+                                            const tred_blocking* blocking, int32_t n_ev,
+                                            const int64_t* ev_off, int64_t n_dep, const float* seg,
+                                            const int32_t* fp, int32_t* keys, int32_t* n_active,
+                                            float* blocks, uint32_t* rows, int32_t cap,
+                                            double* charge_sum, void* work, void* stream) {
+    TRED_REQUIRE(n_ev > 0, "n_ev must be > 0");
+    TRED_REQUIRE(ev_off != nullptr, "ev_off is NULL");
+    TRED_REQUIRE(((uintptr_t)rows & 3) == 0, "rows must be 4-byte aligned");
+    const FusedEffq fz{phys, seg, charge_sum};
+    return block_bin(grid, blocking, n_ev, ev_off, n_dep, fp, nullptr, nullptr, 0, keys, n_active,
+                     blocks, rows, cap, work, stream, &fz);
 }
 
 extern "C" tred_status tred_block_bin_adjoint(const tred_grid* grid, const tred_blocking* blocking,

@@ -235,19 +235,20 @@ struct Idx3 {
 // stored; per-tile tables give every footprint cell's stencil its weights, zero for
 // nodes outside the window (those reads land on other finite values of the tile).
 // (four waves per SIMD for the 2-point rule: four 256-thread workgroups per CU)
-template <int NGL, int CAP, int NT>
+// BIN: the cells are added into the bins of B (FP32 atomics) instead of being written
+// as patches; off, val and val_cap are not used.
+template <int NGL, int CAP, int NT, bool BIN>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4 : 1))) void k_effq(
-    EffqParams P, int64_t n_dep,
-                                             const float* __restrict__ seg,
-                                             const int32_t* __restrict__ fp,
-                                             const int64_t* __restrict__ off,
-                                             float* __restrict__ val, int64_t val_cap,
-                                             double* __restrict__ charge_sum) {
+    EffqParams P, int64_t n_dep, const float* __restrict__ seg, const int32_t* __restrict__ fp,
+    const int64_t* __restrict__ off, float* __restrict__ val, int64_t val_cap,
+    double* __restrict__ charge_sum, EffqBins B) {
     constexpr int NPOS = NGL / 2;                 // nodes with xi > 0 in a cell
     constexpr int S = NGL + 2 * NPOS;             // stencil nodes per axis
     constexpr int NST = NPOS + NGL;               // sliding state of a column
     constexpr int TX = (S + 1 + 3) / 4 * 4;       // x table row: first node, S weights
-    constexpr int TY = 2 * S;                     // y table row: S offsets, S weights
+    // y table row: S offsets, S weights (BIN: and the y parts of the bin index and of
+    // the cell offset in its bin; the x table row holds the x parts after its weights)
+    constexpr int TY = 2 * S + (BIN ? 2 : 0);
     constexpr int NW = NT / kWave;
     __shared__ __align__(16) float sm[CAP];
     __shared__ double red[NW];
@@ -270,9 +271,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
         const int32_t* f = fp + 6 * d;
         int F0[3] = {f[0], f[1], f[2]}, F1[3] = {f[3], f[4], f[5]};
         if (F1[0] < F0[0] || F1[1] < F0[1] || F1[2] < F0[2]) continue;
-        const int64_t o0 = off[d], o1 = off[d + 1];
-        // patches past val_cap, or of 2^31 cells or more (32-bit offsets), are skipped
-        if (o1 > val_cap || o1 - o0 > INT32_MAX) continue;
+        int64_t o0 = 0;
+        const int32_t* slotp = nullptr;   // BIN: the slot map of this deposition's event
+        if constexpr (BIN) {
+            slotp = B.slot + (int64_t)event_of(d, B.ev_off, B.nev) * B.nbins;
+        } else {
+            const int64_t o1 = off[d + 1];
+            o0 = off[d];
+            // patches past val_cap, or of 2^31 cells or more (32-bit offsets), are skipped
+            if (o1 > val_cap || o1 - o0 > INT32_MAX) continue;
+        }
         float s[7];
 #pragma unroll
         for (int k = 0; k < 7; ++k) s[k] = seg[7 * d + k];
@@ -354,7 +362,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
         }
         // patch of this deposition (its cell count, FX FY FT, is below 2^31: 32-bit offsets)
         const int FY = Fs[1], FT = Fs[2];
-        float* vd = val + o0;
+        float* vd = BIN ? nullptr : val + o0;
         double nsum = 0.0;
 
         for (int X0 = F0[0]; X0 <= F1[0]; X0 += T[0])
@@ -387,6 +395,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
 #pragma unroll
                         for (int a = 0; a < S; ++a)
                             tabx[i * TX + 1 + a] = (x0 + a >= 0 && x0 + a < ncx) ? su[a] : 0.0f;
+                        if constexpr (BIN) {
+                            const int gx = X0 + i, bx = gx / B.bf[0];
+                            tabx[i * TX + S + 1] = __int_as_float(bx * B.nb[1] * B.nb[2]);
+                            tabx[i * TX + S + 2] = __int_as_float((gx - bx * B.bf[0]) * B.bf[1] * B.bf[2]);
+                        }
                     } else {
                         const int y = i - nx;
                         const int y0 = (Y0 + y - 1 - ey0) * NGL + (NGL - NPOS);
@@ -395,6 +408,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
                             const bool ok = y0 + b >= 0 && y0 + b < ncy;
                             taby[y * TY + b] = __int_as_float((ok ? y0 + b : 0) * PY);
                             taby[y * TY + S + b] = ok ? su[b] : 0.0f;
+                        }
+                        if constexpr (BIN) {
+                            const int gy = Y0 + y, by = gy / B.bf[1];
+                            taby[y * TY + 2 * S] = __int_as_float(by * B.nb[2]);
+                            taby[y * TY + 2 * S + 1] = __int_as_float((gy - by * B.bf[1]) * B.bf[2]);
                         }
                     }
                 }
@@ -509,7 +527,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
                                 for (int a = 0; a < S; ++a) ax = fmaf(tx[1 + a], r[a], ax);
                                 acc = fmaf(ty[S + b], ax, acc);
                             }
-                            vd[((X0 + it.i - F0[0]) * FY + (Y0 + it.j - F0[1])) * FT + (Z0 + it.k - F0[2])] = acc;
+                            if constexpr (BIN) {
+                                // t bin of the cell (the binary32 quotient is within one of it)
+                                const int gt = Z0 + it.k;
+                                int bt = (int)((float)gt * B.inv_bf2);
+                                bt -= bt * B.bf[2] > gt ? 1 : 0;
+                                bt += (bt + 1) * B.bf[2] <= gt ? 1 : 0;
+                                const int sl = slotp[__float_as_int(tx[S + 1]) + __float_as_int(ty[2 * S]) + bt];
+                                if (sl >= 0 && acc != 0.0f)
+                                    unsafeAtomicAdd(B.blocks + (int64_t)sl * B.vblk +
+                                                        (__float_as_int(tx[S + 2]) + __float_as_int(ty[2 * S + 1]) +
+                                                         (gt - bt * B.bf[2])),
+                                                    acc);
+                            } else {
+                                vd[((X0 + it.i - F0[0]) * FY + (Y0 + it.j - F0[1])) * FT + (Z0 + it.k - F0[2])] = acc;
+                            }
                         }
                     }
                     __syncthreads();
@@ -562,19 +594,59 @@ void gl_rule(int n, double* xi, double* w) {
     }
 }
 
-template <int NGL>
+template <int NGL, bool BIN>
 void launch_effq(const EffqParams& P, int64_t n_dep, const float* seg, const int32_t* fp,
-                 const int64_t* off, float* val, int64_t val_cap, double* cs, hipStream_t st) {
+                 const int64_t* off, float* val, int64_t val_cap, double* cs, const EffqBins& B,
+                 hipStream_t st) {
     // LDS floats of a tile: at least the tables and window columns of one x-y cell and
     // its neighbours, one tick each, and their sliding state
     constexpr int S = NGL + 2 * (NGL / 2);
-    constexpr int CMIN = 9 * NGL * NGL * (NGL + NGL / 2) + 3 * NGL * (3 * NGL + 1) +
-                         (S + 4) / 4 * 4 + 4 * S;
+    constexpr int TX = (S + 1 + 3) / 4 * 4, TY = 2 * S + (BIN ? 2 : 0);
+    constexpr int CMIN = 9 * NGL * NGL * (NGL + NGL / 2) + 3 * NGL * (3 * NGL + 1) + TX + TY + 2 * S;
     constexpr int CAP = TRED_EFFQ_CAP > CMIN ? TRED_EFFQ_CAP : CMIN;
     constexpr int NT = TRED_EFFQ_NT;
     int64_t grid = n_dep < (1 << 20) ? n_dep : (1 << 20);
-    hipLaunchKernelGGL((k_effq<NGL, CAP, NT>), dim3((unsigned)grid), dim3(NT), 0, st, P, n_dep, seg,
-                       fp, off, val, val_cap, cs);
+    hipLaunchKernelGGL((k_effq<NGL, CAP, NT, BIN>), dim3((unsigned)grid), dim3(NT), 0, st, P, n_dep,
+                       seg, fp, off, val, val_cap, cs, B);
+}
+
+// kernel parameters of the rule with n_gl nodes: nodes, weights and the stencil
+// weights u of one grid point (nodes with xi > 0 of cell g-1 (weight |xi|/2), all
+// nodes of cell g (1 - |xi|/2), nodes with xi < 0 of cell g+1 (|xi|/2))
+EffqParams effq_params(const tred_grid* grid, const tred_physics* phys) {
+    EffqParams P;
+    P.g = *grid;
+    P.ph = *phys;
+    double xi[8], w[8];
+    const int n = phys->n_gl;
+    gl_rule(n, xi, w);
+    for (int i = 0; i < 8; ++i) {
+        P.xi[i] = i < n ? (float)xi[i] : 0.f;
+        P.w[i] = i < n ? (float)w[i] : 0.f;
+    }
+    const int npos = n / 2;
+    int k = 0;
+    for (int l = n - npos; l < n; ++l) P.u[k++] = (float)(std::fabs(xi[l]) / 2.0);
+    for (int l = 0; l < n; ++l) P.u[k++] = (float)(1.0 - std::fabs(xi[l]) / 2.0);
+    for (int l = 0; l < npos; ++l) P.u[k++] = (float)(std::fabs(xi[l]) / 2.0);
+    for (; k < 16; ++k) P.u[k] = 0.f;
+    return P;
+}
+
+template <bool BIN>
+void launch_effq_rule(const EffqParams& P, int64_t n_dep, const float* seg, const int32_t* fp,
+                      const int64_t* off, float* val, int64_t val_cap, double* cs,
+                      const EffqBins& B, hipStream_t st) {
+    switch (P.ph.n_gl) {
+        case 1: launch_effq<1, BIN>(P, n_dep, seg, fp, off, val, val_cap, cs, B, st); break;
+        case 2: launch_effq<2, BIN>(P, n_dep, seg, fp, off, val, val_cap, cs, B, st); break;
+        case 3: launch_effq<3, BIN>(P, n_dep, seg, fp, off, val, val_cap, cs, B, st); break;
+        case 4: launch_effq<4, BIN>(P, n_dep, seg, fp, off, val, val_cap, cs, B, st); break;
+        case 5: launch_effq<5, BIN>(P, n_dep, seg, fp, off, val, val_cap, cs, B, st); break;
+        case 6: launch_effq<6, BIN>(P, n_dep, seg, fp, off, val, val_cap, cs, B, st); break;
+        case 7: launch_effq<7, BIN>(P, n_dep, seg, fp, off, val, val_cap, cs, B, st); break;
+        default: launch_effq<8, BIN>(P, n_dep, seg, fp, off, val, val_cap, cs, B, st); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -937,34 +1009,18 @@ extern "C" tred_status tred_effq(const tred_grid* grid, const tred_physics* phys
     if (n_dep == 0) return TRED_OK;
     TRED_REQUIRE(seg && fp && off, "seg/fp/off is NULL");
     TRED_REQUIRE(val != nullptr || val_cap == 0, "val is NULL");
-    EffqParams P;
-    P.g = *grid;
-    P.ph = *phys;
-    double xi[8], w[8];
-    const int n = phys->n_gl;
-    gl_rule(n, xi, w);
-    for (int i = 0; i < 8; ++i) {
-        P.xi[i] = i < n ? (float)xi[i] : 0.f;
-        P.w[i] = i < n ? (float)w[i] : 0.f;
-    }
-    // stencil of grid point g: nodes with xi > 0 of cell g-1 (weight |xi|/2), all
-    // nodes of cell g (1 - |xi|/2), nodes with xi < 0 of cell g+1 (|xi|/2)
-    const int npos = n / 2;
-    int k = 0;
-    for (int l = n - npos; l < n; ++l) P.u[k++] = (float)(std::fabs(xi[l]) / 2.0);
-    for (int l = 0; l < n; ++l) P.u[k++] = (float)(1.0 - std::fabs(xi[l]) / 2.0);
-    for (int l = 0; l < npos; ++l) P.u[k++] = (float)(std::fabs(xi[l]) / 2.0);
-    for (; k < 16; ++k) P.u[k] = 0.f;
-    hipStream_t st = (hipStream_t)stream;
-    switch (n) {
-        case 1: launch_effq<1>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
-        case 2: launch_effq<2>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
-        case 3: launch_effq<3>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
-        case 4: launch_effq<4>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
-        case 5: launch_effq<5>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
-        case 6: launch_effq<6>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
-        case 7: launch_effq<7>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
-        default: launch_effq<8>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, st); break;
-    }
+    const EffqParams P = effq_params(grid, phys);
+    launch_effq_rule<false>(P, n_dep, seg, fp, off, val, val_cap, charge_sum, EffqBins{},
+                            (hipStream_t)stream);
     return tred_check_launch("tred_effq");
+}
+
+// (the binning has laid out the bins: slot map, zeroed rows; validated by the caller)
+tred_status effq_into_bins(const tred_grid* grid, const tred_physics* phys, int64_t n_dep,
+                           const float* seg, const int32_t* fp, const EffqBins& B,
+                           double* charge_sum, hipStream_t st) {
+    if (n_dep == 0) return TRED_OK;
+    const EffqParams P = effq_params(grid, phys);
+    launch_effq_rule<true>(P, n_dep, seg, fp, nullptr, nullptr, 0, charge_sum, B, st);
+    return tred_check_launch("effective charge into the bins");
 }

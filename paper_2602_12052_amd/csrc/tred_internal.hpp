@@ -22,6 +22,41 @@ constexpr int kWave = 64;
 constexpr unsigned kXcd = 8;   // XCDs of an MI355X; workgroup ids are dealt to them round-robin
 
 // ---------------------------------------------------------------------------
+// effective charge added straight into the bins (effq.hip computes, bin.hip lays
+// out the bins): the binning's bin -> slot map (slot, or -1 for a bin that is not
+// held) and the geometry needed to address a fine cell inside its bin
+// ---------------------------------------------------------------------------
+struct EffqBins {
+    float* blocks;
+    const int32_t* slot;     // [nev][nbins]
+    const int64_t* ev_off;   // event bounds over the depositions; NULL: one event
+    int64_t nbins;           // bins per event
+    int64_t vblk;            // cells per bin
+    int32_t bf[3];           // bin extent in fine cells
+    int32_t nb[3];           // bins per axis
+    int32_t nev;
+    float inv_bf2;           // 1 / bf[2] (binary32; bin index corrected by +-1)
+};
+
+// event of deposition d: ev_off[e] <= d < ev_off[e + 1] (ev_off NULL: one event)
+__device__ __forceinline__ int event_of(int64_t d, const int64_t* __restrict__ ev_off, int nev) {
+    if (ev_off == nullptr) return 0;
+    int lo = 0, hi = nev - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ev_off[mid] <= d) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// (effq.hip) the effective charge of every deposition added into the bins of B
+// (FP32 atomics), as tred_effq followed by the accumulation of the binning
+tred_status effq_into_bins(const tred_grid* grid, const tred_physics* phys, int64_t n_dep,
+                           const float* seg, const int32_t* fp, const EffqBins& B,
+                           double* charge_sum, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // complex arithmetic on float2
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }

@@ -74,6 +74,7 @@ EXPORTS = [
     "tred_scatter_waveforms_adjoint", "tred_block_conv_adjoint", "tred_block_bin_adjoint",
     "tred_effq_adjoint", "tred_block_row_words", "tred_block_bin_rows", "tred_block_conv_rows",
     "tred_block_bin_events_rows", "tred_block_conv_adjoint_rows", "tred_block_bin_rows_noalloc",
+    "tred_effq_bin", "tred_effq_bin_events",
 ]
 
 _lib = None
@@ -139,6 +140,8 @@ def lib():
     L.tred_block_conv_rows.argtypes = [P, P, I32, P, P, P, P]
     L.tred_block_bin_events_rows.argtypes = [P, P, I32, P, I64, P, P, P, I64, P, P, P, P, I32,
                                              P, P]
+    L.tred_effq_bin.argtypes = [P, P, P, I64, P, P, P, P, P, P, I32, P, P, P]
+    L.tred_effq_bin_events.argtypes = [P, P, P, I32, P, I64, P, P, P, P, P, P, I32, P, P, P]
     L.tred_block_conv_adjoint_rows.argtypes = [P, P, I32, P, P, P, P]
     L.tred_block_bin_rows_noalloc.argtypes = [P, P, I64, P, P, P, I64, P, P, P, P, I32, P]
     for name in ("tred_effq_windows", "tred_effq", "tred_block_bin", "tred_conv_plan_create",
@@ -344,6 +347,50 @@ def tred_block_bin_rows(grid, blocking, fp, off, val, keys, n_active, blocks, ro
                                      _ptr(rows), cap, _ptr(work), _stream(stream)))
 
 
+def _bin_out_check(grid, blocking, keys, n_active, blocks, rows, kst):
+    import torch
+    _dt(keys, torch.int32, "keys"), _dt(n_active, torch.int32, "n_active")
+    _dt(blocks, torch.float32, "blocks"), _dt(rows, torch.int32, "rows")
+    cap = 0 if keys is None else keys.shape[0]
+    if cap and keys.shape[1] != kst:
+        raise ValueError(f"keys must be [cap][{kst}]")
+    if cap and (blocks is None or blocks.shape[0] < cap):
+        raise ValueError("blocks has fewer rows than keys")
+    if rows is not None:
+        if rows.shape[0] < cap:
+            raise ValueError("rows has fewer rows than keys")
+        if rows.shape[1] != tred_block_row_words(grid, blocking):
+            raise ValueError("rows must have tred_block_row_words() columns")
+    return cap
+
+
+def tred_effq_bin(grid, phys, blocking, seg, fp, keys, n_active, blocks, rows, work,
+                  charge_sum=None, stream=None):
+    """Effective charge added straight into the bins: the outputs of tred_effq followed
+    by tred_block_bin_rows (rows given) or tred_block_bin (rows None), without patches."""
+    import torch
+    cap = _bin_out_check(grid, blocking, keys, n_active, blocks, rows, 3)
+    _dt(charge_sum, torch.float64, "charge_sum")
+    g, p, b = grid_struct(grid), physics_struct(phys), blocking_struct(blocking)
+    _check(lib().tred_effq_bin(C.byref(g), C.byref(p), C.byref(b), seg.shape[0], _ptr(seg),
+                               _ptr(fp), _ptr(keys), _ptr(n_active), _ptr(blocks), _ptr(rows),
+                               cap, _ptr(charge_sum), _ptr(work), _stream(stream)))
+
+
+def tred_effq_bin_events(grid, phys, blocking, ev_off, seg, fp, keys, n_active, blocks, rows,
+                         work, charge_sum=None, stream=None):
+    """tred_effq_bin over a batch of events (keys [cap][4])."""
+    import torch
+    _dt(ev_off, torch.int64, "ev_off")
+    cap = _bin_out_check(grid, blocking, keys, n_active, blocks, rows, 4)
+    _dt(charge_sum, torch.float64, "charge_sum")
+    g, p, b = grid_struct(grid), physics_struct(phys), blocking_struct(blocking)
+    _check(lib().tred_effq_bin_events(C.byref(g), C.byref(p), C.byref(b), ev_off.numel() - 1,
+                                      _ptr(ev_off), seg.shape[0], _ptr(seg), _ptr(fp), _ptr(keys),
+                                      _ptr(n_active), _ptr(blocks), _ptr(rows), cap,
+                                      _ptr(charge_sum), _ptr(work), _stream(stream)))
+
+
 def tred_block_bin_rows_noalloc(grid, blocking, fp, off, val, keys, n_active, blocks, rows,
                                 stream=None):
     """tred_block_bin_rows without a workspace (the library's static per-device scratch;
@@ -519,19 +566,25 @@ class Pipeline:
     host synchronisation (capacities fixed at construction)."""
 
     def __init__(self, grid, phys, blocking, kpix, kticks, resp, n_dep, val_cap, block_cap,
-                 pix_cap, fft=None, mpcp=True, batch=64, row_masks=True):
+                 pix_cap, fft=None, mpcp=True, batch=64, row_masks=True, fused=False):
         """row_masks: bin with row masks (only the rows a footprint reaches are written
-        and transformed); False leaves every row of `blocks` defined (dense blocks)."""
+        and transformed); False leaves every row of `blocks` defined (dense blocks).
+        fused: the effective charge goes straight into the bins (tred_effq_bin): no
+        patches are kept (results() has no "val"; val_cap only sizes the gradient's
+        patch buffer)."""
         import torch
         dev = "cuda"
         self.grid, self.phys, self.blocking = grid_struct(grid), physics_struct(phys), \
             blocking_struct(blocking)
         self.n_dep = int(n_dep)
+        self.fused = bool(fused)
+        self.val_cap = int(val_cap)
         self.plan = ConvPlan(grid, blocking, kpix, kticks, fft, mpcp, batch)
         self.plan.set_response(resp)
         self.fp = torch.empty((self.n_dep, 6), dtype=torch.int32, device=dev)
         self.off = torch.empty(self.n_dep + 1, dtype=torch.int64, device=dev)
-        self.val = torch.empty(int(val_cap), dtype=torch.float32, device=dev)
+        self.val = None if self.fused else torch.empty(self.val_cap, dtype=torch.float32,
+                                                       device=dev)
         self.charge_sum = torch.zeros(1, dtype=torch.float64, device=dev)
         self.keys = torch.empty((int(block_cap), 3), dtype=torch.int32, device=dev)
         self.n_active = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -555,10 +608,18 @@ class Pipeline:
     def run(self, seg, stream=None, stop_after: Optional[str] = None):
         tred_effq_windows(self.grid, self.phys, seg, self.fp, self.off, stream)
         self.charge_sum.zero_()
-        tred_effq(self.grid, self.phys, seg, self.fp, self.off, self.val, self.charge_sum, stream)
-        if stop_after == "effq":
-            return
-        self.bin(stream)
+        if self.fused:
+            if stop_after == "effq":
+                raise ValueError("a fused pipeline has no separate effective-charge stage")
+            tred_effq_bin(self.grid, self.phys, self.blocking, seg, self.fp, self.keys,
+                          self.n_active, self.blocks, self.rows, self.bin_work, self.charge_sum,
+                          stream)
+        else:
+            tred_effq(self.grid, self.phys, seg, self.fp, self.off, self.val, self.charge_sum,
+                      stream)
+            if stop_after == "effq":
+                return
+            self.bin(stream)
         if stop_after == "bin":
             return
         self.conv(stream)
@@ -590,7 +651,7 @@ class Pipeline:
         if not hasattr(self, "d_out_blocks"):
             self.d_out_blocks = torch.empty_like(self.out_blocks)
             self.d_blocks = torch.empty_like(self.blocks)
-            self.d_val = torch.empty_like(self.val)
+            self.d_val = torch.empty(self.val_cap, dtype=torch.float32, device="cuda")
             self.d_seg = torch.empty((self.n_dep, 7), dtype=torch.float32, device="cuda")
             self.d_phys = torch.zeros(3, dtype=torch.float64, device="cuda")
         tred_scatter_waveforms_adjoint(self.plan, self.keys, self.n_active, self.pix, self.n_pix,
@@ -613,8 +674,10 @@ class Pipeline:
         patch length off[n], the active-bin count or the pixel count exceeds the
         buffer it was given, so part of the event was dropped). Synchronises."""
         n = self.n_dep if n_dep is None else int(n_dep)
-        _check_counts(int(self.off[n].item()), self.val.numel(), int(self.n_active.item()),
-                      self.keys.shape[0], int(self.n_pix.item()), self.pix.shape[0])
+        # (fused: no patches are stored, so the patch length bounds nothing)
+        nval = 0 if self.fused else int(self.off[n].item())
+        _check_counts(nval, self.val_cap, int(self.n_active.item()), self.keys.shape[0],
+                      int(self.n_pix.item()), self.pix.shape[0])
 
     def results(self, check=True):
         """Host copies of the outputs (synchronises); raises TredError if the run
@@ -628,7 +691,7 @@ class Pipeline:
         npx = int(self.n_pix.item())
         nval = int(self.off[-1].item())
         return dict(fp=self.fp.cpu().numpy(), off=self.off.cpu().numpy(),
-                    val=self.val[:min(nval, self.val.numel())].cpu().numpy(),
+                    val=None if self.fused else self.val[:min(nval, self.val_cap)].cpu().numpy(),
                     charge_sum=float(self.charge_sum.item()), n_active=na,
                     keys=self.keys[:min(na, self.keys.shape[0])].cpu().numpy(), n_pix=npx,
                     pix=self.pix[:min(npx, self.pix.shape[0])].cpu().numpy(),
@@ -679,9 +742,13 @@ class BatchPipeline:
     capture it in a HIP graph per batch shape)."""
 
     def __init__(self, grid, phys, blocking, kpix, kticks, resp, n_ev_max, n_dep_max, val_cap,
-                 block_cap, pix_cap, fft=None, mpcp=True, batch=64, plan=None, row_masks=True):
+                 block_cap, pix_cap, fft=None, mpcp=True, batch=64, plan=None, row_masks=True,
+                 fused=False):
+        """fused: effective charge straight into the bins (tred_effq_bin_events), no
+        patch buffer (val_cap is then ignored)."""
         import torch
         dev = "cuda"
+        self.fused = bool(fused)
         self.grid, self.phys, self.blocking = grid_struct(grid), physics_struct(phys), \
             blocking_struct(blocking)
         self.n_ev_max, self.n_dep_max = int(n_ev_max), int(n_dep_max)
@@ -692,7 +759,8 @@ class BatchPipeline:
         g, b = self.grid, self.blocking
         self.fp = torch.empty((self.n_dep_max, 6), dtype=torch.int32, device=dev)
         self.off = torch.empty(self.n_dep_max + 1, dtype=torch.int64, device=dev)
-        self.val = torch.empty(int(val_cap), dtype=torch.float32, device=dev)
+        self.val = None if self.fused else torch.empty(int(val_cap), dtype=torch.float32,
+                                                       device=dev)
         self.charge_sum = torch.zeros(1, dtype=torch.float64, device=dev)
         self.keys = torch.empty((int(block_cap), 4), dtype=torch.int32, device=dev)
         self.n_active = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -721,16 +789,24 @@ class BatchPipeline:
         fp, off = self.fp[:n], self.off[:n + 1]
         tred_effq_windows(self.grid, self.phys, seg, fp, off, stream)
         self.charge_sum.zero_()
-        tred_effq(self.grid, self.phys, seg, fp, off, self.val, self.charge_sum, stream)
+        if self.fused:
+            tred_effq_bin_events(self.grid, self.phys, self.blocking, ev_off, seg, fp, self.keys,
+                                 self.n_active, self.blocks, self.rows, self.bin_work,
+                                 self.charge_sum, stream)
+        else:
+            tred_effq(self.grid, self.phys, seg, fp, off, self.val, self.charge_sum, stream)
+            if self.rows is not None:
+                tred_block_bin_events_rows(self.grid, self.blocking, ev_off, fp, off, self.val,
+                                           self.keys, self.n_active, self.blocks, self.rows,
+                                           self.bin_work, stream)
+            else:
+                tred_block_bin_events(self.grid, self.blocking, ev_off, fp, off, self.val,
+                                      self.keys, self.n_active, self.blocks, self.bin_work,
+                                      stream)
         if self.rows is not None:
-            tred_block_bin_events_rows(self.grid, self.blocking, ev_off, fp, off, self.val,
-                                       self.keys, self.n_active, self.blocks, self.rows,
-                                       self.bin_work, stream)
             tred_block_conv_rows(self.plan, self.n_active, self.blocks, self.rows, self.out_blocks,
                                  stream)
         else:
-            tred_block_bin_events(self.grid, self.blocking, ev_off, fp, off, self.val, self.keys,
-                                  self.n_active, self.blocks, self.bin_work, stream)
             tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
         tred_scatter_waveforms_events(self.plan, n_ev, self.keys, self.n_active, self.out_blocks,
                                       self.pix, self.n_pix, self.wf, self.scat_work, stream)
@@ -743,7 +819,7 @@ class BatchPipeline:
         n = self.n_dep_max if n_dep is None else int(n_dep)
         na = int(self.n_active.item())
         npx = int(self.n_pix.item())
-        if n_dep is not None:
+        if n_dep is not None and not self.fused:
             _check_counts(int(self.off[n].item()), self.val.numel(), na, self.keys.shape[0],
                           npx, self.pix.shape[0])
         else:

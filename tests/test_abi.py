@@ -239,3 +239,36 @@ def test_noalloc_binning_rejects_grids_beyond_its_scratch(T):
     assert L.tred_block_bin_rows_noalloc(C.byref(gs), C.byref(bs), 1, p, p, p, 10, p, p, p, p, 4,
                                          None) == T.TRED_ECAPACITY
     assert b"static scratch" in L.tred_last_error()
+
+
+def test_fused_effq_bin_rejects(T):
+    """The effective charge into the bins checks its parameters on the host before any
+    work is enqueued: 4-byte aligned row masks, the line form's point_frac > 0, an
+    event batch with its offsets, and bins small enough for 32-bit cell offsets."""
+    L = T.lib()
+    cfg = _cfg()
+    g, b = T.grid_struct(cfg.grid), T.blocking_struct(cfg.blocking)
+    ph = T.physics_struct(cfg.physics)
+    p = C.c_void_p(0x1000)  # never dereferenced
+    assert L.tred_effq_bin(C.byref(g), C.byref(ph), C.byref(b), 1, p, p, p, p, p,
+                           C.c_void_p(0x1002), 4, None, p, None) == T.TRED_EINVAL
+    assert b"rows" in L.tred_last_error()
+    ph0 = T.physics_struct(cfg.physics)
+    ph0.point_frac = 0.0
+    assert L.tred_effq_bin(C.byref(g), C.byref(ph0), C.byref(b), 1, p, p, p, p, p, p, 4, None, p,
+                           None) == T.TRED_EINVAL
+    assert b"point_frac" in L.tred_last_error()
+    assert L.tred_effq_bin(C.byref(g), None, C.byref(b), 1, p, p, p, p, p, p, 4, None, p,
+                           None) == T.TRED_EINVAL
+    assert b"physics" in L.tred_last_error()
+    assert L.tred_effq_bin_events(C.byref(g), C.byref(ph), C.byref(b), 2, None, 1, p, p, p, p, p,
+                                  p, 4, None, p, None) == T.TRED_EINVAL
+    assert b"ev_off" in L.tred_last_error()
+    assert L.tred_effq_bin_events(C.byref(g), C.byref(ph), C.byref(b), 0, p, 1, p, p, p, p, p, p,
+                                  4, None, p, None) == T.TRED_EINVAL
+    big_g = W.Grid(origin=(0.0, 0.0, 0.0), spacing=(0.044, 0.044, W.TICK), npix=(1024, 1024),
+                   sub=(10, 10), nticks=2048)
+    gb, bb = T.grid_struct(big_g), T.blocking_struct(W.Blocking((512, 512), 1024))
+    assert L.tred_effq_bin(C.byref(gb), C.byref(ph), C.byref(bb), 1, p, p, p, p, p, p, 4, None, p,
+                           None) == T.TRED_EINVAL
+    assert b"cells per bin" in L.tred_last_error()

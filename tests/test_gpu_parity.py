@@ -60,13 +60,13 @@ def small_cfg(npix=6, sub=3, nticks=200, blk=(2, 2, 64), kpix=(3, 5), kticks=100
 
 
 def gpu_path(T, g, ph, blk, kpix, kticks, fft, seg, resp, mpcp=True, batch=8, block_cap=None,
-             check=True):
+             check=True, fused=False):
     say(f"  gpu path: npix={g.npix} sub={g.sub} nticks={g.nticks} blk={blk.blk_pix}x{blk.blk_ticks}"
-        f" K={kpix}x{kticks} fft={fft} n={seg.shape[0]} mpcp={mpcp}")
+        f" K={kpix}x{kticks} fft={fft} n={seg.shape[0]} mpcp={mpcp} fused={fused}")
     sd = dev(seg)
     val_cap, bcap, pix_cap = T.size_event(g, ph, blk, kpix, sd)
     pl = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap,
-                    block_cap or bcap, pix_cap, fft, mpcp, batch)
+                    block_cap or bcap, pix_cap, fft, mpcp, batch, fused=fused)
     pl.run(sd)
     if not check:
         with pytest.raises(T.TredError, match="active bins"):
@@ -409,9 +409,13 @@ def test_block_capacity_truncation(T, orc):
 # ---------------------------------------------------------------------------
 
 
-@pytest.fixture(scope="module")
-def module_run(T):
-    say("module-scale event (1e5 depositions, 256x256 pixels, 21x21x2048 response)")
+@pytest.fixture(scope="module", params=["patches", "fused"])
+def module_run(T, request):
+    """The module event through the two-call path (patches, then binning) and through
+    the path bench.py times (effective charge added straight into the bins)."""
+    fused = request.param == "fused"
+    say(f"module-scale event (1e5 depositions, 256x256 pixels, 21x21x2048 response), "
+        f"{request.param}")
     cfg = W.cfg_module()
     seg = W.gen_segments(cfg)
     resp = W.synthetic_response(cfg.kpix, cfg.grid.sub, cfg.kticks)
@@ -423,7 +427,7 @@ def module_run(T):
                          T.DEFAULT_CONV_SCRATCH)
     say(f"  {bcap} active bins, {batch} bins per convolution pass")
     r = gpu_path(T, cfg.grid, cfg.physics, cfg.blocking, cfg.kpix, cfg.kticks, cfg.fft, seg, resp,
-                 mpcp=True, batch=batch)
+                 mpcp=True, batch=batch, fused=fused)
     return cfg, seg, resp, r
 
 
@@ -444,6 +448,8 @@ def test_module_integer_outputs_bitexact(module_run, orc):
 def test_module_sampled_patches(module_run, orc):
     say("test_module_sampled_patches")
     cfg, seg, resp, r = module_run
+    if r["val"] is None:
+        pytest.skip("the fused path keeps no patches (its bins are checked by test_gpu_fused)")
     rng = np.random.default_rng(1)
     pick = np.sort(rng.choice(seg.shape[0], 300, replace=False))
     fp, off = r["fp"], r["off"]
