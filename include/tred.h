@@ -127,7 +127,8 @@ tred_status tred_effq_windows(const tred_grid* grid, const tred_physics* phys, i
  * val_cap: length of val; depositions whose patch would end past val_cap are
  * skipped (the caller detects this from off[n_dep] > val_cap), and so are patches of
  * 2^31 cells or more (off[d+1] - off[d] > INT32_MAX; their values are not written).
- * charge_sum (may be NULL): binary64 sum over all evaluated nodes of w * q,
+ * charge_sum (may be NULL): sum over all evaluated nodes of w * q (binary32 along
+ * one column of nodes within a tile of cells, binary64 over columns),
  * accumulated (not overwritten) by this call. */
 tred_status tred_effq(const tred_grid* grid, const tred_physics* phys, int64_t n_dep,
                       const float* seg, const int32_t* fp, const int64_t* off, float* val,

@@ -128,14 +128,7 @@ __global__ __launch_bounds__(256) void k_zero_blocks(float4* __restrict__ blocks
     const int64_t n4 = na * vblk / 4;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * blockDim.x)
-#if TRED_NT_STORE
-    {
-        using f4 = __attribute__((ext_vector_type(4))) float;
-        __builtin_nontemporal_store((f4){0.f, 0.f, 0.f, 0.f}, (f4*)(blocks + i));
-    }
-#else
         blocks[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-#endif
 }
 
 __global__ __launch_bounds__(256) void k_zero_tail(float* __restrict__ blocks,

@@ -36,7 +36,7 @@
 #endif
 // persistent workgroups of the forward time FFTs (at most)
 #ifndef TRED_TF_GRID
-#define TRED_TF_GRID 8192
+#define TRED_TF_GRID 16384
 #endif
 // wave-level ordering inside the inverse time FFTs (1) or workgroup barriers (0)
 #ifndef TRED_TI_WAVESYNC

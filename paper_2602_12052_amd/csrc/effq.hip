@@ -441,7 +441,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
                         const bool cnt = cx >= ox0 && cx <= ox1 && cy >= oy0 && cy <= oy1;
                         const float bxy = rx * gvec[0] + ry * gvec[1];
                         const float exy = rx * rx * isg2[0] + ry * ry * isg2[1];
-                        // w * q of the NGL nodes of cell ct (zero outside the window)
+                        // w * q of the NGL nodes of cell ct (zero outside the window); the
+                        // column's nodes are summed in binary32 (csum: at most the T2 + 2
+                        // cells of this tile) and the sum joins the binary64 total once
+                        float csum = 0.0f;
                         auto cell = [&](int ct, float* q) {
                             const bool in = ct >= C0[2] && ct <= C1[2];
                             const float ctf = (float)(ct - W.lo[2]);
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
                                     v = pref * exp_neg_half(e) * erf_diff(kq * (1.0f - sst), -kq * sst);
                                 }
                                 q[l] = in ? wt * v : 0.0f;
-                                if (cnt) nsum += (double)q[l];
+                                csum += q[l];
                             }
                         };
                         float hold[NPOS > 0 ? NPOS : 1], cur[NGL], nxt[NGL];
@@ -506,6 +509,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
 #pragma unroll
                             for (int k = 0; k < NGL; ++k) stc[NPOS + k] = cur[k];
                         }
+                        if (cnt) nsum += (double)csum;
                     }
                     __syncthreads();
                     // 2) x and y parts of the spread: each footprint cell of the tile sums the

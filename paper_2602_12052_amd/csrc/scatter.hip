@@ -88,14 +88,17 @@ __global__ __launch_bounds__(1024) void k_compact_pix(ScatArgs S, int32_t* __res
 }
 
 // One workgroup per pixel slot (slots at or past n_pix get a zero waveform). Its threads
-// walk the waveform in spans of 1024 ticks, four ticks per thread, so the pixel's bin
-// lookups are made once per span. Per
+// walk the waveform in spans of kGatherSpan ticks (kGatherSpan / 256 per thread), so the
+// pixel's bin lookups are made once per span. Per
 // sample the covering bins are summed in (bx, by, bt) order. The loads carry no
 // branches, so a thread keeps the loads of four bins in flight: each block-output row
 // is read through a buffer resource of its own length (ticks outside it read zero),
 // and the bin slots of a column are loaded once per wave (one per lane); the active
 // ones are found by a ballot and taken with readlane.
-constexpr int kGatherSpan = 1024;
+#ifndef TRED_GATHER_SPAN
+#define TRED_GATHER_SPAN 2048
+#endif
+constexpr int kGatherSpan = TRED_GATHER_SPAN;
 
 __global__ __launch_bounds__(256) void k_gather(ScatArgs S, const int32_t* __restrict__ pix,
                                                 const int32_t* __restrict__ n_pix,

@@ -259,7 +259,7 @@ __device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, uint32_t voff
 // Streaming stores of data read only by a later kernel (larger than the L2) may carry
 // the non-temporal cache policy (TRED_NT_STORE).
 #ifndef TRED_NT_STORE
-#define TRED_NT_STORE 0
+#define TRED_NT_STORE 1
 #endif
 __device__ __forceinline__ void buf_st_f2(float2 v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
                                           uint32_t soff) {

@@ -151,7 +151,10 @@ def check_same(a, b):
     say(f"  {a['n_active']} bins; blocks rel-L2 {e:.2e}, max |diff| / max {m:.2e}; charge sums "
         f"{a['charge_sum']:.9e} / {b['charge_sum']:.9e}")
     assert e < ORDER_TOL and m < 10 * ORDER_TOL
-    assert abs(a["charge_sum"] - b["charge_sum"]) <= 1e-12 * abs(a["charge_sum"])
+    # node sums: binary32 along a column within a tile, whose size differs between the
+    # two kernels (the fused one's tables are wider), binary64 over columns; both are
+    # held to the oracle's 1e-6 elsewhere
+    assert abs(a["charge_sum"] - b["charge_sum"]) <= 1e-6 * abs(a["charge_sum"])
 
 
 @pytest.mark.parametrize("name,kw,rows_on", [
