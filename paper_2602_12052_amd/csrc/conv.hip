@@ -38,6 +38,12 @@
 #ifndef TRED_TF_GRID
 #define TRED_TF_GRID 16384
 #endif
+// forward spatial stage: one barrier per channel, the x pass of the next channel in
+// the phase of the current one's y pass and multiply-adds (1: x pass first, 2: after),
+// or two phases per channel (0)
+#ifndef TRED_SPP_PIPE
+#define TRED_SPP_PIPE 1
+#endif
 // wave-level ordering inside the inverse time FFTs (1) or workgroup barriers (0)
 #ifndef TRED_TI_WAVESYNC
 #define TRED_TI_WAVESYNC 1
@@ -852,7 +858,9 @@ __host__ __device__ inline SppLds spp_lds(int box, int boy) {
     if (a2 > a) a = a2;
     int b = s.ysz;
     if (RS > 1 && s.y2sz > b) b = s.y2sz;
-    if (s.zsz > b) b = s.zsz;   // B also holds the forward stage's second staging buffer
+    // B also holds the forward stage's second staging buffer and, with the channel
+    // pipeline, the second x-pass output after it
+    if (s.zsz + s.asz > b) b = s.zsz + s.asz;
     s.A = even_up(a);
     s.B = even_up(b);
     s.total = s.tw + s.A + s.B;
@@ -901,7 +909,10 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     float2* regB = regA + Ls.A;
     // staged time spectra [NB][NF][NIN px][NIN py] of channels ch (even, odd) in two
     // buffers: the next channel's are staged while this one's are transformed
-    auto zbs = [&](int ch) { return (ch & 1) ? regB : regA; };
+    // (an offset, not a choice between two pointers: a pointer pair indexed by the
+    // channel parity ends up in scratch memory)
+    const int zdelta = Ls.A;                // regB - regA
+    auto zbs = [&](int ch) { return regA + (ch & 1) * zdelta; };
     float2* abuf = regA + Ls.zsz;           // [NB][NF][FS kx][P1 py]
     for (int i = tid; i < FS; i += NT) twl[i] = tws[i];
 
@@ -989,9 +1000,8 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     const uint32_t rbytes = (uint32_t)(NF * rstride * 8);
     const uint32_t rvoff = (uint32_t)(fl * rstride * 8 + item * 16);
 
-    for (int ch = 0; ch < A.nch; ++ch) {
-        const float2* zbuf = zbs(ch);
-        // x pass: for each (bin, frequency, py, k2x) an L-point DFT over the gathered px
+    // x pass: for each (bin, frequency, py, k2x) an L-point DFT over the gathered px
+    auto xpass = [&](const float2* zbuf, float2* ab) {
         for (int i = tid; i < NB * NF * NIN * RS; i += NT) {
             const int kk = i % RS;
             int r = i / RS;
@@ -1012,22 +1022,23 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
 #pragma unroll
                 for (int m = 0; m < L; ++m) t[m] = make_float2(0.f, 0.f);
             }
-            float2* ar = abuf + bf * FS * P1 + py;
+            float2* ar = ab + bf * FS * P1 + py;
 #pragma unroll
             for (int m = 0; m < L; ++m) ar[P::k_of(m, kk) * P1] = t[m];
         }
-        __syncthreads();
-        // y pass and multiply-accumulate with the response spectra of every piece. The
-        // spectra of piece 0 are requested before the y pass and those of piece c + 1
-        // before the multiply-adds of piece c (two register buffers), so L2 latency is
-        // covered by arithmetic. Vector loads complete in issue order, so a wait for
-        // response spectra also waits for every time-spectra load issued before them:
-        // the time spectra of channel ch + 2 are requested after the last piece's
-        // response spectra, which leaves the rest of this channel and the x and y passes
-        // of the next before any wait depends on them, and those of channel ch + 1 are
-        // staged after the y pass. Everything is unconditional: pieces past nc load
-        // piece nc - 1 again and accumulate into slots that are never read, the last
-        // channels request the last channel again.
+    };
+    // y pass and multiply-accumulate with the response spectra of every piece, for
+    // channel ch from the x-pass output ab. The spectra of piece 0 are requested before
+    // the y pass and those of piece c + 1 before the multiply-adds of piece c (two or
+    // three register buffers), so L2 latency is covered by arithmetic. Vector loads
+    // complete in issue order, so a wait for response spectra also waits for every
+    // time-spectra load issued before them: the time spectra of channel ch + AH + 1 are
+    // requested after the last piece's response spectra, which leaves the rest of this
+    // channel and what follows before any wait depends on them, and those of channel
+    // ch + AH (requested AH channels ago) are staged after the y pass. Everything is
+    // unconditional: pieces past nc load piece nc - 1 again and accumulate into slots
+    // that are never read, the last channels request the last channel again.
+    auto ymac = [&](int ch, const float2* ab, int AH) {
         const auto rr = buf_rsrc(rhat + ((int64_t)ch * A.ft + f0) * rstride, rbytes);
         auto load_w = [&](float2* wv, int c) {
 #pragma unroll
@@ -1049,7 +1060,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         if (active) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const float4* ar4 = (const float4*)(abuf + ((b * NF + fl) * FS + kx) * P1);
+                const float4* ar4 = (const float4*)(ab + ((b * NF + fl) * FS + kx) * P1);
                 float2 x[NIN];
 #pragma unroll
                 for (int q = 0; q < NIN / 2; ++q) {
@@ -1061,16 +1072,16 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 Dft<L>::run(s[b]);
             }
         }
-        // channel ch + 1 into the other buffer (the x pass of ch - 1 that read it ended
-        // before this channel's x pass)
-        store_T(zbs(ch + 1));
+        // channel ch + AH into its buffer (the x pass that last read that buffer ended
+        // before this phase)
+        store_T(zbs(ch + AH));
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (c + WB - 1 < NC) load_w(w[(c + WB - 1) % WB], min(c + WB - 1, clast));
             if (c == (NC > WB ? NC - WB : 0)) {   // after the last piece's request (and store_T)
                 __builtin_amdgcn_sched_barrier(0);   // vector loads complete in issue order
-                load_T(min(ch + 2, A.nch - 1));
-                flags(min(ch + 3, A.nch - 1));
+                load_T(min(ch + AH + 1, A.nch - 1));
+                flags(min(ch + AH + 2, A.nch - 1));
             }
             __builtin_amdgcn_sched_barrier(0);
             if (active) {
@@ -1082,7 +1093,33 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+    };
+    if constexpr (TRED_SPP_PIPE != 0) {
+        // channel pipeline: the x pass of channel ch + 1 and the y pass and
+        // multiply-adds of channel ch share one phase (one barrier per channel); the
+        // x-pass output is double-buffered after the staged time spectra of the same
+        // channel parity
+        auto abufs = [&](int ch) { return zbs(ch) + Ls.zsz; };
+        xpass(zbs(0), abufs(0));
+        store_T(zbs(1));
+        load_T(min(2, A.nch - 1));
+        flags(min(3, A.nch - 1));
         __syncthreads();
+        for (int ch = 0; ch < A.nch; ++ch) {
+            if (TRED_SPP_PIPE == 1 && ch + 1 < A.nch) xpass(zbs(ch + 1), abufs(ch + 1));
+            __builtin_amdgcn_sched_barrier(0);
+            ymac(ch, abufs(ch), 2);
+            __builtin_amdgcn_sched_barrier(0);
+            if (TRED_SPP_PIPE == 2 && ch + 1 < A.nch) xpass(zbs(ch + 1), abufs(ch + 1));
+            __syncthreads();
+        }
+    } else {
+        for (int ch = 0; ch < A.nch; ++ch) {
+            xpass(zbs(ch), abuf);
+            __syncthreads();
+            ymac(ch, abuf, 1);
+            __syncthreads();
+        }
     }
 
     // inverse spatial transforms of every response piece and the mirror-pair unpacking
