@@ -1000,7 +1000,13 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     const uint32_t rbytes = (uint32_t)(NF * rstride * 8);
     const uint32_t rvoff = (uint32_t)(fl * rstride * 8 + item * 16);
 
-    // x pass: for each (bin, frequency, py, k2x) an L-point DFT over the gathered px
+    // x pass: for each (bin, frequency, py, k2x) an L-point DFT over the gathered px.
+    // With at most one item per thread its phase factors are read once, here (not at
+    // fs 36, whose three waves per SIMD cap the registers at 168).
+    constexpr bool XONE = NB * NF * NIN * RS <= NT && FS != 36;
+    float2 wx[RS];
+#pragma unroll
+    for (int j = 0; j < RS; ++j) wx[j] = twl[((j * (tid % RS)) % RS) * L];
     auto xpass = [&](const float2* zbuf, float2* ab) {
         for (int i = tid; i < NB * NF * NIN * RS; i += NT) {
             const int kk = i % RS;
@@ -1015,7 +1021,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 for (int px = 0; px < NIN; ++px) x[px] = zr[px * NIN];
                 float2 w[RS];
 #pragma unroll
-                for (int j = 0; j < RS; ++j) w[j] = twl[((j * kk) % RS) * L];
+                for (int j = 0; j < RS; ++j) w[j] = XONE ? wx[j] : twl[((j * kk) % RS) * L];
                 pfa_gather<L, RS, NIN>(x, w, t);
                 Dft<L>::run(t);
             } else {
