@@ -239,9 +239,9 @@ def bench_adjoint(args):
     caps = [max(a, b) for a, b in zip(tred.size_event(g, ph, blk, cfg.kpix, sd),
                                       tred.size_event(g, pt, blk, cfg.kpix, sd))]
     pl = tred.Pipeline(g, ph, blk, cfg.kpix, cfg.kticks, dresp, seg.shape[0], caps[0], caps[1],
-                       caps[2], cfg.fft, True, caps[1])
+                       caps[2], cfg.fft, True, caps[1], fused=not args.unfused)
     tgt = tred.Pipeline(g, pt, blk, cfg.kpix, cfg.kticks, dresp, seg.shape[0], caps[0], caps[1],
-                        caps[2], cfg.fft, True, caps[1])
+                        caps[2], cfg.fft, True, caps[1], fused=not args.unfused)
     tgt.run(sd)
     torch.cuda.synchronize()
     nt = int(tgt.n_pix.item())
@@ -292,6 +292,7 @@ def bench_adjoint(args):
                                "x 6250 ticks, response 21x21 px x 2048 ticks, bins 16x16 px x 512 "
                                "ticks; target waveforms with diff_T +10 %, diff_L -10 %, lifetime "
                                "+20 %", "n_dep": int(seg.shape[0]),
+                   "effective_charge": "patches" if args.unfused else "into the bins",
                    "active_bins": int(pl.n_active.item()), "pixels": int(pl.n_pix.item())},
         "step_ms": {"p50": float(np.percentile(ts, 50)), "p99": float(np.percentile(ts, 99))},
         "stage_ms": {"forward": float(np.median(tf)), "loss+gradient": float(np.median(tb))},

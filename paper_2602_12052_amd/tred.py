@@ -648,6 +648,13 @@ class Pipeline:
         The chain runs the four adjoint calls on the integer structures of run()
         (footprints, keys, pixel list); the effective charge is recomputed."""
         import torch
+        if self.fused:
+            # the forward pass kept no patches, so only here does the patch length meet
+            # the buffer it sizes (the patch gradient): refuse a truncated gradient
+            nval = int(self.off[self.n_dep].item())
+            if nval > self.val_cap:
+                raise TredError(TRED_ECAPACITY, f"backward: patch cells {nval} > val capacity "
+                                                f"{self.val_cap}")
         if not hasattr(self, "d_out_blocks"):
             self.d_out_blocks = torch.empty_like(self.out_blocks)
             self.d_blocks = torch.empty_like(self.blocks)

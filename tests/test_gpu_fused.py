@@ -255,3 +255,55 @@ def test_fused_batch_pipeline_matches_two_call_path(T):
     e = rel_l2(b["wf"], a["wf"])
     say(f"  {a['n_active']} (event, bin) pairs; waveforms rel-L2 {e:.2e}")
     assert e < ORDER_TOL
+
+
+def test_fused_pipeline_gradient_matches_two_call_path(T):
+    """The gradient of a fixed waveform weighting through a fused pipeline (no patches
+    in the forward pass; the transposed calls use a patch-sized gradient buffer of
+    val_cap cells) equals the two-call pipeline's: both run the same transposed calls
+    on the same footprints, keys and pixels."""
+    import torch
+    say("test_fused_pipeline_gradient_matches_two_call_path")
+    g, ph, blk, seg = config(n=15, seed=13)
+    kpix, kticks, fft = (3, 5), 100, (8, 8, 256)
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=3)
+    sd = dev(seg)
+    val_cap, bcap, pix_cap = T.size_event(g, ph, blk, kpix, sd)
+    res = []
+    for fused in (False, True):
+        pl = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap, bcap,
+                        pix_cap, fft, True, 4, fused=fused)
+        pl.run(sd)
+        npx = int(pl.n_pix.item())
+        c = np.cos(0.03 * np.arange(pl.wf.numel(), dtype=np.float64)).reshape(pl.wf.shape)
+        c[npx:] = 0.0
+        d_seg, d_phys = pl.backward(sd, dev(c.astype(np.float32)))
+        torch.cuda.synchronize()
+        res.append((pl.pix[:npx].cpu().numpy(), d_seg.double().cpu().numpy(),
+                    d_phys.cpu().numpy().copy()))
+    (pa, ga, fa), (pb, gb, fb) = res
+    assert np.array_equal(pa, pb)
+    e = rel_l2(gb, ga)
+    ep = float(np.max(np.abs(fb - fa) / np.maximum(np.abs(fa), 1e-300)))
+    say(f"  d_seg rel-L2 {e:.2e}, d_phys max rel {ep:.2e}")
+    assert e < ORDER_TOL and ep < 1e-6
+
+
+def test_fused_backward_refuses_small_patch_buffer(T):
+    """A fused pipeline built with fewer patch cells than the event needs runs its
+    forward pass (which keeps no patches) but refuses the gradient instead of
+    truncating it."""
+    say("test_fused_backward_refuses_small_patch_buffer")
+    g, ph, blk, seg = config(n=15, seed=14)
+    kpix, kticks, fft = (3, 5), 100, (8, 8, 256)
+    resp = W.random_symmetric_response(kpix, g.sub, kticks, seed=3)
+    sd = dev(seg)
+    val_cap, bcap, pix_cap = T.size_event(g, ph, blk, kpix, sd)
+    pl = T.Pipeline(g, ph, blk, kpix, kticks, dev(resp), seg.shape[0], val_cap // 2, bcap,
+                    pix_cap, fft, True, 4, fused=True)
+    pl.run(sd)
+    r = pl.results()             # the forward pass needs no patch buffer
+    assert r["n_pix"] > 0
+    import torch
+    with pytest.raises(T.TredError, match="patch cells"):
+        pl.backward(sd, torch.zeros_like(pl.wf))
