@@ -430,7 +430,7 @@ def main():
                     help="module: the benchmark event; plain-small: the 1,000-segment event")
     ap.add_argument("--events", type=int, default=64, help="events of the batched form")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="device memory of a chunk")
-    ap.add_argument("--chunk-bins", type=int, default=1024,
+    ap.add_argument("--chunk-bins", type=int, default=512,
                     help="(event, bin) pairs per chunk of the batched form (at least one event)")
     ap.add_argument("--pass-gb", type=float, default=60.0, help="convolution scratch per pass")
     ap.add_argument("--form", default="fft",
