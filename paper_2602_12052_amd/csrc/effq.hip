@@ -421,6 +421,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
                     const int nz = Z1 - Z0 + 1;
                     const bool first = Z0 == F0[2], last = Z1 == F1[2];
                     // 1) columns: node charges along t, t part of the spread
+                    const int c0t = __builtin_amdgcn_readfirstlane(C0[2]);
+                    const int c1t = __builtin_amdgcn_readfirstlane(C1[2]);
                     for (int c = tid; c < ncw; c += NT) {
                         const int yn = c / ncx, xn = c - yn * ncx;
                         const int cx = ex0 + xn / NGL, lx = xn % NGL;
@@ -446,7 +448,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
                         // cells of this tile) and the sum joins the binary64 total once
                         float csum = 0.0f;
                         auto cell = [&](int ct, float* q) {
-                            const bool in = ct >= C0[2] && ct <= C1[2];
+                            // ct is the same for every column of the tile: the cells
+                            // outside the window (two at each end of a column) are
+                            // skipped by the whole workgroup
+                            const int cts = __builtin_amdgcn_readfirstlane(ct);
+                            if (cts < c0t || cts > c1t) {
+#pragma unroll
+                                for (int l = 0; l < NGL; ++l) q[l] = 0.0f;
+                                return;
+                            }
                             const float ctf = (float)(ct - W.lo[2]);
 #pragma unroll
                             for (int l = 0; l < NGL; ++l) {
@@ -469,7 +479,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NGL <= 2 ? 4
                                     const float e = px * px * isg2[0] + py * py * isg2[1] + pt * pt * isg2[2];
                                     v = pref * exp_neg_half(e) * erf_diff(kq * (1.0f - sst), -kq * sst);
                                 }
-                                q[l] = in ? wt * v : 0.0f;
+                                q[l] = wt * v;
                                 csum += q[l];
                             }
                         };
