@@ -163,6 +163,10 @@ def test_footprints_bitexact_adversarial(T, orc):
                         fft=(36, 36, 1024), n=20, seed=23), False),
     ("fs36-eight-inputs", dict(npix=16, blk=(8, 8, 128), kpix=(25, 25), kticks=200,
                                fft=(36, 36, 512), n=15, seed=24), True),
+    # 12-pixel bins with sixteen inputs per axis at fs 40: the x pass by half rows of
+    # pixels meets rows that straddle two time-spectrum groups, and rows past By
+    ("fs40-12px-half-rows", dict(npix=24, nticks=700, blk=(12, 12, 512), kpix=(21, 21),
+                                 kticks=1800, fft=(40, 40, 1024), n=20, seed=25), True),
 ])
 def test_small_paths_match_oracle(T, orc, name, kw, mpcp):
     say(f"test_small_paths_match_oracle[{name}]")
