@@ -664,77 +664,28 @@ void launch_effq_rule(const EffqParams& P, int64_t n_dep, const float* seg, cons
 }
 
 // ---------------------------------------------------------------------------
-// Gradient of the effective charge (Sec. V-C). The node charge q = Qp g(r, D, sigma)
-// is differentiated in forward mode with respect to the node offset r (3), the
-// segment vector D (3) and the widths sigma (3) (dual numbers, binary32); per node the
-// gradient of the loss with respect to its charge is the transposed trilinear spread
-// G_n = sum over the grid points g whose stencil holds n of u(g, n) dL/dV_g. The
-// sums over nodes (binary64) are carried through the chain rule of the transport
-// (t = z / v, t_mid, the widths and Qp = Q exp(-t_mid / lifetime)) per deposition.
+// Gradient of the effective charge (Sec. V-C), in closed form. The node charge is
+// q = Qp g(r, D, sigma) with r the node's offset from the segment start (from the
+// midpoint for a point charge), D the segment vector and sigma the widths. With
+// I_a = 1 / sigma_a^2, alpha = sum D_a^2 I_a, s = (sum r_a D_a I_a) / alpha the
+// parameter of the closest point, p = r - s D the offset from it, k = sqrt(alpha / 2)
+// and the erf limits A = -k s, B = k (1 - s), the line charge is
+//   g = N (erf B - erf A),  N = exp(-sum p_a^2 I_a / 2) / (4 pi sigma_x sigma_y sigma_t sqrt(alpha)).
+// Differentiating through alpha, s and the limits, with gA, gB the erf derivatives
+// (2 / sqrt(pi)) exp(-A^2), exp(-B^2), phi = N k (gB - gA) / alpha and
+// psi = N (gB (1 - s) + gA s) / (2 k):
+//   dg/dr_a     = I_a (-g p_a - phi D_a)
+//   dg/dD_a     = I_a ((g s - phi) p_a + (phi s + psi - g / alpha) D_a)
+//   dg/dsigma_a = (I_a / sigma_a) (g p_a^2 + 2 phi p_a D_a + (g / alpha - psi) D_a^2) - g / sigma_a
+// (point charge: phi = psi = 0, no alpha terms). The per-deposition factors (I_a, D_a,
+// alpha, sigma_a) come out of the sums over nodes, so each node adds G_n w_n times
+// g, g p_a, g p_a^2, g s p_a, phi, phi p_a, phi s and psi into sixteen binary64 sums,
+// G_n = sum over the grid points c whose stencil holds n of u(c, n) dL/dV_c being the
+// transposed trilinear spread. Writing the gradient in p rather than r keeps the terms
+// of a long segment (|r| up to its length, |p| a few widths) free of cancellation.
+// The sums then go through the chain rule of the transport (t = z / v, t_mid, the
+// widths and Qp = Q exp(-t_mid / lifetime)) once per deposition.
 // ---------------------------------------------------------------------------
-constexpr int kNd = 9;   // partials: r_x, r_y, r_t, D_x, D_y, D_t, sigma_x, sigma_y, sigma_t
-struct Dual {
-    float v;
-    float d[kNd];
-};
-__device__ __forceinline__ Dual dconst(float v) {
-    Dual a;
-    a.v = v;
-#pragma unroll
-    for (int k = 0; k < kNd; ++k) a.d[k] = 0.f;
-    return a;
-}
-__device__ __forceinline__ Dual dvar(float v, int j) {
-    Dual a = dconst(v);
-#pragma unroll
-    for (int k = 0; k < kNd; ++k) a.d[k] = k == j ? 1.f : 0.f;
-    return a;
-}
-__device__ __forceinline__ Dual operator+(const Dual& a, const Dual& b) {
-    Dual c;
-    c.v = a.v + b.v;
-#pragma unroll
-    for (int k = 0; k < kNd; ++k) c.d[k] = a.d[k] + b.d[k];
-    return c;
-}
-__device__ __forceinline__ Dual operator-(const Dual& a, const Dual& b) {
-    Dual c;
-    c.v = a.v - b.v;
-#pragma unroll
-    for (int k = 0; k < kNd; ++k) c.d[k] = a.d[k] - b.d[k];
-    return c;
-}
-__device__ __forceinline__ Dual operator*(const Dual& a, const Dual& b) {
-    Dual c;
-    c.v = a.v * b.v;
-#pragma unroll
-    for (int k = 0; k < kNd; ++k) c.d[k] = a.d[k] * b.v + a.v * b.d[k];
-    return c;
-}
-__device__ __forceinline__ Dual operator*(float s, const Dual& a) {
-    Dual c;
-    c.v = s * a.v;
-#pragma unroll
-    for (int k = 0; k < kNd; ++k) c.d[k] = s * a.d[k];
-    return c;
-}
-// f(a) with f(a.v) = fv and f'(a.v) = fp
-__device__ __forceinline__ Dual dapply(const Dual& a, float fv, float fp) {
-    Dual c;
-    c.v = fv;
-#pragma unroll
-    for (int k = 0; k < kNd; ++k) c.d[k] = fp * a.d[k];
-    return c;
-}
-__device__ __forceinline__ Dual drcp(const Dual& a) {
-    const float r = 1.0f / a.v;
-    return dapply(a, r, -r * r);
-}
-__device__ __forceinline__ Dual dsqrt(const Dual& a) {
-    const float r = sqrtf(a.v);
-    return dapply(a, r, 0.5f / r);
-}
-
 template <int NGL>
 __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
                                                   const float* __restrict__ seg,
@@ -743,7 +694,9 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
                                                   const float* __restrict__ dval, int64_t val_cap,
                                                   float* __restrict__ dseg,
                                                   double* __restrict__ dphys) {
-    constexpr int NT = 256, NW = NT / kWave, NA = 10;
+    constexpr int NT = 256, NW = NT / kWave;
+    // sums over nodes: g, g p (3), g p^2 (3), g s p (3), phi, phi p (3), phi s, psi
+    enum { SG = 0, SGP = 1, SGP2 = 4, SGSP = 7, SPHI = 10, SPHP = 11, SPHS = 14, SPSI = 15, NA = 16 };
     constexpr int CAPA = 12288;   // patch cells staged in LDS (larger patches read memory)
     __shared__ double red[NW][NA];
     __shared__ float sdv[CAPA];
@@ -778,12 +731,25 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
         base[1] = (double)g.origin[1] + ((double)W.lo[1] + 0.5) * h[1] - (double)s[1];
         base[2] = (double)g.origin[2] + (double)W.lo[2] * h[2] - t0;
         const bool point = W.point != 0;
-        float fb[3], fh[3];
+        // per-deposition factors in binary32, as the nodes use them
+        float fb[3], fh[3], Df[3], Is[3];
+        float alf = 0.0f;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             fb[a] = (float)(point ? base[a] - 0.5 * D[a] : base[a]);
             fh[a] = (float)h[a];
+            Df[a] = point ? 0.0f : (float)D[a];
+            const float sf = (float)sg[a];
+            Is[a] = 1.0f / (sf * sf);
+            alf = fmaf(Df[a] * Df[a], Is[a], alf);
         }
+        const double ssp = (double)(float)sg[0] * (double)(float)sg[1] * (double)(float)sg[2];
+        // (2 pi)^(-3/2) / (sigma_x sigma_y sigma_t), or 1 / (4 pi sigma_x sigma_y sigma_t sqrt(alpha))
+        const float pref = point ? (float)(0.0634936359342409697 / ssp)
+                                 : (float)(0.0795774715459476679 / (ssp * sqrt((double)alf)));
+        const float ial = point ? 0.0f : 1.0f / alf;
+        const float kq = sqrtf(0.5f * alf);
+        const float kia = kq * ial, hik = point ? 0.0f : 0.5f / kq;
         const float jac = (float)(h[0] * h[1] * h[2] / 8.0);
         int C0[3], C1[3], nn[3];
 #pragma unroll
@@ -844,53 +810,48 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
                 }
             }
             if (G == 0.0f) continue;
-            const float rx = fb[0] + ((float)(cc[0] - W.lo[0]) + 0.5f * xi[0]) * fh[0];
-            const float ry = fb[1] + ((float)(cc[1] - W.lo[1]) + 0.5f * xi[1]) * fh[1];
-            const float rt = fb[2] + ((float)(cc[2] - W.lo[2]) + 0.5f * xi[2]) * fh[2];
-            const Dual R[3] = {dvar(rx, 0), dvar(ry, 1), dvar(rt, 2)};
-            const Dual SG[3] = {dvar((float)sg[0], 6), dvar((float)sg[1], 7), dvar((float)sg[2], 8)};
-            Dual IS[3];
+            float r[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) IS[a] = drcp(SG[a] * SG[a]);
-            const Dual ssp = SG[0] * SG[1] * SG[2];
-            Dual gq;
+            for (int a = 0; a < 3; ++a) r[a] = fb[a] + ((float)(cc[a] - W.lo[a]) + 0.5f * xi[a]) * fh[a];
+            const float w = G * wt * jac;
             if (point) {
-                const Dual e = R[0] * R[0] * IS[0] + R[1] * R[1] * IS[1] + R[2] * R[2] * IS[2];
-                const float ex = exp_neg(-0.5f * e.v);
-                const Dual E = dapply(e, ex, -0.5f * ex);
-                gq = (0.0634936359342409697f) * (E * drcp(ssp));   // (2 pi)^(-3/2)
-            } else {
-                const Dual Dd[3] = {dvar((float)D[0], 3), dvar((float)D[1], 4), dvar((float)D[2], 5)};
-                const Dual al = Dd[0] * Dd[0] * IS[0] + Dd[1] * Dd[1] * IS[1] + Dd[2] * Dd[2] * IS[2];
-                const Dual be = R[0] * Dd[0] * IS[0] + R[1] * Dd[1] * IS[1] + R[2] * Dd[2] * IS[2];
-                const Dual sst = be * drcp(al);
-                Dual e = dconst(0.f);
+                const float e = r[0] * r[0] * Is[0] + r[1] * r[1] * Is[1] + r[2] * r[2] * Is[2];
+                const float wg = w * (pref * exp_neg(-0.5f * e));
+                acc[SG] += (double)wg;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const Dual pa = R[a] - sst * Dd[a];
-                    e = e + pa * pa * IS[a];
+                    acc[SGP + a] += (double)(wg * r[a]);
+                    acc[SGP2 + a] += (double)(wg * r[a] * r[a]);
                 }
-                const float ex = exp_neg(-0.5f * e.v);
-                const Dual E = dapply(e, ex, -0.5f * ex);
-                const Dual kq = dsqrt(0.5f * al);
-                const Dual A1 = dconst(0.f) - kq * sst;         // lower limit
-                const Dual B1 = kq - kq * sst;                  // upper limit
-                const float ed = erf_diff(B1.v, A1.v);
-                const float gb = 1.12837916709551257f * exp_neg(-B1.v * B1.v);
-                const float ga = 1.12837916709551257f * exp_neg(-A1.v * A1.v);
-                Dual Ed;
-                Ed.v = ed;
+            } else {
+                const float sst = (r[0] * Df[0] * Is[0] + r[1] * Df[1] * Is[1] + r[2] * Df[2] * Is[2]) * ial;
+                float p[3], e = 0.0f;
 #pragma unroll
-                for (int k = 0; k < kNd; ++k) Ed.d[k] = gb * B1.d[k] - ga * A1.d[k];
-                // 1 / (4 pi sigma_x sigma_y sigma_t sqrt(alpha))
-                gq = (0.0795774715459476679f) * (E * Ed * drcp(ssp * dsqrt(al)));
+                for (int a = 0; a < 3; ++a) {
+                    p[a] = r[a] - sst * Df[a];
+                    e = fmaf(p[a] * p[a], Is[a], e);
+                }
+                const float N = pref * exp_neg(-0.5f * e);
+                const float A1 = -kq * sst, B1 = kq - kq * sst;
+                const float gb = 1.12837916709551257f * exp_neg(-B1 * B1);   // 2 / sqrt(pi)
+                const float ga = 1.12837916709551257f * exp_neg(-A1 * A1);
+                const float wg = w * (N * erf_diff(B1, A1));
+                const float wph = w * (N * (gb - ga) * kia);
+                const float wps = w * (N * fmaf(gb, 1.0f - sst, ga * sst) * hik);
+                acc[SG] += (double)wg;
+                acc[SPHI] += (double)wph;
+                acc[SPHS] += (double)(wph * sst);
+                acc[SPSI] += (double)wps;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    acc[SGP + a] += (double)(wg * p[a]);
+                    acc[SGP2 + a] += (double)(wg * p[a] * p[a]);
+                    acc[SGSP + a] += (double)(wg * sst * p[a]);
+                    acc[SPHP + a] += (double)(wph * p[a]);
+                }
             }
-            const double Gw = (double)G * (double)wt * (double)jac;
-            acc[9] += Gw * (double)gq.v;
-#pragma unroll
-            for (int k = 0; k < kNd; ++k) acc[k] += Gw * Qp * (double)gq.d[k];
         }
-        // workgroup reduction of the ten sums
+        // workgroup reduction of the sums
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
             double x = acc[k];
@@ -900,13 +861,23 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
         }
         __syncthreads();
         if (tid == 0) {
-            double A[NA];
+            double S[NA];
 #pragma unroll
             for (int k = 0; k < NA; ++k) {
-                A[k] = 0.0;
-                for (int w = 0; w < NW; ++w) A[k] += red[w][k];
+                S[k] = 0.0;
+                for (int w = 0; w < NW; ++w) S[k] += red[w][k];
             }
-            // A[0..2]: d/dr, A[3..5]: d/dD, A[6..8]: d/dsigma, A[9]: d/dQp
+            // A[0..2]: d/dr, A[3..5]: d/dD, A[6..8]: d/dsigma (each times Qp), A[9]: d/dQp
+            double A[10];
+            const double sgS = S[SG], ia = point ? 0.0 : 1.0 / (double)alf;
+            for (int a = 0; a < 3; ++a) {
+                const double I = (double)Is[a], Da = (double)Df[a], sa = (double)(float)sg[a];
+                A[a] = Qp * I * (-S[SGP + a] - Da * S[SPHI]);
+                A[3 + a] = Qp * I * (S[SGSP + a] - S[SPHP + a] + Da * (S[SPHS] + S[SPSI] - sgS * ia));
+                A[6 + a] = Qp * ((I / sa) * (S[SGP2 + a] + 2.0 * Da * S[SPHP + a] +
+                                             Da * Da * (sgS * ia - S[SPSI])) - sgS / sa);
+            }
+            A[9] = sgS;
             double dP0[3], dP1[3];
             for (int a = 0; a < 3; ++a) {
                 if (point) {
