@@ -30,6 +30,12 @@
 #ifndef TRED_XCD_REMAP
 #define TRED_XCD_REMAP 1
 #endif
+// transposed spatial stage at L = 8 (fs 24, 40): response-spectrum pieces requested
+// ahead of the multiply-adds (register buffers; 2 keeps the kernel within three waves
+// per SIMD)
+#ifndef TRED_SPP_ADJ_PRE
+#define TRED_SPP_ADJ_PRE 2
+#endif
 // bins per workgroup of the transposed spatial stage at fs = 40
 #ifndef TRED_SPP_ADJ_NB
 #define TRED_SPP_ADJ_NB 1
@@ -1514,8 +1520,9 @@ __host__ __device__ inline SppAdjLds<FS, L, NIN, NB> spp_adj_lds(int box, int bo
     s.g2 = RS > 1 ? NB * NF * NIN * L * RS : 0;
     s.ob = NB * NF * Bx * By;
     s.A = even_up(s.du + s.a2);
+    // the pipelined channel loop (RS > 1) holds the four stage buffers apart
     int bb = s.gb > s.g2 + s.ob ? s.gb : s.g2 + s.ob;
-    s.B = even_up(bb + s.yb);
+    s.B = RS > 1 ? even_up(s.gb + s.yb + s.g2 + s.ob) : even_up(bb + s.yb);
     s.total = s.tw + (s.A > s.B ? s.A : s.B);
     return s;
 }
@@ -1530,13 +1537,18 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     constexpr int RS = S::RS, TPF = S::TPF, NF = S::NF, NT = S::NT;
     extern __shared__ float4 sm4[];
     float2* sm = (float2*)sm4;
-    const unsigned nbg = gridDim.x;
+    // bins fastest in the logical order; each XCD walks a contiguous range of
+    // frequencies (as in k_spp), so a response-spectrum slab is fetched into one L2
+    const unsigned nbg = gridDim.x, total = gridDim.x * gridDim.y;
+    const unsigned wid = blockIdx.y * nbg + blockIdx.x;
+    unsigned lid = wid;
+    if (TRED_XCD_REMAP && total % kXcd == 0) lid = (wid % kXcd) * (total / kXcd) + wid / kXcd;
     const int na = min(*n_active, A.cap);
     const int nloc = min(nbp, na - b0);
-    const int bl0 = (int)(blockIdx.x % nbg) * NB;
+    const int bl0 = (int)(lid % nbg) * NB;
     if (bl0 >= nloc) return;
     const int nbv = min(NB, nloc - bl0);
-    const int f0 = (int)blockIdx.y * NF;
+    const int f0 = (int)(lid / nbg) * NF;
     const int tid = threadIdx.x;
     const bool active = tid < NF * TPF;
     const int tw_ = active ? tid : NF * TPF - 1;
@@ -1667,53 +1679,36 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             o_fo[k] = o_ok[k] ? (uint32_t)(b * A.nch * ng + p / kTile) : 0u;
         }
     }
-    for (int ch = 0; ch < A.nch; ++ch) {
-        const auto rr = buf_rsrc(rhat + ((int64_t)ch * A.ft + f0) * rstride, rbytes);
-        // conjugate multiply-accumulate over the pieces and the L-point inverse over k1
-        if (active) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                float2 t[L];
-#pragma unroll
-                for (int m = 0; m < L; ++m) t[m] = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if (c < A.nc) {
-#pragma unroll
-                        for (int mp = 0; mp < L / 2; ++mp) {
-                            const float4 v = buf_f4(rr, rvoff, (uint32_t)((c * L + 2 * mp) * TPF * 8));
-                            t[2 * mp] = cfma(dacc[b][c][2 * mp], make_float2(v.x, -v.y), t[2 * mp]);
-                            t[2 * mp + 1] = cfma(dacc[b][c][2 * mp + 1], make_float2(v.z, -v.w), t[2 * mp + 1]);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int m = 0; m < L; ++m) t[m] = cconj(t[m]);
-                Dft<L>::run(t);
-                const int bf = b * NF + fl;
-                if constexpr (RS == 1) {
-                    float2* yr = yb + (bf * FS + kx) * YB;
-#pragma unroll
-                    for (int n = 0; n < L; ++n)
-                        if (n < By) yr[n] = cconj(t[n]);
-                } else {
-                    float2* gr = gbuf + ((bf * FS + kx) * L) * RS + k2;
-#pragma unroll
-                    for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
-                }
-            }
-        }
-        __syncthreads();
-        if constexpr (RS > 1) {
+    if constexpr (RS > 1 && L <= 8) {
+        // Channel pipeline, two barriers per channel. Stages of channel ch:
+        //   M  conjugate multiply-add over the pieces, L-point inverse over k1 -> gq
+        //   Y  RS-point inverse over k2, rows py < By -> yq
+        //   X  L-point inverse over kx = k_of(k1, kk) for every py < By -> g2q
+        //   R  RS-point inverse, columns px < Bx -> obq
+        //   S  stores of obq into dT
+        // Interval A of step k runs M(k), X(k - 1) and S(k - 2); interval B runs Y(k) and
+        // R(k - 1). Every stage has a buffer of its own, written in one interval and read
+        // in the next, so one barrier closes each interval. The response spectra of the
+        // first PRE pieces of M(k) are requested at the start of interval A, ahead of the
+        // X and S work, and piece c + PRE after the multiply-adds of piece c (a ring of
+        // PRE register buffers; the last piece is requested again where c + PRE >= nc).
+        float2* gq = reg;                  // [NB][NF][FS kx][L n1][RS k2]
+        float2* yq = gq + Ls.gb;           // [NB][NF][FS kx][YB py]
+        float2* g2q = yq + Ls.yb;          // [NB][NF][NIN py][L n1][RS kk]
+        float2* obq = g2q + Ls.g2;         // [NB][NF][Bx px][By py]
+        constexpr int PRE = TRED_SPP_ADJ_PRE;   // pieces requested ahead (registers)
+        static_assert(PRE >= 1 && PRE <= 4, "pieces requested ahead");
+        const int clast = A.nc - 1;
+        auto stage_y = [&]() {
             for (int i = tid; i < NB * NF * FS * L; i += NT) {
                 const int n1 = i % L;
                 const int r = i / L;   // bf * FS + kx
-                const float2* gr = gbuf + (r * L + n1) * RS;
+                const float2* gr = gq + (r * L + n1) * RS;
                 float2 t[RS];
 #pragma unroll
                 for (int k = 0; k < RS; ++k) t[k] = gr[k];
                 Dft<RS>::run(t);
-                float2* yr = yb + r * YB;
+                float2* yr = yq + r * YB;
                 int py = (RS * n1) % FS;   // n_of(n1, n2), stepping n2 by L (mod FS)
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
@@ -1722,48 +1717,43 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                     py = py >= FS ? py - FS : py;
                 }
             }
-            __syncthreads();
-        }
-        // x inverse: L-point stage over kx = k_of(k1, kk) for every py. Items run over
-        // py < NIN (a compile-time bound) so that their decomposition is shifts and
-        // multiplies by constants; rows py >= By are skipped.
+        };
+        auto stage_x = [&]() {
 #pragma unroll
-        for (int it = 0; it < (NB * NF * NIN * RS + NT - 1) / NT; ++it) {
-            const int i = tid + it * NT;
-            const int kk = i % RS;
-            const int r = i / RS;     // bf * NIN + py
-            const int py = r % NIN, bf = r / NIN;
-            if (i >= NB * NF * NIN * RS || py >= By) continue;
-            const float2* yr = yb + bf * FS * YB + py;
-            float2 t[L];
-            const int kb = (Pfa<L, RS>::k_of(0, 1) * kk) % FS;   // k_of(0, kk)
+            for (int it = 0; it < (NB * NF * NIN * RS + NT - 1) / NT; ++it) {
+                const int i = tid + it * NT;
+                const int kk = i % RS;
+                const int r = i / RS;     // bf * NIN + py
+                const int py = r % NIN, bf = r / NIN;
+                if (i >= NB * NF * NIN * RS || py >= By) continue;
+                const float2* yr = yq + bf * FS * YB + py;
+                float2 t[L];
+                const int kb = (Pfa<L, RS>::k_of(0, 1) * kk) % FS;   // k_of(0, kk)
 #pragma unroll
-            for (int m = 0; m < L; ++m) {
-                int kxm = kb + P::k_of(m, 0);
-                kxm = kxm >= FS ? kxm - FS : kxm;
-                t[m] = cconj(yr[kxm * YB]);
-            }
-            Dft<L>::run(t);
-            if constexpr (RS == 1) {
-#pragma unroll
-                for (int n = 0; n < L; ++n)
-                    if (n < Bx) ob[(bf * Bx + n) * By + py] = cconj(t[n]);
-            } else {
-                float2* gr = g2 + ((bf * NIN + py) * L) * RS + kk;   // [bf][py][n1][kk]
+                for (int m = 0; m < L; ++m) {
+                    int kxm = kb + P::k_of(m, 0);
+                    kxm = kxm >= FS ? kxm - FS : kxm;
+                    t[m] = cconj(yr[kxm * YB]);
+                }
+                Dft<L>::run(t);
+                float2* gr = g2q + ((bf * NIN + py) * L) * RS + kk;
 #pragma unroll
                 for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
             }
-        }
-        __syncthreads();
-        if constexpr (RS > 1) {
+        };
+        // stage R runs in the interval of stage Y, whose items past the first NT fall
+        // to the first threads: R's items start after those threads
+        constexpr int YX = (NB * NF * FS * L) % NT;
+        const int rrot = tid >= YX ? tid - YX : tid + NT - YX;
+        auto stage_r = [&]() {
 #pragma unroll
             for (int it = 0; it < (NB * NF * NIN * L + NT - 1) / NT; ++it) {
-                const int i = tid + it * NT;
+                const int i = rrot + it * NT;
                 const int n1 = i % L;
                 const int r = i / L;  // bf * NIN + py
                 const int py = r % NIN, bf = r / NIN;
                 if (i >= NB * NF * NIN * L || py >= By) continue;
-                const float2* gr = g2 + (r * L + n1) * RS;
+                const float2* gr = g2q + (r * L + n1) * RS;
                 float2 t[RS];
 #pragma unroll
                 for (int k = 0; k < RS; ++k) t[k] = gr[k];
@@ -1771,25 +1761,200 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 int px = (RS * n1) % FS;   // n_of(n1, n2)
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
-                    if (px < Bx) ob[(bf * Bx + px) * By + py] = cconj(t[n2]);
+                    if (px < Bx) obq[(bf * Bx + px) * By + py] = cconj(t[n2]);
                     px += L;
                     px = px >= FS ? px - FS : px;
                 }
             }
-            __syncthreads();
-        }
-        // dT[b][ch][p / kTileT][f][p % kTileT] for the bin's pixels p = px * By + py, with
-        // the per-thread offsets computed before the channel loop
-        {
+        };
+        auto stage_s = [&](int ch) {
             const auto tr = buf_rsrc(dT + ((int64_t)bl0 * A.nch + ch) * tstride,
                                      (uint32_t)(((int64_t)nbv * A.nch - ch) * tstride * 8));
 #pragma unroll
             for (int k = 0; k < IT5; ++k) {
                 const bool need = !A.rows || gflag[o_fo[k] + ch * ng] != 0;
-                if (o_ok[k]) buf_st_f2(ob[o_src[k]], tr, need ? o_off[k] : 0xfffffff0u, 0u);
+                if (o_ok[k]) buf_st_f2(obq[o_src[k]], tr, need ? o_off[k] : 0xfffffff0u, 0u);
             }
+        };
+        for (int k = 0; k < A.nch + 2; ++k) {
+            const bool doM = k < A.nch;
+            const auto rr = buf_rsrc(rhat + ((int64_t)min(k, A.nch - 1) * A.ft + f0) * rstride, rbytes);
+            auto load_w = [&](float2* wv, int c) {
+#pragma unroll
+                for (int mp = 0; mp < L / 2; ++mp) {
+                    const float4 v = buf_f4(rr, rvoff, (uint32_t)((c * L + 2 * mp) * TPF * 8));
+                    wv[2 * mp] = make_float2(v.x, -v.y);
+                    wv[2 * mp + 1] = make_float2(v.z, -v.w);
+                }
+            };
+            float2 w[PRE][L];
+            if (doM) {
+#pragma unroll
+                for (int c = 0; c < PRE; ++c) load_w(w[c], min(c, clast));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (k >= 2) stage_s(k - 2);
+            if (k >= 1 && k <= A.nch) stage_x();
+            __builtin_amdgcn_sched_barrier(0);
+            if (doM) {
+                float2 t[NB][L];
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int m = 0; m < L; ++m) t[b][m] = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (c < A.nc && active) {
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+#pragma unroll
+                            for (int m = 0; m < L; ++m)
+                                t[b][m] = cfma(dacc[b][c][m], w[c % PRE][m], t[b][m]);
+                    }
+                    if (c + PRE < 4) load_w(w[c % PRE], min(c + PRE, clast));
+                }
+                if (active) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                        for (int m = 0; m < L; ++m) t[b][m] = cconj(t[b][m]);
+                        Dft<L>::run(t[b]);
+                        float2* gr = gq + (((b * NF + fl) * FS + kx) * L) * RS + k2;
+#pragma unroll
+                        for (int n = 0; n < L; ++n) gr[n * RS] = t[b][n];
+                    }
+                }
+            }
+            __syncthreads();
+            if (k < A.nch) stage_y();
+            if (k >= 1 && k <= A.nch) stage_r();
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        for (int ch = 0; ch < A.nch; ++ch) {
+            const auto rr = buf_rsrc(rhat + ((int64_t)ch * A.ft + f0) * rstride, rbytes);
+            // conjugate multiply-accumulate over the pieces and the L-point inverse over k1
+            if (active) {
+    #pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    float2 t[L];
+    #pragma unroll
+                    for (int m = 0; m < L; ++m) t[m] = make_float2(0.f, 0.f);
+    #pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (c < A.nc) {
+    #pragma unroll
+                            for (int mp = 0; mp < L / 2; ++mp) {
+                                const float4 v = buf_f4(rr, rvoff, (uint32_t)((c * L + 2 * mp) * TPF * 8));
+                                t[2 * mp] = cfma(dacc[b][c][2 * mp], make_float2(v.x, -v.y), t[2 * mp]);
+                                t[2 * mp + 1] = cfma(dacc[b][c][2 * mp + 1], make_float2(v.z, -v.w), t[2 * mp + 1]);
+                            }
+                        }
+                    }
+    #pragma unroll
+                    for (int m = 0; m < L; ++m) t[m] = cconj(t[m]);
+                    Dft<L>::run(t);
+                    const int bf = b * NF + fl;
+                    if constexpr (RS == 1) {
+                        float2* yr = yb + (bf * FS + kx) * YB;
+    #pragma unroll
+                        for (int n = 0; n < L; ++n)
+                            if (n < By) yr[n] = cconj(t[n]);
+                    } else {
+                        float2* gr = gbuf + ((bf * FS + kx) * L) * RS + k2;
+    #pragma unroll
+                        for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
+                    }
+                }
+            }
+            __syncthreads();
+            if constexpr (RS > 1) {
+                for (int i = tid; i < NB * NF * FS * L; i += NT) {
+                    const int n1 = i % L;
+                    const int r = i / L;   // bf * FS + kx
+                    const float2* gr = gbuf + (r * L + n1) * RS;
+                    float2 t[RS];
+    #pragma unroll
+                    for (int k = 0; k < RS; ++k) t[k] = gr[k];
+                    Dft<RS>::run(t);
+                    float2* yr = yb + r * YB;
+                    int py = (RS * n1) % FS;   // n_of(n1, n2), stepping n2 by L (mod FS)
+    #pragma unroll
+                    for (int n2 = 0; n2 < RS; ++n2) {
+                        if (py < By) yr[py] = cconj(t[n2]);
+                        py += L;
+                        py = py >= FS ? py - FS : py;
+                    }
+                }
+                __syncthreads();
+            }
+            // x inverse: L-point stage over kx = k_of(k1, kk) for every py. Items run over
+            // py < NIN (a compile-time bound) so that their decomposition is shifts and
+            // multiplies by constants; rows py >= By are skipped.
+    #pragma unroll
+            for (int it = 0; it < (NB * NF * NIN * RS + NT - 1) / NT; ++it) {
+                const int i = tid + it * NT;
+                const int kk = i % RS;
+                const int r = i / RS;     // bf * NIN + py
+                const int py = r % NIN, bf = r / NIN;
+                if (i >= NB * NF * NIN * RS || py >= By) continue;
+                const float2* yr = yb + bf * FS * YB + py;
+                float2 t[L];
+                const int kb = (Pfa<L, RS>::k_of(0, 1) * kk) % FS;   // k_of(0, kk)
+    #pragma unroll
+                for (int m = 0; m < L; ++m) {
+                    int kxm = kb + P::k_of(m, 0);
+                    kxm = kxm >= FS ? kxm - FS : kxm;
+                    t[m] = cconj(yr[kxm * YB]);
+                }
+                Dft<L>::run(t);
+                if constexpr (RS == 1) {
+    #pragma unroll
+                    for (int n = 0; n < L; ++n)
+                        if (n < Bx) ob[(bf * Bx + n) * By + py] = cconj(t[n]);
+                } else {
+                    float2* gr = g2 + ((bf * NIN + py) * L) * RS + kk;   // [bf][py][n1][kk]
+    #pragma unroll
+                    for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
+                }
+            }
+            __syncthreads();
+            if constexpr (RS > 1) {
+    #pragma unroll
+                for (int it = 0; it < (NB * NF * NIN * L + NT - 1) / NT; ++it) {
+                    const int i = tid + it * NT;
+                    const int n1 = i % L;
+                    const int r = i / L;  // bf * NIN + py
+                    const int py = r % NIN, bf = r / NIN;
+                    if (i >= NB * NF * NIN * L || py >= By) continue;
+                    const float2* gr = g2 + (r * L + n1) * RS;
+                    float2 t[RS];
+    #pragma unroll
+                    for (int k = 0; k < RS; ++k) t[k] = gr[k];
+                    Dft<RS>::run(t);
+                    int px = (RS * n1) % FS;   // n_of(n1, n2)
+    #pragma unroll
+                    for (int n2 = 0; n2 < RS; ++n2) {
+                        if (px < Bx) ob[(bf * Bx + px) * By + py] = cconj(t[n2]);
+                        px += L;
+                        px = px >= FS ? px - FS : px;
+                    }
+                }
+                __syncthreads();
+            }
+            // dT[b][ch][p / kTileT][f][p % kTileT] for the bin's pixels p = px * By + py, with
+            // the per-thread offsets computed before the channel loop
+            {
+                const auto tr = buf_rsrc(dT + ((int64_t)bl0 * A.nch + ch) * tstride,
+                                         (uint32_t)(((int64_t)nbv * A.nch - ch) * tstride * 8));
+    #pragma unroll
+                for (int k = 0; k < IT5; ++k) {
+                    const bool need = !A.rows || gflag[o_fo[k] + ch * ng] != 0;
+                    if (o_ok[k]) buf_st_f2(ob[o_src[k]], tr, need ? o_off[k] : 0xfffffff0u, 0u);
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
