@@ -1502,7 +1502,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
 // outputs pruned to the bin's Bx x By pixels -> dT[ch] (layout of T).
 template <int FS, int L, int NIN, int NB>
 struct SppAdjLds {
-    int tw, YO, P2, YB, du, a2, gb, yb, g2, ob, A, B, total;
+    int tw, P2, YB, du, a2, gb, yb, g2, ob, A, B, total;
 };
 
 template <int FS, int L, int NIN, int NB, int NF>
@@ -1510,10 +1510,9 @@ __host__ __device__ inline SppAdjLds<FS, L, NIN, NB> spp_adj_lds(int box, int bo
     constexpr int RS = FS / L;
     SppAdjLds<FS, L, NIN, NB> s;
     s.tw = even_up(FS);
-    s.YO = (boy % 2 == 0) ? boy + 1 : boy;     // odd row stride of the output-gradient tile
     s.P2 = even_up(FS) + 2;                    // even: 16-byte rows for the column reads
     s.YB = (By % 2 == 0) ? By + 1 : By;
-    s.du = NB * NF * box * s.YO;
+    s.du = NB * NF * boy * s.P2;                // output-gradient rows qy of P2 (qx fastest)
     s.a2 = NB * NF * FS * s.P2;
     s.gb = RS > 1 ? NB * NF * FS * L * RS : 0;
     s.yb = NB * NF * FS * s.YB;
@@ -1556,16 +1555,19 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     const int kx = item / RS, k2 = item % RS;
     const int Bx = A.Bx, By = A.By, box = A.box, boy = A.boy;
     const auto Ls = spp_adj_lds<FS, L, NIN, NB, NF>(box, boy, Bx, By);
-    const int YO = Ls.YO, P2 = Ls.P2, YB = Ls.YB;
+    const int P2 = Ls.P2, YB = Ls.YB;
     float2* twl = sm;
     float2* reg = sm + Ls.tw;
-    float2* du = reg;                  // [NB][NF][box qx][YO qy]
+    float2* du = reg;                  // [NB][NF][boy qy][P2 qx], zero past qx = box
     float2* a2 = reg + Ls.du;          // [NB][NF][FS kx][P2 qy]
     float2* gbuf = reg;                // [NB][NF][FS kx][L n1][RS k2]
     float2* g2 = reg;                  // [NB][NF][By py][L n1][RS kk]
     float2* ob = reg + Ls.g2;          // [NB][NF][Bx px][By py]
     float2* yb = reg + (Ls.gb > Ls.g2 + Ls.ob ? Ls.gb : Ls.g2 + Ls.ob);   // [NB][NF][FS kx][YB py]
     for (int i = tid; i < FS; i += NT) twl[i] = tws[i];
+    // the staging rows are read whole (FS entries, unconditionally): the entries past the
+    // output footprint (qx >= box, qy >= boy) are zero, written once here and never after
+    for (int i = tid; i < Ls.A; i += NT) reg[i] = make_float2(0.f, 0.f);
     __syncthreads();
     float2 wy[RS];
 #pragma unroll
@@ -1586,7 +1588,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 if (b < nbv)
                     u = dU[((((int64_t)(bl0 + b) * A.nc + c) * qtiles + q / kTile) * A.ft + f0 + fl2) *
                                kTile + q % kTile];
-                du[(r * box + q / boy) * YO + q % boy] = u;
+                du[(r * boy + q % boy) * P2 + q / boy] = u;
             }
             __syncthreads();
             if (A.mpcp) {
@@ -1595,23 +1597,27 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 for (int i = tid; i < NB * NF * npair; i += NT) {
                     const int q = i % npair, r = i / npair;
                     const int qm = nq - 1 - q;
-                    float2* yy = du + r * box * YO;
-                    const int ia = (q / boy) * YO + q % boy, ib = (qm / boy) * YO + qm % boy;
+                    float2* yy = du + r * boy * P2;
+                    const int ia = (q % boy) * P2 + q / boy, ib = (qm % boy) * P2 + qm / boy;
                     const float2 u = yy[ia], w = yy[ib];
                     yy[ia] = make_float2(u.x - w.y, u.y + w.x);
                     if (ib != ia) yy[ib] = make_float2(w.x - u.y, w.y + u.x);
                 }
                 __syncthreads();
             }
-            // x stage: for each (b, qy, kk) an L-point DFT over the gathered qx < box
+            // x stage: for each (b, qy, kk) an L-point DFT over the gathered qx (zero past box)
             for (int i = tid; i < NB * NF * boy * RS; i += NT) {
                 const int kk = i % RS;
-                const int r = i / RS;
+                const int r = i / RS;   // bf * boy + qy
                 const int qy = r % boy, bf = r / boy;
+                const float4* dr4 = (const float4*)(du + r * P2);
                 float2 x[FS];
 #pragma unroll
-                for (int qx = 0; qx < FS; ++qx)
-                    x[qx] = qx < box ? du[(bf * box + qx) * YO + qy] : make_float2(0.f, 0.f);
+                for (int q = 0; q < FS / 2; ++q) {
+                    const float4 v = dr4[q];
+                    x[2 * q] = make_float2(v.x, v.y);
+                    x[2 * q + 1] = make_float2(v.z, v.w);
+                }
                 float2 w[RS];
 #pragma unroll
                 for (int j = 0; j < RS; ++j) w[j] = twl[((j * kk) % RS) * L];
@@ -1623,13 +1629,17 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 for (int m = 0; m < L; ++m) ar[P::k_of(m, kk) * P2] = t[m];
             }
             __syncthreads();
-            // y stage: thread (kx, k2) over the gathered qy < boy
+            // y stage: thread (kx, k2) over the gathered qy (zero past boy)
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const float2* ar = a2 + ((b * NF + fl) * FS + kx) * P2;
+                const float4* ar4 = (const float4*)(a2 + ((b * NF + fl) * FS + kx) * P2);
                 float2 x[FS];
 #pragma unroll
-                for (int qy = 0; qy < FS; ++qy) x[qy] = qy < boy ? ar[qy] : make_float2(0.f, 0.f);
+                for (int q = 0; q < FS / 2; ++q) {
+                    const float4 v = ar4[q];
+                    x[2 * q] = make_float2(v.x, v.y);
+                    x[2 * q + 1] = make_float2(v.z, v.w);
+                }
                 pfa_gather<L, RS, FS>(x, wy, dacc[b][c]);
                 Dft<L>::run(dacc[b][c]);
             }
