@@ -1534,6 +1534,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     using S = SppShape<FS, L, NIN, NB>;
     using P = Pfa<L, S::RS>;
     constexpr int RS = S::RS, TPF = S::TPF, NF = S::NF, NT = S::NT;
+    constexpr bool kPipe = RS > 1 && L <= 8;   // pipelined channel loop
     extern __shared__ float4 sm4[];
     float2* sm = (float2*)sm4;
     // bins fastest in the logical order; each XCD walks a contiguous range of
@@ -1642,6 +1643,10 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 }
                 pfa_gather<L, RS, FS>(x, wy, dacc[b][c]);
                 Dft<L>::run(dacc[b][c]);
+                if constexpr (kPipe) {   // held conjugated by the pipelined channel loop
+#pragma unroll
+                    for (int m = 0; m < L; ++m) dacc[b][c][m] = cconj(dacc[b][c][m]);
+                }
             }
             __syncthreads();
         } else {
@@ -1689,7 +1694,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             o_fo[k] = o_ok[k] ? (uint32_t)(b * A.nch * ng + p / kTile) : 0u;
         }
     }
-    if constexpr (RS > 1 && L <= 8) {
+    if constexpr (kPipe) {
         // Channel pipeline, two barriers per channel. Stages of channel ch:
         //   M  conjugate multiply-add over the pieces, L-point inverse over k1 -> gq
         //   Y  RS-point inverse over k2, rows py < By -> yq
@@ -1702,6 +1707,11 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         // first PRE pieces of M(k) are requested at the start of interval A, ahead of the
         // X and S work, and piece c + PRE after the multiply-adds of piece c (a ring of
         // PRE register buffers; the last piece is requested again where c + PRE >= nc).
+        // The inverse transforms are forward DFTs of conjugates, and the values between
+        // stages are kept conjugated so that no stage flips signs: the accumulators hold
+        // conj(dacc), so M sums conj(dacc) Rhat = conj(sum dacc conj(Rhat)) and its DFT is
+        // the conjugated k1 inverse; Y's DFT is the conjugate of the k2 inverse, which X
+        // transforms as read; R conjugates its outputs once.
         float2* gq = reg;                  // [NB][NF][FS kx][L n1][RS k2]
         float2* yq = gq + Ls.gb;           // [NB][NF][FS kx][YB py]
         float2* g2q = yq + Ls.yb;          // [NB][NF][NIN py][L n1][RS kk]
@@ -1718,11 +1728,11 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
 #pragma unroll
                 for (int k = 0; k < RS; ++k) t[k] = gr[k];
                 Dft<RS>::run(t);
-                float2* yr = yq + r * YB;
+                float2* yr = yq + r * YB;   // conjugated (stage X reads it so)
                 int py = (RS * n1) % FS;   // n_of(n1, n2), stepping n2 by L (mod FS)
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
-                    if (py < By) yr[py] = cconj(t[n2]);
+                    if (py < By) yr[py] = t[n2];
                     py += L;
                     py = py >= FS ? py - FS : py;
                 }
@@ -1743,7 +1753,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 for (int m = 0; m < L; ++m) {
                     int kxm = kb + P::k_of(m, 0);
                     kxm = kxm >= FS ? kxm - FS : kxm;
-                    t[m] = cconj(yr[kxm * YB]);
+                    t[m] = yr[kxm * YB];
                 }
                 Dft<L>::run(t);
                 float2* gr = g2q + ((bf * NIN + py) * L) * RS + kk;
@@ -1793,8 +1803,8 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
 #pragma unroll
                 for (int mp = 0; mp < L / 2; ++mp) {
                     const float4 v = buf_f4(rr, rvoff, (uint32_t)((c * L + 2 * mp) * TPF * 8));
-                    wv[2 * mp] = make_float2(v.x, -v.y);
-                    wv[2 * mp + 1] = make_float2(v.z, -v.w);
+                    wv[2 * mp] = make_float2(v.x, v.y);
+                    wv[2 * mp + 1] = make_float2(v.z, v.w);
                 }
             };
             float2 w[PRE][L];
@@ -1807,27 +1817,28 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             if (k >= 1 && k <= A.nch) stage_x();
             __builtin_amdgcn_sched_barrier(0);
             if (doM) {
-                float2 t[NB][L];
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-#pragma unroll
-                    for (int m = 0; m < L; ++m) t[b][m] = make_float2(0.f, 0.f);
+                float2 t[NB][L];   // set by piece 0 (nc >= 1); read by active threads only
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     if (c < A.nc && active) {
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
 #pragma unroll
-                            for (int m = 0; m < L; ++m)
-                                t[b][m] = cfma(dacc[b][c][m], w[c % PRE][m], t[b][m]);
+                            for (int m = 0; m < L; ++m) {
+                                const float2 d = dacc[b][c][m], r = w[c % PRE][m];
+                                if (c == 0) {   // the sum from zero, as cfma's steps
+                                    t[b][m].x = fmaf(-d.y, r.y, d.x * r.x);
+                                    t[b][m].y = fmaf(d.y, r.x, d.x * r.y);
+                                } else {
+                                    t[b][m] = cfma(d, r, t[b][m]);
+                                }
+                            }
                     }
                     if (c + PRE < 4) load_w(w[c % PRE], min(c + PRE, clast));
                 }
                 if (active) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-#pragma unroll
-                        for (int m = 0; m < L; ++m) t[b][m] = cconj(t[b][m]);
                         Dft<L>::run(t[b]);
                         float2* gr = gq + (((b * NF + fl) * FS + kx) * L) * RS + k2;
 #pragma unroll
