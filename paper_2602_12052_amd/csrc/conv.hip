@@ -1431,66 +1431,120 @@ __global__ __launch_bounds__(256) void k_group_need(ConvArgs A, int b0, int nb,
     }
 }
 
-// k_tf_adj: per (half T tile, channel, bin); wave wv handles pixel p of the half tile.
+// k_tf_adj: the transpose of the time FFT per group (bin, channel, half T tile): F^H of
+// the group's 8 rows of T-layout gradients (wave wv: pixel wv of the half tile),
+// cropped to Bt ticks and unpacked from the mirror pair into the rows of d blocks.
+// Workgroups are persistent (groups q = w, w + G, ..., with tf_group's order, so the
+// two halves of a tile go to one XCD) and request a group's half tile one iteration
+// before its transform and its need flag (row masks) two iterations before, so the
+// reads of the spectra overlap the transforms. Every iteration issues the same vector
+// memory operations in the same order (as in k_tf_list): a group that is not needed
+// (no marked row or mirror row), a row that is not marked and the ticks past Bt
+// address an empty buffer resource or an offset past its end, which reads zero and
+// drops stores, so each wait is for the operation it needs.
 template <int FT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 ? 4 : 1))) void k_tf_adj(
-    ConvArgs A, int b0, const int32_t* __restrict__ n_active, const float2* __restrict__ dT,
+    ConvArgs A, int b0, int nb, const int32_t* __restrict__ n_active, const float2* __restrict__ dT,
     const float2* __restrict__ tw, float* __restrict__ dblocks) {
     extern __shared__ float lds[];
     constexpr int M = FT / kWave;
-    const int bl = blockIdx.z, b = b0 + bl;
-    if (b >= min(*n_active, A.cap)) return;
-    const int ch = blockIdx.y;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int pt = blockIdx.x / (kTileT / kTile), half = blockIdx.x % (kTileT / kTile);
-    // with row masks, groups without a marked row are not needed
-    if (A.rows && A.tflag[((int64_t)bl * A.nch + ch) * (A.ppad / kTile) + blockIdx.x] == 0) return;
+    constexpr int SPT = FT * kTile / 512;   // staged half-tile values per thread
+    constexpr uint32_t kOob = 0xfffffff0u;
+    const int nact = min(min(*n_active, A.cap) - b0, nb);
+    if (nact <= 0) return;
+    const int nbx = A.ppad / kTile;
+    const int total = nact * A.nch * nbx;   // groups (the host keeps nb * nch * nbx < 2^31)
+    const int G = (int)gridDim.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int ntile = A.ppad / kTileT;
+    const int mb = A.Bt / kWave;
     float2* twl = (float2*)(lds + tf_lds_floats<FT>());
     fft_tw_fill<FT>(twl, tw, threadIdx.x, blockDim.x);
-    // stage the half tile [f][kTile] of T-layout gradients
-    const float2* s2 = dT + (((int64_t)bl * A.nch + ch) * (A.ppad / kTileT) + pt) * FT * kTileT +
-                       half * kTile;
-    float2* stage = (float2*)lds;
-    for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x) {
-        const int f = i / kTile, cc = i % kTile;
-        stage[f * kTile + tf_col(f, cc)] = s2[(int64_t)f * kTileT + cc];
-    }
-    __syncthreads();
-    float2 v[M];
+    const auto fr = buf_rsrc(A.tflag, A.rows ? (uint32_t)total : 0u);
+    // need flag of group q (requested now, read an iteration later); 1 without row masks
+    auto load_flag = [&](int q) -> uint32_t {
+        const int qc = min(q, total - 1);
+        const TfGroup g = tf_group(A, qc);
+        const uint32_t idx = (uint32_t)(qc - qc % nbx + g.pt * (kTileT / kTile) + g.half);
+        const uint32_t f = buf_u8(fr, idx, 0u);
+        return A.rows ? f : 1u;
+    };
+    // half tile of group q: thread t holds columns t % kTile of rows f = t / kTile +
+    // (512 / kTile) k, read from the tile's [f][kTileT] layout
+    float2 pre[SPT];
+    auto load = [&](int q, bool need) {
+        const int qc = min(q, total - 1);
+        const TfGroup g = tf_group(A, qc);
+        const float2* s2 = dT + (((int64_t)g.bl * A.nch + g.ch) * ntile + g.pt) * FT * kTileT +
+                           g.half * kTile;
+        const auto r = buf_rsrc(s2, need && q < total ? (uint32_t)((FT * kTileT - g.half * kTile) * 8) : 0u);
+        const int f0 = (int)threadIdx.x / kTile, cc = (int)threadIdx.x % kTile;
+        const uint32_t voff = (uint32_t)((f0 * kTileT + cc) * 8);
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int f = lane + kWave * m;
-        v[m] = cconj(stage[f * kTile + tf_col(f, wv)]);
-    }
+        for (int k = 0; k < SPT; ++k)
+            pre[k] = buf_f2(r, voff, (uint32_t)(k * (512 / kTile) * kTileT * 8));
+    };
     __syncthreads();
-    wave_fft<FT, true, true>(v, lds + wv * kFftLds<FT>, twl, lane);   // F^H = conj F conj
-    const int p = pt * kTileT + half * kTile + wv;
-    if (p >= A.Bx * A.By) return;
-    const int jx = ch / A.sy, jy = ch % A.sy;
-    const int jb = A.S - 1 - ch;
-    const bool pair = A.mpcp && jb != ch;
-    const int px = p / A.By, py = p % A.By;
-    float* blk = dblocks + (int64_t)b * A.vblk;
-    float* r0 = blk + ((int64_t)(px * A.sx + jx) * A.NYf + (py * A.sy + jy)) * A.Bt;
-    const int jbx = jb / A.sy, jby = jb % A.sy;
-    const int q1 = ((A.Bx - 1 - px) * A.sx + jbx) * A.NYf + ((A.By - 1 - py) * A.sy + jby);
-    float* r1 = blk + (int64_t)q1 * A.Bt;
-    // with row masks only the marked rows are written
-    bool w0 = true, w1 = pair;
-    if (A.rows) {
-        const uint32_t* rw = A.rows + (int64_t)b * A.nrw;
-        const int q0 = (px * A.sx + jx) * A.NYf + (py * A.sy + jy);
-        w0 = (rw[q0 >> 5] >> (q0 & 31)) & 1u;
-        w1 = w1 && ((rw[q1 >> 5] >> (q1 & 31)) & 1u);
-    }
-    const int mb = A.Bt / kWave;
+    int q = (int)blockIdx.x;
+    uint32_t need = __builtin_amdgcn_readfirstlane(load_flag(q));
+    load(q, need != 0u);
+    uint32_t fnext = load_flag(q + G);
+    for (; q < total; q += G) {
+        const TfGroup g = tf_group(A, q);
+        // stage the half tile [f][kTile] (columns swizzled) and take this wave's column
+        float2* stage = (float2*)lds;
+        {
+            const int f0 = (int)threadIdx.x / kTile, cc = (int)threadIdx.x % kTile;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        if (m < mb) {
-            const float2 z = cconj(v[m]);
-            if (w0) r0[lane + kWave * m] = z.x;
-            if (w1) r1[lane + kWave * m] = z.y;
+            for (int k = 0; k < SPT; ++k) {
+                const int f = f0 + (512 / kTile) * k;
+                stage[f * kTile + tf_col(f, cc)] = pre[k];
+            }
         }
+        __syncthreads();
+        float2 v[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int f = lane + kWave * m;
+            v[m] = cconj(stage[f * kTile + tf_col(f, wv)]);
+        }
+        __syncthreads();   // the staging tile overlaps the FFT scratch
+        const bool cur = need != 0u;
+        // the next group's half tile and the flag after it, in flight during the transform
+        need = __builtin_amdgcn_readfirstlane(fnext);
+        load(q + G, need != 0u);
+        fnext = load_flag(q + 2 * G);
+        if (cur) wave_fft<FT, true, true>(v, lds + wv * kFftLds<FT>, twl, lane);   // F^H = conj F conj
+        // rows of pixel p: Q_j (real part) and, under mirror-pair packing, Q_j' of the
+        // mirrored pixel (imaginary part); with row masks only marked rows are written
+        const int p = g.pt * kTileT + g.half * kTile + wv;
+        const bool pv = cur && p < A.Bx * A.By;
+        const int pc = min(p, A.Bx * A.By - 1);
+        const int jx = g.ch / A.sy, jy = g.ch % A.sy;
+        const int jb = A.S - 1 - g.ch;
+        const bool pair = A.mpcp && jb != g.ch;
+        const int px = pc / A.By, py = pc % A.By;
+        const int jbx = jb / A.sy, jby = jb % A.sy;
+        const int q0 = (px * A.sx + jx) * A.NYf + (py * A.sy + jy);
+        const int q1 = ((A.Bx - 1 - px) * A.sx + jbx) * A.NYf + ((A.By - 1 - py) * A.sy + jby);
+        bool w0 = pv, w1 = pv && pair;
+        if (A.rows) {
+            const uint32_t* rw = A.rows + (int64_t)(b0 + g.bl) * A.nrw;
+            w0 = w0 && ((rw[q0 >> 5] >> (q0 & 31)) & 1u);
+            w1 = w1 && ((rw[q1 >> 5] >> (q1 & 31)) & 1u);
+        }
+        float* blk = dblocks + (int64_t)(b0 + g.bl) * A.vblk;
+        const uint32_t vb = (uint32_t)(A.vblk * 4);   // a bin is below 2^31 bytes
+        const auto r0 = buf_rsrc(blk, w0 ? vb : 0u), r1 = buf_rsrc(blk, w1 ? vb : 0u);
+        const uint32_t o0 = 4u * (uint32_t)(q0 * A.Bt + lane), o1 = 4u * (uint32_t)(q1 * A.Bt + lane);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float2 z = cconj(v[m]);
+            const uint32_t so = (uint32_t)(m * kWave * 4);
+            buf_st_f1(z.x, r0, m < mb ? o0 : kOob, m < mb ? so : 0u);
+            buf_st_f1(z.y, r1, m < mb ? o1 : kOob, m < mb ? so : 0u);
+        }
+        __syncthreads();   // the next staging tile overlaps this transform's scratch
     }
 }
 
@@ -2229,9 +2283,16 @@ tred_status launch_time_adj(const ConvArgs& A, int b0, int nb, const int32_t* na
         hipLaunchKernelGGL((k_ti_adj<FT>), dim3(A.qpad / kTile, A.nc, nb), dim3(512), lds, st, A, b0,
                            na, dout, tw, dU);
     } else {
+        // persistent workgroups: a multiple of 2 kXcd (tile halves on one XCD)
+        const int64_t groups = (int64_t)(A.ppad / kTile) * A.nch * nb;
+        if (groups > INT32_MAX / 4)
+            return tred_fail(TRED_EUNSUPPORTED, "adjoint time stage: %lld row groups per pass",
+                             (long long)groups);
+        const int64_t G = std::min<int64_t>(TRED_TF_GRID, (groups + 2 * kXcd - 1) / (2 * kXcd) * (2 * kXcd));
+        if (G <= 0) return TRED_OK;
         allow_lds(k_tf_adj<FT>, lds);
-        hipLaunchKernelGGL((k_tf_adj<FT>), dim3(A.ppad / kTile, A.nch, nb), dim3(512), lds, st, A, b0,
-                           na, dT, tw, dblocks);
+        hipLaunchKernelGGL((k_tf_adj<FT>), dim3((unsigned)G), dim3(512), lds, st, A, b0, nb, na, dT, tw,
+                           dblocks);
     }
     return tred_check_launch("tred_block_conv_adjoint time");
 }

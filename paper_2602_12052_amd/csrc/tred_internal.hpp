@@ -268,6 +268,14 @@ __device__ __forceinline__ void buf_st_f2(float2 v, __amdgpu_buffer_rsrc_t r, ui
                                           TRED_NT_STORE ? 2 : 0);
 }
 
+__device__ __forceinline__ void buf_st_f1(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ uint32_t buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, voff, soff, 0);
+}
+
 __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
     c.x = fmaf(a.x, b.x, c.x);
     c.x = fmaf(-a.y, b.y, c.x);
