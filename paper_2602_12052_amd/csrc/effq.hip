@@ -663,6 +663,11 @@ void launch_effq_rule(const EffqParams& P, int64_t n_dep, const float* seg, cons
     }
 }
 
+// waves per SIMD the effective-charge gradient is compiled for (register bound)
+#ifndef TRED_EFFQ_ADJ_WAVES
+#define TRED_EFFQ_ADJ_WAVES 2
+#endif
+
 // ---------------------------------------------------------------------------
 // Gradient of the effective charge (Sec. V-C), in closed form. The node charge is
 // q = Qp g(r, D, sigma) with r the node's offset from the segment start (from the
@@ -687,7 +692,7 @@ void launch_effq_rule(const EffqParams& P, int64_t n_dep, const float* seg, cons
 // widths and Qp = Q exp(-t_mid / lifetime)) once per deposition.
 // ---------------------------------------------------------------------------
 template <int NGL>
-__global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TRED_EFFQ_ADJ_WAVES))) void k_effq_adj(EffqParams P, int64_t n_dep,
                                                   const float* __restrict__ seg,
                                                   const int32_t* __restrict__ fp,
                                                   const int64_t* __restrict__ off,
@@ -702,7 +707,26 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
     __shared__ float sdv[CAPA];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const tred_grid& g = P.g;
-    constexpr int ngl = NGL;
+    // Node j of a dual cell, for the ascending Gauss-Legendre nodes (the first NH
+    // negative, the last NH positive, a middle one zero): j < NH lies in cell c + 1 at
+    // xi_j, j >= NH in cell c. Offset from the centre of cell c in cell widths, and
+    // spread weights onto c and c + 1 times the quadrature weight w_j.
+    constexpr int NH = NGL / 2;
+    __shared__ float stq[3][8];   // offset, weight onto c, weight onto c + 1 (x and y axes)
+    float tqo[NGL], tq0[NGL], tq1[NGL];   // the same, in registers (t axis)
+#pragma unroll
+    for (int j = 0; j < NGL; ++j) {
+        const float x = P.xi[j], wq = P.w[j], ax = 0.5f * fabsf(x);
+        tqo[j] = j < NH ? 1.0f + 0.5f * x : 0.5f * x;
+        tq0[j] = wq * (j < NH ? ax : 1.0f - ax);
+        tq1[j] = wq * (j < NH ? 1.0f - ax : ax);
+        if (tid == j) {
+            stq[0][j] = tqo[j];
+            stq[1][j] = tq0[j];
+            stq[2][j] = tq1[j];
+        }
+    }
+    __syncthreads();
     for (int64_t d = blockIdx.x; d < n_dep; d += gridDim.x) {
         const int32_t* f = fp + 6 * d;
         const int F0[3] = {f[0], f[1], f[2]}, F1[3] = {f[3], f[4], f[5]};
@@ -750,15 +774,17 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
         const float ial = point ? 0.0f : 1.0f / alf;
         const float kq = sqrtf(0.5f * alf);
         const float kia = kq * ial, hik = point ? 0.0f : 0.5f / kq;
-        const float jac = (float)(h[0] * h[1] * h[2] / 8.0);
-        int C0[3], C1[3], nn[3];
+        const double jac = h[0] * h[1] * h[2] / 8.0;   // node volume, applied to the sums
+        // Dual cells: the nodes between grid points c and c + 1 of an axis (those of cell
+        // c with xi >= 0 and those of cell c + 1 with xi < 0) spread onto c and c + 1
+        // only, so a dual cell reads the patch gradient at 2 x 2 x 2 grid points and the
+        // transposed spread of its nodes is separable. Dual cells c = F0 - 1 .. F1 hold
+        // every node whose spread reaches the footprint.
+        int nd[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            C0[a] = max(W.lo[a], F0[a] - 1);
-            C1[a] = min(W.hi[a], F1[a] + 1);
-            nn[a] = empty ? 0 : max(0, C1[a] - C0[a] + 1) * ngl;
-        }
+        for (int a = 0; a < 3; ++a) nd[a] = empty ? 0 : F1[a] - F0[a] + 2;
         const int FY = F1[1] - F0[1] + 1, FTt = F1[2] - F0[2] + 1;
+        const int ostr[3] = {FY * FTt, FTt, 1};
         const float* dv = dval + (empty ? 0 : off[d]);
         const int64_t cnt = empty ? 0 : off[d + 1] - off[d];
         const bool staged = cnt <= CAPA;
@@ -769,61 +795,97 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
         double acc[NA];
 #pragma unroll
         for (int k = 0; k < NA; ++k) acc[k] = 0.0;
-        const int64_t total = (int64_t)nn[0] * nn[1] * nn[2];
-        // node (kx, ky, kt) of the window, stepped by NT (32-bit components)
-        Idx3 itn;
-        itn.init(tid, NT, max(nn[1], 1), max(nn[2], 1));
-        for (int64_t i = tid; i < total; i += NT, itn.next()) {
-            const int kx = itn.i, ky = itn.j, kt = itn.k;
-            const int cc[3] = {C0[0] + kx / ngl, C0[1] + ky / ngl, C0[2] + kt / ngl};
-            const int ll[3] = {kx % ngl, ky % ngl, kt % ngl};
-            // transposed spread: grid points c (1 - |xi| / 2) and c + sign(xi) (|xi| / 2)
-            float xi[3], wt = 1.0f;
-            int g2[3];
-            float u1[3], u2[3];
+        float ot[NGL];   // node offsets along t (from the centre of cell c)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                xi[a] = P.xi[ll[a]];
-                wt *= P.w[ll[a]];
-                u1[a] = 1.0f - 0.5f * fabsf(xi[a]);
-                u2[a] = 0.5f * fabsf(xi[a]);
-                g2[a] = xi[a] > 0.0f ? cc[a] + 1 : (xi[a] < 0.0f ? cc[a] - 1 : cc[a]);
-            }
-            float G = 0.0f;
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                int gp[3];
-                float u = 1.0f;
-                bool ok = true;
+        for (int j = 0; j < NGL; ++j) ot[j] = tqo[j] * fh[2];
+        const int64_t total = (int64_t)nd[0] * nd[1] * nd[2];
+        Idx3 itc;
+        itc.init(tid, NT, max(nd[1], 1), max(nd[2], 1));
+        auto run = [&](auto node) {
+            for (int64_t i = tid; i < total; i += NT, itc.next()) {
+                const int c[3] = {F0[0] - 1 + itc.i, F0[1] - 1 + itc.j, F0[2] - 1 + itc.k};
+                // patch gradient at c and c + 1 per axis (zero outside the footprint)
+                int o[3][2];
+                bool v[3][2], wl[3][2];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const bool second = (m >> a) & 1;
-                    if (second && g2[a] == cc[a]) ok = false;
-                    gp[a] = second ? g2[a] : cc[a];
-                    u *= second ? u2[a] : u1[a];
-                    if (gp[a] < F0[a] || gp[a] > F1[a]) ok = false;
+                    v[a][0] = c[a] >= F0[a];
+                    v[a][1] = c[a] + 1 <= F1[a];
+                    o[a][0] = v[a][0] ? (c[a] - F0[a]) * ostr[a] : 0;
+                    o[a][1] = v[a][1] ? (c[a] + 1 - F0[a]) * ostr[a] : 0;
+                    // nodes j >= NH lie in cell c, nodes j < NH in cell c + 1; either
+                    // cell may lie outside the quadrature window
+                    wl[a][0] = c[a] >= W.lo[a] && c[a] <= W.hi[a];
+                    wl[a][1] = c[a] + 1 >= W.lo[a] && c[a] + 1 <= W.hi[a];
                 }
-                if (ok) {
-                    const int64_t at = ((int64_t)(gp[0] - F0[0]) * FY + (gp[1] - F0[1])) * FTt +
-                                       (gp[2] - F0[2]);
-                    G += u * (staged ? sdv[at] : dv[at]);
+                float Dv[2][2][2];
+#pragma unroll
+                for (int bx = 0; bx < 2; ++bx)
+#pragma unroll
+                    for (int by = 0; by < 2; ++by)
+#pragma unroll
+                        for (int bt = 0; bt < 2; ++bt) {
+                            const bool ok = v[0][bx] && v[1][by] && v[2][bt];
+                            const int at = o[0][bx] + o[1][by] + o[2][bt];
+                            const float x = staged ? sdv[at] : dv[at];
+                            Dv[bx][by][bt] = ok ? x : 0.0f;
+                        }
+                // spread weights along t folded in: St[bx][by][jt]
+                float St[2][2][NGL];
+#pragma unroll
+                for (int jt = 0; jt < NGL; ++jt) {
+                    const bool okt = jt < NH ? wl[2][1] : wl[2][0];
+                    const float a0 = okt ? tq0[jt] : 0.0f, a1 = okt ? tq1[jt] : 0.0f;
+#pragma unroll
+                    for (int bx = 0; bx < 2; ++bx)
+#pragma unroll
+                        for (int by = 0; by < 2; ++by)
+                            St[bx][by][jt] = fmaf(a0, Dv[bx][by][0], a1 * Dv[bx][by][1]);
+                }
+                const float rbx = fb[0] + (float)(c[0] - W.lo[0]) * fh[0];
+                const float rby = fb[1] + (float)(c[1] - W.lo[1]) * fh[1];
+                const float rbt = fb[2] + (float)(c[2] - W.lo[2]) * fh[2];
+#pragma unroll 1
+                for (int jx = 0; jx < NGL; ++jx) {
+                    const bool okx = jx < NH ? wl[0][1] : wl[0][0];
+                    const float ax0 = okx ? stq[1][jx] : 0.0f, ax1 = okx ? stq[2][jx] : 0.0f;
+                    const float rx = fmaf(stq[0][jx], fh[0], rbx);
+                    // binary32 sums over the NGL^2 nodes of this x slice
+                    float fs[NA];
+#pragma unroll
+                    for (int k = 0; k < NA; ++k) fs[k] = 0.0f;
+#pragma unroll 1
+                    for (int jy = 0; jy < NGL; ++jy) {
+                        const bool oky = jy < NH ? wl[1][1] : wl[1][0];
+                        const float ay0 = oky ? stq[1][jy] : 0.0f, ay1 = oky ? stq[2][jy] : 0.0f;
+                        const float ry = fmaf(stq[0][jy], fh[1], rby);
+                        const float w00 = ax0 * ay0, w01 = ax0 * ay1, w10 = ax1 * ay0, w11 = ax1 * ay1;
+#pragma unroll
+                        for (int jt = 0; jt < NGL; ++jt) {
+                            const float w = fmaf(w00, St[0][0][jt],
+                                                 fmaf(w01, St[0][1][jt], fmaf(w10, St[1][0][jt], w11 * St[1][1][jt])));
+                            const float r[3] = {rx, ry, rbt + ot[jt]};
+                            node(w, r, fs);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < NA; ++k) acc[k] += (double)fs[k];
                 }
             }
-            if (G == 0.0f) continue;
-            float r[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) r[a] = fb[a] + ((float)(cc[a] - W.lo[a]) + 0.5f * xi[a]) * fh[a];
-            const float w = G * wt * jac;
-            if (point) {
+        };
+        if (point) {
+            run([&](float w, const float* r, float* fs) {
                 const float e = r[0] * r[0] * Is[0] + r[1] * r[1] * Is[1] + r[2] * r[2] * Is[2];
                 const float wg = w * (pref * exp_neg(-0.5f * e));
-                acc[SG] += (double)wg;
+                fs[SG] += wg;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    acc[SGP + a] += (double)(wg * r[a]);
-                    acc[SGP2 + a] += (double)(wg * r[a] * r[a]);
+                    fs[SGP + a] = fmaf(wg, r[a], fs[SGP + a]);
+                    fs[SGP2 + a] = fmaf(wg * r[a], r[a], fs[SGP2 + a]);
                 }
-            } else {
+            });
+        } else {
+            run([&](float w, const float* r, float* fs) {
                 const float sst = (r[0] * Df[0] * Is[0] + r[1] * Df[1] * Is[1] + r[2] * Df[2] * Is[2]) * ial;
                 float p[3], e = 0.0f;
 #pragma unroll
@@ -838,18 +900,18 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
                 const float wg = w * (N * erf_diff(B1, A1));
                 const float wph = w * (N * (gb - ga) * kia);
                 const float wps = w * (N * fmaf(gb, 1.0f - sst, ga * sst) * hik);
-                acc[SG] += (double)wg;
-                acc[SPHI] += (double)wph;
-                acc[SPHS] += (double)(wph * sst);
-                acc[SPSI] += (double)wps;
+                fs[SG] += wg;
+                fs[SPHI] += wph;
+                fs[SPHS] = fmaf(wph, sst, fs[SPHS]);
+                fs[SPSI] += wps;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    acc[SGP + a] += (double)(wg * p[a]);
-                    acc[SGP2 + a] += (double)(wg * p[a] * p[a]);
-                    acc[SGSP + a] += (double)(wg * sst * p[a]);
-                    acc[SPHP + a] += (double)(wph * p[a]);
+                    fs[SGP + a] = fmaf(wg, p[a], fs[SGP + a]);
+                    fs[SGP2 + a] = fmaf(wg * p[a], p[a], fs[SGP2 + a]);
+                    fs[SGSP + a] = fmaf(wg * sst, p[a], fs[SGSP + a]);
+                    fs[SPHP + a] = fmaf(wph, p[a], fs[SPHP + a]);
                 }
-            }
+            });
         }
         // workgroup reduction of the sums
 #pragma unroll
@@ -860,13 +922,16 @@ __global__ __launch_bounds__(256) void k_effq_adj(EffqParams P, int64_t n_dep,
             if (lane == 0) red[wave][k] = x;
         }
         __syncthreads();
+        if (tid < NA) {   // thread k totals sum k over the waves (in place, column k)
+            double x = red[0][tid];
+            for (int w = 1; w < NW; ++w) x += red[w][tid];
+            red[0][tid] = x * jac;
+        }
+        __syncthreads();
         if (tid == 0) {
             double S[NA];
 #pragma unroll
-            for (int k = 0; k < NA; ++k) {
-                S[k] = 0.0;
-                for (int w = 0; w < NW; ++w) S[k] += red[w][k];
-            }
+            for (int k = 0; k < NA; ++k) S[k] = red[0][k];
             // A[0..2]: d/dr, A[3..5]: d/dD, A[6..8]: d/dsigma (each times Qp), A[9]: d/dQp
             double A[10];
             const double sgS = S[SG], ia = point ? 0.0 : 1.0 / (double)alf;
