@@ -49,7 +49,7 @@ def dot(a, b):
 
 
 def grad_cfg(npix=8, sub=3, nticks=300, blk=(2, 2, 64), kpix=(3, 5), kticks=100, fft=(8, 8, 256),
-             n=6, seed=21, length=(0.05, 0.3)):
+             n=6, seed=21, length=(0.05, 0.3), n_gl=2):
     """Small region whose diffusion widths are above their floor (so the widths depend
     on the drift time and the diffusion constants) and whose segments take the line
     form."""
@@ -57,7 +57,7 @@ def grad_cfg(npix=8, sub=3, nticks=300, blk=(2, 2, 64), kpix=(3, 5), kticks=100,
     g = W.Grid(origin=(0.0, 0.0, 0.0), spacing=(h, h, W.TICK), npix=(npix, npix), sub=(sub, sub),
                nticks=nticks)
     ph = W.Physics(diff_T=1.2e-3, diff_L=6.0e-4, lifetime=40.0,
-                   sigma_min=(0.02 * h, 0.02 * h, 0.02 * W.TICK))
+                   sigma_min=(0.02 * h, 0.02 * h, 0.02 * W.TICK), n_gl=n_gl)
     zmax = nticks * W.TICK * ph.v_drift
     seg = W.gen_uniform_segments(n, (npix * W.PITCH, npix * W.PITCH), (0.15 * zmax, 0.7 * zmax),
                                  length_range=length, seed=seed)
@@ -307,11 +307,14 @@ def compare_grad(name, got, ref, tol):
     assert err <= tol, (name, err)
 
 
-def test_effq_gradient_vs_finite_differences(T, orc):
-    """dL/d(depositions, diff_T, diff_L, lifetime) for L = sum c * val (patch values)."""
+@pytest.mark.parametrize("n_gl", [2, 1, 3, 4])
+def test_effq_gradient_vs_finite_differences(T, orc, n_gl):
+    """dL/d(depositions, diff_T, diff_L, lifetime) for L = sum c * val (patch values), for
+    Gauss-Legendre rules of 1 to 4 points per axis (odd rules have a node at the cell
+    centre, which spreads onto its own grid point only)."""
     import torch
-    say("test_effq_gradient_vs_finite_differences")
-    g, ph, blk, kpix, kticks, fft, seg = grid_cfg_for_grad()
+    say(f"test_effq_gradient_vs_finite_differences[n_gl={n_gl}]")
+    g, ph, blk, kpix, kticks, fft, seg = grad_cfg(n_gl=n_gl)
     fp, off, ip = orc.footprints(g, ph, seg)
     assert not ip.any()
     nval = int(off[-1])
@@ -335,10 +338,6 @@ def test_effq_gradient_vs_finite_differences(T, orc):
     compare_grad("end points", got_seg[:, :6], ref_seg[:, :6], 1e-4)
     compare_grad("charges", got_seg[:, 6], ref_seg[:, 6], 1e-4)
     compare_grad("diff_T, diff_L, lifetime", got_phys, ref_phys, 1e-4)
-
-
-def grid_cfg_for_grad():
-    return grad_cfg()
 
 
 @pytest.mark.parametrize("name,kw", [
