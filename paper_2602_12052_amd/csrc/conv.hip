@@ -1134,16 +1134,69 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         }
     }
 
-    // inverse spatial transforms of every response piece and the mirror-pair unpacking
+    // inverse spatial transforms of every response piece and the mirror-pair unpacking.
+    // Per piece: the k1 inverse from the accumulators (M), the k2 inverse (Y, RS > 1),
+    // the x inverse over k1 (X) and over k2 (R, RS > 1), then the unpacking and stores
+    // of U (S). S of piece c - 1 reads y2 while M of piece c writes the other LDS
+    // region, so the two share a phase (four barriers per piece). Between the stages the
+    // values are kept conjugated where that saves sign flips: Y and R store their DFTs
+    // as computed (the conjugates of the inverses), X transforms Y's output as read, and
+    // S folds the last conjugation into the unpacking.
     const int qtiles = A.qpad / kTile;
     float2* gbuf = regA;                    // [NB][NF][FS kx][L n1][RS k2]
     float2* ybuf = regB;                    // [NB][NF][FS kx][YB qy]
     float2* g2 = regA;                      // [NB][NF][boy qy][L n1][RS k2]
-    float2* y2 = RS > 1 ? regB : regA;      // [NB][NF][box qx][YB qy]
+    float2* y2 = RS > 1 ? regB : regA;      // [NB][NF][box qx][YB qy], conjugated
+    // S items of this thread, the same for every piece: i = tid + NT k over [b][qt][fl2][qi];
+    // the y2 offsets of Y[q] and of its mirror Y[q'] (16 bits each; bit 31: q >= nq,
+    // stores zero) and the byte offset in piece c's part of this workgroup's bins of U
+    // (past the buffer resource for items outside the bins: dropped)
+    constexpr int QTM = (FS * FS + kTile - 1) / kTile;
+    constexpr int IS = (NB * QTM * NF * kTile + NT - 1) / NT;
+    static_assert(NB * NF * FS * (FS + 1) < 32768, "packed y2 offsets");
+    const int nq = box * boy;
+    const int nst = NB * qtiles * NF * kTile;
+    uint32_t s_src[IS], s_off[IS];
+#pragma unroll
+    for (int k = 0; k < IS; ++k) {
+        const int i = tid + NT * k;
+        const int qi = i % kTile;
+        int r = i / kTile;
+        const int fl2 = r % NF;
+        r /= NF;
+        const int qt = r % qtiles;
+        const int b = r / qtiles;
+        const int q = qt * kTile + qi;
+        const bool ok = i < nst && b < nbv;
+        uint32_t sp = 0x80000000u;
+        if (ok && q < nq) {
+            const int qx = q / boy, qy = q % boy;
+            const int base = (b * NF + fl2) * box * YB;
+            sp = (uint32_t)(base + qx * YB + qy) | ((uint32_t)(base + (box - 1 - qx) * YB + (boy - 1 - qy)) << 16);
+        }
+        s_src[k] = sp;
+        s_off[k] = ok ? (uint32_t)(8 * ((((int64_t)b * A.nc * qtiles + qt) * A.ft + f0 + fl2) * kTile + qi))
+                      : 0xfffffff0u;
+    }
+    const int64_t upiece = (int64_t)qtiles * A.ft * kTile;   // elements of one piece of a bin
+    float2* Ub = U + (int64_t)bl0 * A.nc * upiece;
+    const int64_t ubytes = (int64_t)nbv * A.nc * upiece * 8;   // below 2^31 (host check)
+    auto store_piece = [&](int c) {
+        const auto ur = buf_rsrc(Ub + (int64_t)c * upiece, (uint32_t)(ubytes - (int64_t)c * upiece * 8));
+#pragma unroll
+        for (int k = 0; k < IS; ++k) {
+            const uint32_t sp = s_src[k];
+            const float2 a = y2[sp & 0xffffu], m = y2[(sp >> 16) & 0x7fffu];
+            // y2 holds conj(Y): I[q] = Re Y[q] + Im Y[q'] (mirror pair) or Y[q]
+            float2 vq = A.mpcp ? make_float2(a.x - m.y, -a.y - m.x) : make_float2(a.x, -a.y);
+            if (sp >> 31) vq = make_float2(0.f, 0.f);
+            buf_st_f2(vq, ur, s_off[k], 0u);
+        }
+    };
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         if (c >= A.nc) break;
-        // y-inverse, L-point stage over k1 (conj(DFT(conj .)) = inverse DFT)
+        // M: y-inverse, L-point stage over k1 (conj(DFT(conj .)) = inverse DFT)
         if (active) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
@@ -1153,10 +1206,10 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 Dft<L>::run(t);
                 const int bf = b * NF + fl;
                 if constexpr (RS == 1) {
-                    float2* yr = ybuf + (bf * FS + kx) * YB;
+                    float2* yr = ybuf + (bf * FS + kx) * YB;   // conjugated
 #pragma unroll
                     for (int n = 0; n < L; ++n)
-                        if (n < boy) yr[n] = cconj(t[n]);
+                        if (n < boy) yr[n] = t[n];
                 } else {
                     float2* gr = gbuf + ((bf * FS + kx) * L) * RS + k2;
 #pragma unroll
@@ -1164,9 +1217,10 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 }
             }
         }
+        if (c > 0) store_piece(c - 1);
         __syncthreads();
         if constexpr (RS > 1) {
-            // y-inverse, RS-point stage over k2 -> qy = n_of(n1, n2) < boy
+            // Y: y-inverse, RS-point stage over k2 -> qy = n_of(n1, n2) < boy (conjugated)
             for (int i = tid; i < NB * NF * FS * L; i += NT) {
                 const int n1 = i % L;
                 const int r = i / L;   // bf * FS + kx
@@ -1179,12 +1233,13 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
                     const int qy = P::n_of(n1, n2);
-                    if (qy < boy) yr[qy] = cconj(t[n2]);
+                    if (qy < boy) yr[qy] = t[n2];
                 }
             }
             __syncthreads();
         }
-        // x-inverse, L-point stage over kx = k_of(k1, k2x) for every qy
+        // X: x-inverse, L-point stage over kx = k_of(k1, k2x) for every qy (the
+        // conjugated y inverse is the DFT's input as stored)
         for (int i = tid; i < NB * NF * boy * RS; i += NT) {
             const int kk = i % RS;
             const int r = i / RS;     // bf * boy + qy
@@ -1192,12 +1247,12 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             const float2* yr = ybuf + bf * FS * YB + qy;
             float2 t[L];
 #pragma unroll
-            for (int m = 0; m < L; ++m) t[m] = cconj(yr[P::k_of(m, kk) * YB]);
+            for (int m = 0; m < L; ++m) t[m] = yr[P::k_of(m, kk) * YB];
             Dft<L>::run(t);
             if constexpr (RS == 1) {
 #pragma unroll
                 for (int n = 0; n < L; ++n)
-                    if (n < box) y2[(bf * box + n) * YB + qy] = cconj(t[n]);
+                    if (n < box) y2[(bf * box + n) * YB + qy] = t[n];
             } else {
                 float2* gr = g2 + (r * L) * RS + kk;
 #pragma unroll
@@ -1206,6 +1261,7 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
         }
         __syncthreads();
         if constexpr (RS > 1) {
+            // R: x-inverse, RS-point stage -> qx = n_of(n1, n2) < box (conjugated)
             for (int i = tid; i < NB * NF * boy * L; i += NT) {
                 const int n1 = i % L;
                 const int r = i / L;  // bf * boy + qy
@@ -1218,36 +1274,13 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
                     const int qx = P::n_of(n1, n2);
-                    if (qx < box) y2[(bf * box + qx) * YB + qy] = cconj(t[n2]);
+                    if (qx < box) y2[(bf * box + qx) * YB + qy] = t[n2];
                 }
             }
             __syncthreads();
         }
-        // I[q] = Re Y[q] + Im Y[q'] (mirror-pair unpacking, as in k_sp)
-        const int nq = box * boy;
-        for (int i = tid; i < NB * qtiles * NF * kTile; i += NT) {
-            const int qi = i % kTile;
-            int r = i / kTile;
-            const int fl2 = r % NF;
-            r /= NF;
-            const int qt = r % qtiles;
-            const int b = r / qtiles;
-            if (b >= nbv) continue;
-            const int q = qt * kTile + qi;
-            float2 vq = make_float2(0.f, 0.f);
-            if (q < nq) {
-                const int qx = q / boy, qy = q % boy;
-                const float2* yy = y2 + (b * NF + fl2) * box * YB;
-                vq = yy[qx * YB + qy];
-                if (A.mpcp) {
-                    const float2 yb = yy[(box - 1 - qx) * YB + (boy - 1 - qy)];
-                    vq = make_float2(vq.x + yb.y, vq.y - yb.x);
-                }
-            }
-            U[((((int64_t)(bl0 + b) * A.nc + c) * qtiles + qt) * A.ft + f0 + fl2) * kTile + qi] = vq;
-        }
-        __syncthreads();
     }
+    store_piece(A.nc - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -2218,6 +2251,11 @@ tred_status launch_spp_nc(const ConvArgs& A, int b0, int nb, const int32_t* na, 
     if (tbytes > INT32_MAX)
         return tred_fail(TRED_EUNSUPPORTED, "spatial stage: %lld B of time spectra per workgroup",
                          (long long)tbytes);
+    // the stores of U address NB bins' pieces with 32-bit offsets
+    const int64_t ubytes = (int64_t)NB * A.nc * (A.qpad / kTile) * A.ft * kTile * 8;
+    if (ubytes > INT32_MAX)
+        return tred_fail(TRED_EUNSUPPORTED, "spatial stage: %lld B of output spectra per workgroup",
+                         (long long)ubytes);
     allow_lds(k_spp<FS, L, NIN, NB, NC>, lds);
     hipLaunchKernelGGL((k_spp<FS, L, NIN, NB, NC>), dim3((nb + NB - 1) / NB, A.ft / S::NF), dim3(S::NT),
                        lds, st, A, b0, nb, na, T, rhat, tws, U);
