@@ -1230,51 +1230,66 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 for (int k = 0; k < RS; ++k) t[k] = gr[k];
                 Dft<RS>::run(t);
                 float2* yr = ybuf + r * YB;
+                int qy = (RS * n1) % FS;   // n_of(n1, n2), stepping n2 by L (mod FS)
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
-                    const int qy = P::n_of(n1, n2);
                     if (qy < boy) yr[qy] = t[n2];
+                    qy += L;
+                    qy = qy >= FS ? qy - FS : qy;
                 }
             }
             __syncthreads();
         }
         // X: x-inverse, L-point stage over kx = k_of(k1, k2x) for every qy (the
-        // conjugated y inverse is the DFT's input as stored)
-        for (int i = tid; i < NB * NF * boy * RS; i += NT) {
+        // conjugated y inverse is the DFT's input as stored). Items run over qy < FS (a
+        // compile-time bound, so that their decomposition is shifts and multiplies by
+        // constants); rows qy >= boy are skipped.
+        for (int i = tid; i < NB * NF * FS * RS; i += NT) {
             const int kk = i % RS;
-            const int r = i / RS;     // bf * boy + qy
-            const int qy = r % boy, bf = r / boy;
+            const int r = i / RS;     // bf * FS + qy
+            const int qy = r % FS, bf = r / FS;
+            if (qy >= boy) continue;
             const float2* yr = ybuf + bf * FS * YB + qy;
             float2 t[L];
+            const int kb = (Pfa<L, RS>::k_of(0, 1) * kk) % FS;   // k_of(0, kk)
 #pragma unroll
-            for (int m = 0; m < L; ++m) t[m] = yr[P::k_of(m, kk) * YB];
+            for (int m = 0; m < L; ++m) {
+                int kxm = kb + P::k_of(m, 0);
+                kxm = kxm >= FS ? kxm - FS : kxm;
+                t[m] = yr[kxm * YB];
+            }
             Dft<L>::run(t);
             if constexpr (RS == 1) {
 #pragma unroll
                 for (int n = 0; n < L; ++n)
                     if (n < box) y2[(bf * box + n) * YB + qy] = t[n];
             } else {
-                float2* gr = g2 + (r * L) * RS + kk;
+                float2* gr = g2 + ((bf * boy + qy) * L) * RS + kk;
 #pragma unroll
                 for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
             }
         }
         __syncthreads();
         if constexpr (RS > 1) {
-            // R: x-inverse, RS-point stage -> qx = n_of(n1, n2) < box (conjugated)
-            for (int i = tid; i < NB * NF * boy * L; i += NT) {
+            // R: x-inverse, RS-point stage -> qx = n_of(n1, n2) < box (conjugated); items
+            // over qy < FS as in X
+            for (int i = tid; i < NB * NF * FS * L; i += NT) {
                 const int n1 = i % L;
-                const int r = i / L;  // bf * boy + qy
-                const int qy = r % boy, bf = r / boy;
-                const float2* gr = g2 + (r * L + n1) * RS;
+                const int r = i / L;  // bf * FS + qy
+                const int qy = r % FS, bf = r / FS;
+                if (qy >= boy) continue;
+                const float2* gr = g2 + ((bf * boy + qy) * L + n1) * RS;
                 float2 t[RS];
 #pragma unroll
                 for (int k = 0; k < RS; ++k) t[k] = gr[k];
                 Dft<RS>::run(t);
+                float2* yc = y2 + bf * box * YB + qy;
+                int qx = (RS * n1) % FS;   // n_of(n1, n2)
 #pragma unroll
                 for (int n2 = 0; n2 < RS; ++n2) {
-                    const int qx = P::n_of(n1, n2);
-                    if (qx < box) y2[(bf * box + qx) * YB + qy] = t[n2];
+                    if (qx < box) yc[qx * YB] = t[n2];
+                    qx += L;
+                    qx = qx >= FS ? qx - FS : qx;
                 }
             }
             __syncthreads();
