@@ -840,7 +840,7 @@ struct SppShape {
 };
 
 struct SppLds {
-    int tw, P1, YB, zsz, asz, gsz, g2sz, ysz, y2sz, A, B, total;
+    int tw, P1, YB, zsz, asz, gsz, g2sz, ysz, y2sz, A, B, C, total;
 };
 
 __host__ __device__ inline int even_up(int v) { return (v + 1) & ~1; }
@@ -867,9 +867,19 @@ __host__ __device__ inline SppLds spp_lds(int box, int boy) {
     // B also holds the forward stage's second staging buffer and, with the channel
     // pipeline, the second x-pass output after it
     if (s.zsz + s.asz > b) b = s.zsz + s.asz;
+    // RS > 1: the inverse transforms rotate the k2-inverse output, the x-inverse
+    // intermediate and the output of the pieces over B and a third region C
+    if (RS > 1 && s.g2sz > b) b = s.g2sz;
+    int c = 0;
+    if (RS > 1) {
+        c = s.ysz;
+        if (s.g2sz > c) c = s.g2sz;
+        if (s.y2sz > c) c = s.y2sz;
+    }
     s.A = even_up(a);
     s.B = even_up(b);
-    s.total = s.tw + s.A + s.B;
+    s.C = even_up(c);
+    s.total = s.tw + s.A + s.B + s.C;
     return s;
 }
 
@@ -1181,22 +1191,22 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
     const int64_t upiece = (int64_t)qtiles * A.ft * kTile;   // elements of one piece of a bin
     float2* Ub = U + (int64_t)bl0 * A.nc * upiece;
     const int64_t ubytes = (int64_t)nbv * A.nc * upiece * 8;   // below 2^31 (host check)
-    auto store_piece = [&](int c) {
+    auto store_piece = [&](int c, const float2* y2c) {
         const auto ur = buf_rsrc(Ub + (int64_t)c * upiece, (uint32_t)(ubytes - (int64_t)c * upiece * 8));
 #pragma unroll
         for (int k = 0; k < IS; ++k) {
             const uint32_t sp = s_src[k];
-            const float2 a = y2[sp & 0xffffu], m = y2[(sp >> 16) & 0x7fffu];
+            const float2 a = y2c[sp & 0xffffu], m = y2c[(sp >> 16) & 0x7fffu];
             // y2 holds conj(Y): I[q] = Re Y[q] + Im Y[q'] (mirror pair) or Y[q]
             float2 vq = A.mpcp ? make_float2(a.x - m.y, -a.y - m.x) : make_float2(a.x, -a.y);
             if (sp >> 31) vq = make_float2(0.f, 0.f);
             buf_st_f2(vq, ur, s_off[k], 0u);
         }
     };
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (c >= A.nc) break;
-        // M: y-inverse, L-point stage over k1 (conj(DFT(conj .)) = inverse DFT)
+    // M: y-inverse, L-point stage over k1 (conj(DFT(conj .)) = inverse DFT) of piece c
+    // (called from fully unrolled loops, so c indexes the accumulators at compile
+    // time); RS > 1: into gbuf, else into ybuf
+    auto stage_m = [&](int c) {
         if (active) {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
@@ -1217,39 +1227,38 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
                 }
             }
         }
-        if (c > 0) store_piece(c - 1);
-        __syncthreads();
-        if constexpr (RS > 1) {
-            // Y: y-inverse, RS-point stage over k2 -> qy = n_of(n1, n2) < boy (conjugated)
-            for (int i = tid; i < NB * NF * FS * L; i += NT) {
-                const int n1 = i % L;
-                const int r = i / L;   // bf * FS + kx
-                const float2* gr = gbuf + (r * L + n1) * RS;
-                float2 t[RS];
+    };
+    // Y: y-inverse, RS-point stage over k2 -> qy = n_of(n1, n2) < boy (conjugated)
+    auto stage_y = [&](float2* yb) {
+        for (int i = tid; i < NB * NF * FS * L; i += NT) {
+            const int n1 = i % L;
+            const int r = i / L;   // bf * FS + kx
+            const float2* gr = gbuf + (r * L + n1) * RS;
+            float2 t[RS];
 #pragma unroll
-                for (int k = 0; k < RS; ++k) t[k] = gr[k];
-                Dft<RS>::run(t);
-                float2* yr = ybuf + r * YB;
-                int qy = (RS * n1) % FS;   // n_of(n1, n2), stepping n2 by L (mod FS)
+            for (int k = 0; k < RS; ++k) t[k] = gr[k];
+            Dft<RS>::run(t);
+            float2* yr = yb + r * YB;
+            int qy = (RS * n1) % FS;   // n_of(n1, n2), stepping n2 by L (mod FS)
 #pragma unroll
-                for (int n2 = 0; n2 < RS; ++n2) {
-                    if (qy < boy) yr[qy] = t[n2];
-                    qy += L;
-                    qy = qy >= FS ? qy - FS : qy;
-                }
+            for (int n2 = 0; n2 < RS; ++n2) {
+                if (qy < boy) yr[qy] = t[n2];
+                qy += L;
+                qy = qy >= FS ? qy - FS : qy;
             }
-            __syncthreads();
         }
-        // X: x-inverse, L-point stage over kx = k_of(k1, k2x) for every qy (the
-        // conjugated y inverse is the DFT's input as stored). Items run over qy < FS (a
-        // compile-time bound, so that their decomposition is shifts and multiplies by
-        // constants); rows qy >= boy are skipped.
+    };
+    // X: x-inverse, L-point stage over kx = k_of(k1, k2x) for every qy (the conjugated
+    // y inverse is the DFT's input as stored). Items run over qy < FS (a compile-time
+    // bound, so that their decomposition is shifts and multiplies by constants); rows
+    // qy >= boy are skipped. RS > 1: into g2 [bf][boy qy][L n1][RS kk], else into y2.
+    auto stage_x = [&](const float2* yb, float2* dst) {
         for (int i = tid; i < NB * NF * FS * RS; i += NT) {
             const int kk = i % RS;
             const int r = i / RS;     // bf * FS + qy
             const int qy = r % FS, bf = r / FS;
             if (qy >= boy) continue;
-            const float2* yr = ybuf + bf * FS * YB + qy;
+            const float2* yr = yb + bf * FS * YB + qy;
             float2 t[L];
             const int kb = (Pfa<L, RS>::k_of(0, 1) * kk) % FS;   // k_of(0, kk)
 #pragma unroll
@@ -1262,40 +1271,73 @@ __global__ __launch_bounds__((SppShape<FS, L, NIN, NB>::NT)) __attribute__((amdg
             if constexpr (RS == 1) {
 #pragma unroll
                 for (int n = 0; n < L; ++n)
-                    if (n < box) y2[(bf * box + n) * YB + qy] = t[n];
+                    if (n < box) dst[(bf * box + n) * YB + qy] = t[n];
             } else {
-                float2* gr = g2 + ((bf * boy + qy) * L) * RS + kk;
+                float2* gr = dst + ((bf * boy + qy) * L) * RS + kk;
 #pragma unroll
                 for (int n = 0; n < L; ++n) gr[n * RS] = t[n];
             }
         }
-        __syncthreads();
-        if constexpr (RS > 1) {
-            // R: x-inverse, RS-point stage -> qx = n_of(n1, n2) < box (conjugated); items
-            // over qy < FS as in X
-            for (int i = tid; i < NB * NF * FS * L; i += NT) {
-                const int n1 = i % L;
-                const int r = i / L;  // bf * FS + qy
-                const int qy = r % FS, bf = r / FS;
-                if (qy >= boy) continue;
-                const float2* gr = g2 + ((bf * boy + qy) * L + n1) * RS;
-                float2 t[RS];
+    };
+    // R: x-inverse, RS-point stage -> qx = n_of(n1, n2) < box (conjugated); items over
+    // qy < FS as in X
+    auto stage_r = [&](const float2* g2c, float2* y2c) {
+        for (int i = tid; i < NB * NF * FS * L; i += NT) {
+            const int n1 = i % L;
+            const int r = i / L;  // bf * FS + qy
+            const int qy = r % FS, bf = r / FS;
+            if (qy >= boy) continue;
+            const float2* gr = g2c + ((bf * boy + qy) * L + n1) * RS;
+            float2 t[RS];
 #pragma unroll
-                for (int k = 0; k < RS; ++k) t[k] = gr[k];
-                Dft<RS>::run(t);
-                float2* yc = y2 + bf * box * YB + qy;
-                int qx = (RS * n1) % FS;   // n_of(n1, n2)
+            for (int k = 0; k < RS; ++k) t[k] = gr[k];
+            Dft<RS>::run(t);
+            float2* yc = y2c + bf * box * YB + qy;
+            int qx = (RS * n1) % FS;   // n_of(n1, n2)
 #pragma unroll
-                for (int n2 = 0; n2 < RS; ++n2) {
-                    if (qx < box) yc[qx * YB] = t[n2];
-                    qx += L;
-                    qx = qx >= FS ? qx - FS : qx;
-                }
+            for (int n2 = 0; n2 < RS; ++n2) {
+                if (qx < box) yc[qx * YB] = t[n2];
+                qx += L;
+                qx = qx >= FS ? qx - FS : qx;
             }
+        }
+    };
+    if constexpr (RS > 1) {
+        // Three phases per piece: {M(c), R(c - 1)}, {Y(c), S(c - 1)}, {X(c)}. M writes
+        // gbuf (region A); the k2-inverse output, the x-inverse intermediate and the
+        // output of piece c lie in (B, C, B) for even c and (C, B, C) for odd c, so no
+        // phase writes a buffer that another of its stages reads, and every buffer is
+        // read before the phase that overwrites it.
+        auto yb_of = [&](int c) { return regB + (c & 1) * Ls.B; };          // y and y2
+        auto g2_of = [&](int c) { return regB + ((c & 1) ^ 1) * Ls.B; };    // g2
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c >= A.nc) break;
+            stage_m(c);
+            if (c > 0) stage_r(g2_of(c - 1), yb_of(c - 1));
+            __syncthreads();
+            stage_y(yb_of(c));
+            if (c > 0) store_piece(c - 1, yb_of(c - 1));
+            __syncthreads();
+            stage_x(yb_of(c), g2_of(c));
             __syncthreads();
         }
+        stage_r(g2_of(A.nc - 1), yb_of(A.nc - 1));
+        __syncthreads();
+        store_piece(A.nc - 1, yb_of(A.nc - 1));
+    } else {
+        // two phases per piece: {M(c) into ybuf, S(c - 1) from y2 (region A)}, {X(c)}
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c >= A.nc) break;
+            stage_m(c);
+            if (c > 0) store_piece(c - 1, y2);
+            __syncthreads();
+            stage_x(ybuf, y2);
+            __syncthreads();
+        }
+        store_piece(A.nc - 1, y2);
     }
-    store_piece(A.nc - 1);
 }
 
 // ---------------------------------------------------------------------------
