@@ -332,7 +332,8 @@ def bench_batched(args):
     best = tune.best
     blk = W.Blocking((best.blk_pix, best.blk_pix), best.blk_ticks)
     fft = best.fft
-    caps = [tred.size_event(g, ph, blk, cfg.kpix, torch.from_numpy(e).cuda()) for e in evs]
+    caps = [tred.size_event(g, ph, blk, cfg.kpix, torch.from_numpy(e).cuda(), exact_pixels=True)
+            for e in evs]
     bins = np.array([c[1] for c in caps])
     fixed, scratch = autotune._bytes_per_bin(g, blk, cfg.kpix, cfg.kticks, fft, True)
     pass_bins = max(1, int(args.pass_gb * 1e9 // scratch))
@@ -360,20 +361,21 @@ def bench_batched(args):
         offs.append(torch.from_numpy(np.concatenate([[0], np.cumsum(sizes[c])]).astype(np.int64)).cuda())
     log(f"{len(evs)} events, {int(sizes.sum())} depositions, {int(bins.sum())} active (event, bin) "
         f"pairs in {len(chunks)} chunks (<= {chunk_bins} bins), {pass_bins} bins per pass")
-    # eager warm-up of every chunk, then one captured graph per chunk
-    for sg, of in zip(segs, offs):
-        bp.run(sg, of)
+    # eager warm-up of every chunk, then one captured graph per chunk; each chunk writes
+    # waveform rows up to its own pixel capacity (its events' bounds)
+    for sg, of, cc in zip(segs, offs, ccap):
+        bp.run(sg, of, pix_cap=cc[2])
     torch.cuda.synchronize()
     graphs = []
-    for sg, of in zip(segs, offs):
+    for sg, of, cc in zip(segs, offs, ccap):
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            bp.run(sg, of)
+            bp.run(sg, of, pix_cap=cc[2])
         torch.cuda.current_stream().wait_stream(side)
         gr = torch.cuda.CUDAGraph()
         with torch.cuda.graph(gr):
-            bp.run(sg, of)
+            bp.run(sg, of, pix_cap=cc[2])
         graphs.append(gr)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream().cuda_stream

@@ -788,11 +788,17 @@ class BatchPipeline:
             max(4, tred_scatter_events_workspace(self.plan, self.n_ev_max)), dtype=torch.uint8,
             device=dev)
 
-    def run(self, seg, ev_off, stream=None):
-        """seg: float32 [n, 7] device (n <= n_dep_max); ev_off: int64 device [n_ev + 1]."""
+    def run(self, seg, ev_off, stream=None, pix_cap=None):
+        """seg: float32 [n, 7] device (n <= n_dep_max); ev_off: int64 device [n_ev + 1].
+        pix_cap: pixel capacity of this batch (at most the pipeline's; default the
+        pipeline's): the waveforms of this run are rows 0 .. pix_cap - 1 of wf, the rows
+        past the batch's n_pix among them zero, and rows past pix_cap are not touched
+        (a batch of small events then writes no zero waveforms for the largest batch's
+        pixels)."""
         n, n_ev = seg.shape[0], ev_off.numel() - 1
         if n > self.n_dep_max or n_ev > self.n_ev_max:
             raise ValueError("batch exceeds the pipeline's capacities")
+        pc = self._pix_cap(pix_cap)
         fp, off = self.fp[:n], self.off[:n + 1]
         tred_effq_windows(self.grid, self.phys, seg, fp, off, stream)
         self.charge_sum.zero_()
@@ -816,25 +822,33 @@ class BatchPipeline:
         else:
             tred_block_conv(self.plan, self.n_active, self.blocks, self.out_blocks, stream)
         tred_scatter_waveforms_events(self.plan, n_ev, self.keys, self.n_active, self.out_blocks,
-                                      self.pix, self.n_pix, self.wf, self.scat_work, stream)
+                                      self.pix[:pc], self.n_pix, self.wf[:pc], self.scat_work, stream)
 
-    def results(self, n_dep=None):
+    def _pix_cap(self, pix_cap):
+        pc = self.pix.shape[0] if pix_cap is None else int(pix_cap)
+        if pc < 1 or pc > self.pix.shape[0]:
+            raise ValueError("pix_cap must be in 1 .. the pipeline's pixel capacity")
+        return pc
+
+    def results(self, n_dep=None, pix_cap=None):
         """Host copies of the outputs of the last run (synchronises); n_dep: depositions
-        of that run. Raises TredError if the run overflowed a capacity."""
+        of that run, pix_cap: its pixel capacity (the value given to run(), which a graph
+        replay does not record). Raises TredError if the run overflowed a capacity."""
         import torch
         torch.cuda.synchronize()
         n = self.n_dep_max if n_dep is None else int(n_dep)
         na = int(self.n_active.item())
         npx = int(self.n_pix.item())
+        pc = self._pix_cap(pix_cap)
         if n_dep is not None and not self.fused:
             _check_counts(int(self.off[n].item()), self.val.numel(), na, self.keys.shape[0],
-                          npx, self.pix.shape[0])
+                          npx, pc)
         else:
-            _check_counts(0, 0, na, self.keys.shape[0], npx, self.pix.shape[0])
+            _check_counts(0, 0, na, self.keys.shape[0], npx, pc)
         return dict(fp=self.fp[:n].cpu().numpy(), off=self.off[:n + 1].cpu().numpy(),
                     n_active=na, keys=self.keys[:min(na, self.keys.shape[0])].cpu().numpy(),
-                    n_pix=npx, pix=self.pix[:min(npx, self.pix.shape[0])].cpu().numpy(),
-                    wf=self.wf[:min(npx, self.pix.shape[0])].cpu().numpy(),
+                    n_pix=npx, pix=self.pix[:min(npx, pc)].cpu().numpy(),
+                    wf=self.wf[:min(npx, pc)].cpu().numpy(),
                     charge_sum=float(self.charge_sum.item()))
 
 
@@ -889,10 +903,37 @@ def conv_batch(grid, blocking, kpix, kticks, fft, mpcp, n_bins, scratch_bytes) -
 DEFAULT_CONV_SCRATCH = 160e9
 
 
-def size_event(grid, phys, blocking, kpix, seg):
+def _event_pixels(fp, g, b, kpix) -> int:
+    """Pixels of an event's waveforms from its cell footprints fp (host int32 [n, 6]):
+    the union over its active bins (those a footprint reaches, as the binning marks
+    them) of the bins' output footprints in x and y, clipped to the region."""
+    f = fp[(fp[:, 3] >= fp[:, 0]) & (fp[:, 4] >= fp[:, 1]) & (fp[:, 5] >= fp[:, 2])]
+    if len(f) == 0:
+        return 0
+    bf0, bf1 = b.blk_pix[0] * g.sub[0], b.blk_pix[1] * g.sub[1]
+    bx0, bx1 = f[:, 0] // bf0, f[:, 3] // bf0
+    by0, by1 = f[:, 1] // bf1, f[:, 4] // bf1
+    act = np.zeros((int(bx1.max()) + 1, int(by1.max()) + 1), dtype=bool)
+    for dx in range(int((bx1 - bx0).max()) + 1):
+        for dy in range(int((by1 - by0).max()) + 1):
+            m = (bx0 + dx <= bx1) & (by0 + dy <= by1)
+            act[bx0[m] + dx, by0[m] + dy] = True
+    npx, npy = int(g.npix[0]), int(g.npix[1])
+    hx, hy = (int(kpix[0]) - 1) // 2, (int(kpix[1]) - 1) // 2
+    Bx, By = b.blk_pix[0], b.blk_pix[1]
+    pix = np.zeros((npx, npy), dtype=bool)
+    for bx, by in zip(*np.nonzero(act)):
+        pix[max(0, bx * Bx - hx):min(npx, bx * Bx + Bx + hx),
+            max(0, by * By - hy):min(npy, by * By + By + hy)] = True
+    return int(pix.sum())
+
+
+def size_event(grid, phys, blocking, kpix, seg, exact_pixels=False):
     """Capacities of one event: exact patch length and active-bin count (footprint
     step plus a counting pass of the binning, then one synchronisation), and the
-    host bound min(region pixels, bins x output pixels per bin) for the pixels."""
+    host bound min(region pixels, bins x output pixels per bin) for the pixels, or
+    with exact_pixels the event's pixel count itself (its footprints copied to the
+    host; a pipeline sized by it has no slack for depositions that move)."""
     import torch
     n = seg.shape[0]
     fp = torch.empty((n, 6), dtype=torch.int32, device="cuda")
@@ -908,6 +949,8 @@ def size_event(grid, phys, blocking, kpix, seg):
     block_cap = int(na.item())
     per = (b.blk_pix[0] + kpix[0] - 1) * (b.blk_pix[1] + kpix[1] - 1)
     pix_cap = min(int(g.npix[0]) * int(g.npix[1]), block_cap * per)
+    if exact_pixels:
+        pix_cap = _event_pixels(fp.cpu().numpy(), g, b, kpix)
     return max(val_cap, 1), max(block_cap, 1), max(pix_cap, 1)
 
 

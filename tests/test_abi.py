@@ -272,3 +272,25 @@ def test_fused_effq_bin_rejects(T):
     assert L.tred_effq_bin(C.byref(gb), C.byref(ph), C.byref(bb), 1, p, p, p, p, p, p, 4, None, p,
                            None) == T.TRED_EINVAL
     assert b"cells per bin" in L.tred_last_error()
+
+
+@pytest.mark.parametrize("seed,npix,blk,kpix", [(1, 12, (4, 4, 64), (5, 5)), (2, 16, (4, 4, 32), (7, 3)),
+                                                 (3, 10, (2, 2, 64), (3, 5)), (4, 24, (8, 8, 128), (21, 21))])
+def test_event_pixel_count_matches_oracle(T, orc, seed, npix, blk, kpix):
+    """The exact pixel count the batched benchmark sizes its chunks by (host code of the
+    binding) equals the size of the oracle's pixel set, on random events whose
+    footprints reach the region edges."""
+    import numpy as np
+    h = W.PITCH / 3
+    g = W.Grid(origin=(0.0, 0.0, 0.0), spacing=(h, h, W.TICK), npix=(npix, npix), sub=(3, 3),
+               nticks=400)
+    ph = W.Physics(sigma_min=(0.5 * h, 0.5 * h, 0.5 * W.TICK))
+    b = W.Blocking(blk[:2], blk[2])
+    zmax = g.nticks * W.TICK * ph.v_drift
+    seg = W.gen_uniform_segments(25, (npix * W.PITCH, npix * W.PITCH), (0.05 * zmax, 0.8 * zmax),
+                                 seed=seed)
+    fp, off, _ = orc.footprints(g, ph, seg)
+    keys = orc.block_keys(g, b, fp)
+    want = len(orc.pix_set(g, b, kpix, keys))
+    got = T._event_pixels(np.asarray(fp, np.int32), T.grid_struct(g), T.blocking_struct(b), kpix)
+    assert got == want, (got, want)

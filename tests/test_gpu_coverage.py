@@ -337,7 +337,7 @@ def test_event_batch_64_matches_oracle(T, orc):
     """The 64 module-scale events of the batched workload (2.4 M depositions), run as the
     benchmark runs them: events grouped into chunks whose bins fit a 200 GB budget
     (with a 60 GB convolution pass), each chunk through one BatchPipeline (16x16x512
-    bins, FFT 40x40x1024). Per event, the bins and the pixel set equal the oracle's;
+    bins, FFT 40x40x1024) with the chunk's own pixel capacity. Per event, the bins and the pixel set equal the oracle's;
     sampled waveform points of the three smallest events are within 1e-5 of it."""
     import torch
     from paper_2602_12052_amd import autotune
@@ -356,6 +356,10 @@ def test_event_batch_64_matches_oracle(T, orc):
         opix.append(orc.pix_set(g, blk, cfg.kpix, k))
         ofps.append((fp, off))
     bins = np.array([len(k) for k in okeys])
+    # the exact pixel counts the benchmark sizes its chunks by equal the oracle's pixel sets
+    for e in np.argsort(sizes)[[0, 1, len(evs) // 2, -1]]:
+        got = T.size_event(g, ph, blk, cfg.kpix, dev(evs[e]), exact_pixels=True)
+        assert got[1] == bins[e] and got[2] == len(opix[e]), (e, got, bins[e], len(opix[e]))
     fixed, scratch = autotune._bytes_per_bin(g, blk, cfg.kpix, cfg.kticks, cfg.fft, True)
     pass_bins = max(1, int(60e9 // scratch))
     chunk_bins = max(int(bins.max()), int((200e9 - pass_bins * scratch) // fixed))
@@ -384,11 +388,15 @@ def test_event_batch_64_matches_oracle(T, orc):
     for ci, c in enumerate(chunks):
         n = int(sizes[c].sum())
         eo = np.concatenate([[0], np.cumsum(sizes[c])]).astype(np.int64)
-        bp.run(dev(np.concatenate([evs[e] for e in c])), dev(eo))
+        # each chunk with its own pixel capacity, as the benchmark runs them
+        pc = caps[ci][2]
+        bp.run(dev(np.concatenate([evs[e] for e in c])), dev(eo), pix_cap=pc)
         torch.cuda.synchronize()
         na, npx = int(bp.n_active.item()), int(bp.n_pix.item())
         assert int(bp.off[n].item()) <= bp.val.numel()
-        assert na <= bp.keys.shape[0] and npx <= bp.pix.shape[0]
+        assert na <= bp.keys.shape[0] and npx <= pc <= bp.pix.shape[0]
+        # the rows past the chunk's pixels, up to its capacity, are zero waveforms
+        assert npx == pc or float(bp.wf[npx:pc].abs().max()) == 0.0
         keys = bp.keys[:na].cpu().numpy()
         pix = bp.pix[:npx].cpu().numpy()
         for i, e in enumerate(c):

@@ -154,28 +154,29 @@ def test_batch_graph_replays_match_eager(T):
     caps = [max(x, y) for x, y in zip(ca, cb)]
     bp = T.BatchPipeline(g, ph, blk, kpix, kticks, dev(resp), 3, max(len(seg_a), len(seg_b)),
                          caps[0], caps[1], caps[2], fft, True, 4)
-    bp.run(sa, oa)
-    ref_a = bp.results(len(seg_a))
-    bp.run(sb, ob)
-    ref_b = bp.results(len(seg_b))
+    # each batch with its own pixel capacity (batch a's graph writes rows up to ca[2])
+    bp.run(sa, oa, pix_cap=ca[2])
+    ref_a = bp.results(len(seg_a), pix_cap=ca[2])
+    bp.run(sb, ob, pix_cap=cb[2])
+    ref_b = bp.results(len(seg_b), pix_cap=cb[2])
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        bp.run(sa, oa)
+        bp.run(sa, oa, pix_cap=ca[2])
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        bp.run(sa, oa)
+        bp.run(sa, oa, pix_cap=ca[2])
     for rep in range(3):
         graph.replay()
-        got = bp.results(len(seg_a))
+        got = bp.results(len(seg_a), pix_cap=ca[2])
         assert got["n_active"] == ref_a["n_active"] and np.array_equal(got["keys"], ref_a["keys"])
         assert np.array_equal(got["pix"], ref_a["pix"])
         err = rel_l2(got["wf"], ref_a["wf"])
         say(f"  replay {rep}: rel-L2 vs eager {err:.2e}")
         assert err < 1e-6
-        bp.run(sb, ob)            # eager work through the same buffers between replays
-        got_b = bp.results(len(seg_b))
+        bp.run(sb, ob, pix_cap=cb[2])   # eager work through the same buffers between replays
+        got_b = bp.results(len(seg_b), pix_cap=cb[2])
         assert np.array_equal(got_b["keys"], ref_b["keys"])
         assert rel_l2(got_b["wf"], ref_b["wf"]) < 1e-6
