@@ -308,7 +308,8 @@ def bench_batched(args):
     """Batched events: n_ev module-scale events of log-uniform size in [1e3, 2e5]. The
     autotuner picks the bin shape and FFT sizes on three events (the quartile sizes);
     events are taken smallest first (by active bins) and grouped into chunks of at most
-    --chunk-bins (event, bin) pairs that also fit a memory budget; each chunk's whole
+    --chunk-bins (event, bin) pairs that also fit a memory budget (an event with more
+    bins is a chunk of its own); each chunk's whole
     path (effq, binning with the event in the key, one convolution queue over all its
     bins, per-event overlap-add) is captured once in a HIP graph, and the graphs are
     replayed back to back. Reports throughput and the per-event completion latency
@@ -337,8 +338,10 @@ def bench_batched(args):
     bins = np.array([c[1] for c in caps])
     fixed, scratch = autotune._bytes_per_bin(g, blk, cfg.kpix, cfg.kticks, fft, True)
     pass_bins = max(1, int(args.pass_gb * 1e9 // scratch))
-    chunk_bins = max(int(bins.max()), min(args.chunk_bins,
-                                          int((args.budget_gb * 1e9 - pass_bins * scratch) // fixed)))
+    # packing target of a chunk; an event with more bins than that is a chunk of its own
+    # (the pipeline's capacity is the largest chunk, whichever of the two it is)
+    chunk_bins = max(1, min(args.chunk_bins,
+                            int((args.budget_gb * 1e9 - pass_bins * scratch) // fixed)))
     # smallest events first: the median event completes after a small share of the work
     chunks, cur, nb = [], [], 0
     for e in np.argsort(bins, kind="stable"):
@@ -351,16 +354,18 @@ def bench_batched(args):
     chunks.append(cur)
     ccap = [(sum(caps[e][0] for e in c), sum(caps[e][1] for e in c), sum(caps[e][2] for e in c),
              int(sizes[c].sum())) for c in chunks]
+    maxc = max(c[1] for c in ccap)
     bp = tred.BatchPipeline(g, ph, blk, cfg.kpix, cfg.kticks, dresp, max(len(c) for c in chunks),
                             max(c[3] for c in ccap), max(c[0] for c in ccap),
-                            max(c[1] for c in ccap), max(c[2] for c in ccap), fft, True,
-                            min(pass_bins, max(c[1] for c in ccap)), fused=not args.unfused)
+                            maxc, max(c[2] for c in ccap), fft, True,
+                            min(pass_bins, maxc), fused=not args.unfused)
     segs, offs = [], []
     for c in chunks:
         segs.append(torch.from_numpy(np.concatenate([evs[e] for e in c])).cuda())
         offs.append(torch.from_numpy(np.concatenate([[0], np.cumsum(sizes[c])]).astype(np.int64)).cuda())
     log(f"{len(evs)} events, {int(sizes.sum())} depositions, {int(bins.sum())} active (event, bin) "
-        f"pairs in {len(chunks)} chunks (<= {chunk_bins} bins), {pass_bins} bins per pass")
+        f"pairs in {len(chunks)} chunks (packed to <= {chunk_bins} bins, largest {maxc}), "
+        f"{pass_bins} bins per pass")
     # eager warm-up of every chunk, then one captured graph per chunk; each chunk writes
     # waveform rows up to its own pixel capacity (its events' bounds)
     for sg, of, cc in zip(segs, offs, ccap):
@@ -401,9 +406,9 @@ def bench_batched(args):
         "config": {"workload": f"{len(evs)} module-scale events, deposition counts log-uniform in "
                                f"[1e3, 2e5], per-event track/blob mix",
                    "n_dep": int(sizes.sum()), "active_event_bins": int(bins.sum()),
-                   "chunks": len(chunks), "chunk_bins": chunk_bins, "order": "smallest first",
+                   "chunks": len(chunks), "chunk_bins": chunk_bins, "chunk_capacity": maxc, "order": "smallest first",
                    "effective_charge": "patches" if args.unfused else "into the bins",
-                   "bins_per_pass": min(pass_bins, max(c[1] for c in ccap)),
+                   "bins_per_pass": min(pass_bins, maxc),
                    "blocking": [best.blk_pix, best.blk_pix, best.blk_ticks], "fft": list(fft)},
         "event_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "autotune": [{"blk": [t.blk_pix, t.blk_pix, t.blk_ticks], "fft": list(t.fft), "ms": t.ms,
@@ -419,7 +424,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=40)
+    ap.add_argument("--cpu-sample", type=int, default=140)
     ap.add_argument("--plain", action="store_true", help="complex-of-real packing instead of MPCP")
     ap.add_argument("--unfused", action="store_true",
                     help="effective charge as patches (tred_effq), then tred_block_bin_rows, "
