@@ -337,7 +337,10 @@ def bench_batched(args):
             for e in evs]
     bins = np.array([c[1] for c in caps])
     fixed, scratch = autotune._bytes_per_bin(g, blk, cfg.kpix, cfg.kticks, fft, True)
-    pass_bins = max(1, int(args.pass_gb * 1e9 // scratch))
+    # one convolution pass per packed chunk unless --pass-gb bounds its scratch (each
+    # pass has a fixed cost besides its bins, so a second, small pass is not free)
+    pass_bins = (args.chunk_bins if args.pass_gb is None
+                 else max(1, int(args.pass_gb * 1e9 // scratch)))
     # packing target of a chunk; an event with more bins than that is a chunk of its own
     # (the pipeline's capacity is the largest chunk, whichever of the two it is)
     chunk_bins = max(1, min(args.chunk_bins,
@@ -439,7 +442,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="device memory of a chunk")
     ap.add_argument("--chunk-bins", type=int, default=512,
                     help="(event, bin) pairs per chunk of the batched form (at least one event)")
-    ap.add_argument("--pass-gb", type=float, default=60.0, help="convolution scratch per pass")
+    ap.add_argument("--pass-gb", type=float, default=None,
+                    help="convolution scratch per pass (default: one pass per --chunk-bins)")
     ap.add_argument("--form", default="fft",
                     choices=["fft", "direct-split", "direct-bf16", "batched", "adjoint"],
                     help="fft: the benchmark line; direct-*: block-direct convolution on BF16 "
