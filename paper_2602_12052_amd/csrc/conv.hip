@@ -226,6 +226,28 @@ __host__ __device__ constexpr int tf_lds_floats() {
 // of one column over all banks (rows are 64 bytes, four rows span the 64 banks)
 __device__ __forceinline__ int tf_col(int f, int c) { return c ^ ((f >> 2) & (kTile - 1)); }
 
+// Stores a staged tile ([f][kTile], columns swizzled) as half `half` of a T tile (rows
+// of kTileT pixels) with 512 threads: thread t writes pixels c, c + 1
+// (c = 2 (t % (kTile / 2))) of rows f = t / (kTile / 2) + R k (R = 512 / (kTile / 2))
+// with one 16-byte store. The swizzle XORs c with s = (f / 4) % kTile, the same for all
+// of a thread's rows (R is a multiple of 4 kTile), and keeps the two pixels in one
+// aligned pair of the staging row, swapped where s is odd.
+template <int FT>
+__device__ __forceinline__ void tf_store_tile(const float2* stage, __amdgpu_buffer_rsrc_t tr, int half) {
+    constexpr int TPR = kTile / 2, R = 512 / TPR;
+    static_assert(kTile % 2 == 0 && R % (4 * kTile) == 0 && FT % R == 0, "store loop");
+    const int f0 = (int)threadIdx.x / TPR, c = 2 * ((int)threadIdx.x % TPR);
+    const int sw = (f0 >> 2) & (kTile - 1);
+    const float4* src = (const float4*)(stage + f0 * kTile + ((c ^ sw) & ~1));
+    const uint32_t voff = (uint32_t)((f0 * kTileT + half * kTile + c) * 8);
+#pragma unroll
+    for (int k = 0; k < FT / R; ++k) {
+        const float4 p = src[k * R * kTile / 2];
+        const float4 v = (sw & 1) ? make_float4(p.z, p.w, p.x, p.y) : p;
+        buf_st_f4(v, tr, voff, (uint32_t)(k * R * kTileT * 8));
+    }
+}
+
 // Group q -> (bin, channel, tile, half). T tiles hold kTileT = 2 kTile pixels per
 // frequency (one 128-byte line) and a group transforms the 8 rows of one half.
 // Workgroup ids are dealt to the XCDs round-robin; with G a multiple of 2 kXcd the
@@ -340,18 +362,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
         __syncthreads();
         const auto tr = buf_rsrc(T + (((int64_t)g.bl * A.nch + g.ch) * (A.ppad / kTileT) + g.pt) * FT * kTileT,
                                  (uint32_t)(FT * kTileT * sizeof(float2)));
-        // thread t stores pixel c = t % kTile of rows f = t / kTile + (512 / kTile) k; the
-        // swizzle term of those rows does not depend on k (512 / kTile / 4 is a multiple
-        // of kTile), so the LDS and T offsets are a per-thread base plus constants
-        static_assert(FT * kTile % 512 == 0 && (512 / kTile / 4) % kTile == 0, "store loop");
-        {
-            const int f0 = (int)threadIdx.x / kTile, c = (int)threadIdx.x % kTile;
-            const float2* src = stage + f0 * kTile + tf_col(f0, c);
-            const uint32_t voff = (uint32_t)((f0 * kTileT + g.half * kTile + c) * 8);
-#pragma unroll
-            for (int k = 0; k < FT * kTile / 512; ++k)
-                buf_st_f2(src[512 * k], tr, voff, (uint32_t)(k * (512 / kTile) * kTileT * 8));
-        }
+        tf_store_tile<FT>(stage, tr, g.half);
         __syncthreads();   // the next FFT's scratch overlaps the staging tile
     }
 }
@@ -522,16 +533,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
         __syncthreads();
         const auto tr = buf_rsrc(T + (int64_t)tile * FT * kTileT,
                                  wr ? (uint32_t)(FT * kTileT * sizeof(float2)) : 0u);
-        // thread t stores pixel c = t % kTile of rows f = t / kTile + (512 / kTile) k
-        // (as in k_tf)
-        {
-            const int f0 = (int)threadIdx.x / kTile, c = (int)threadIdx.x % kTile;
-            const float2* src = stage + f0 * kTile + tf_col(f0, c);
-            const uint32_t voff = (uint32_t)((f0 * kTileT + h * kTile + c) * 8);
-#pragma unroll
-            for (int k = 0; k < FT * kTile / 512; ++k)
-                buf_st_f2(src[512 * k], tr, voff, (uint32_t)(k * (512 / kTile) * kTileT * 8));
-        }
+        tf_store_tile<FT>(stage, tr, h);
         __syncthreads();   // the next FFT's scratch overlaps the staging tile
     }
 }

@@ -268,6 +268,13 @@ __device__ __forceinline__ void buf_st_f2(float2 v, __amdgpu_buffer_rsrc_t r, ui
                                           TRED_NT_STORE ? 2 : 0);
 }
 
+__device__ __forceinline__ void buf_st_f4(float4 v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff) {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, voff, soff,
+                                           TRED_NT_STORE ? 2 : 0);
+}
+
 __device__ __forceinline__ void buf_st_f1(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
                                           uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
