@@ -1483,9 +1483,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FT <= 1024 
     __syncthreads();
     const int qtiles = A.qpad / kTile;
     float2* d2 = dU + ((((int64_t)bl * A.nc + c) * qtiles + qt) * FT) * kTile;
-    for (int i = threadIdx.x; i < FT * kTile; i += blockDim.x) {
-        const int f = i / kTile, cc = i % kTile;
-        d2[i] = stage[f * kTile + tf_col(f, cc)];
+    // the tile is contiguous: thread t writes elements i, i + 1 (i = 2 (t + 512 k), so
+    // pixels cc, cc + 1 of one row, one aligned LDS pair under the swizzle, swapped
+    // where the swizzle flips bit 0) with one 16-byte store
+    {
+        static_assert(FT * kTile % 1024 == 0 && kTile % 2 == 0, "tile stores");
+        const auto dr = buf_rsrc(d2, (uint32_t)(FT * kTile * sizeof(float2)));
+#pragma unroll
+        for (int k = 0; k < FT * kTile / 1024; ++k) {
+            const int i = 2 * ((int)threadIdx.x + 512 * k);
+            const int f = i / kTile, cc = i % kTile;
+            const int sw = (f >> 2) & (kTile - 1);
+            const float4 p = *(const float4*)(stage + f * kTile + ((cc ^ sw) & ~1));
+            buf_st_f4((sw & 1) ? make_float4(p.z, p.w, p.x, p.y) : p, dr, (uint32_t)(i * 8), 0u);
+        }
     }
 }
 
