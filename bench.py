@@ -346,15 +346,7 @@ def bench_batched(args):
     chunk_bins = max(1, min(args.chunk_bins,
                             int((args.budget_gb * 1e9 - pass_bins * scratch) // fixed)))
     # smallest events first: the median event completes after a small share of the work
-    chunks, cur, nb = [], [], 0
-    for e in np.argsort(bins, kind="stable"):
-        e = int(e)
-        if cur and nb + bins[e] > chunk_bins:
-            chunks.append(cur)
-            cur, nb = [], 0
-        cur.append(e)
-        nb += int(bins[e])
-    chunks.append(cur)
+    chunks = autotune.plan_chunks(bins, chunk_bins)
     ccap = [(sum(caps[e][0] for e in c), sum(caps[e][1] for e in c), sum(caps[e][2] for e in c),
              int(sizes[c].sum())) for c in chunks]
     maxc = max(c[1] for c in ccap)

@@ -112,3 +112,34 @@ def tune(grid, phys, kpix, kticks, resp, seg, mpcp: bool = True,
     if not ok:
         raise RuntimeError("no autotune candidate ran")
     return TuneResult(min(ok, key=lambda t: t.ms), trials)
+
+
+def plan_chunks(bins: Sequence[int], target: int) -> List[List[int]]:
+    """Groups a batch's events into chunks (one HIP graph each) for latency.
+
+    Events are taken smallest first (by active bins; ties keep their order) and a chunk
+    closes before the event that would take it past `target` (event, bin) pairs; an
+    event with more bins than that is a chunk of its own. An event completes when its
+    chunk does, so small chunks of small events let latency follow event size, while
+    the chunk target keeps each convolution launch large enough to fill the GPU
+    (Sec. III-B batches and chunks events to bound memory; the order is this
+    library's). Returns the event indices of each chunk, in the order to run them; the
+    pipeline's capacity is the largest chunk's pair count."""
+    if target < 1:
+        raise ValueError("chunk target must be at least one (event, bin) pair")
+    order = sorted(range(len(bins)), key=lambda e: int(bins[e]))
+    chunks: List[List[int]] = []
+    cur: List[int] = []
+    n = 0
+    for e in order:
+        b = int(bins[e])
+        if b < 0:
+            raise ValueError("negative bin count")
+        if cur and n + b > target:
+            chunks.append(cur)
+            cur, n = [], 0
+        cur.append(e)
+        n += b
+    if cur:
+        chunks.append(cur)
+    return chunks
